@@ -1,0 +1,238 @@
+#!/usr/bin/env python3
+"""Throughput of the pair-distance histogram on one MI355X.
+
+One step is one full pass of the hot path over one frame already resident in
+HBM: stage the binary64 coordinates (convert / wrap / pad), zero the output,
+run the pair kernel (distances, minimum image, binning into LDS
+sub-histograms, flush to uint64), and derive the out-of-range counts.
+
+Default workload: N = 100,000 uniform points in a periodic 40^3 cube, species
+60,000 / 40,000 (histograms AA, BB, AB), r_max = 20, 10,000 bins,
+4,999,950,000 pairs per step. The headline value is binary32; the binary64
+rate is reported beside it.
+
+Prints ONE JSON line. Usage: python bench.py [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402
+
+# algorithmic FLOPs per pair of the canonical op sequence (add, sub, mul,
+# sqrt, rint, min: 1; fma: 2)
+FLOPS_PER_PAIR = {0: 10, 1: 22, 2: 34, 3: 268}
+PEAK_TFLOPS = {0: 157.3, 1: 78.6}        # MI355X vector FP32 / FP64
+KERNEL_NAME = "pairs_kernel"
+
+
+def workload(name: str):
+    if name == "ortho100k":
+        return workloads.ortho(), "ortho100k: N=100,000 uniform, species 60,000/40,000, " \
+                                  "periodic cube L=40, r_max=20, 10,000 bins"
+    if name == "tiny":
+        return workloads.tiny(), "tiny: N=5,000 uniform in [0,10)^3, 1 species, no box, " \
+                                 "r_max=10*sqrt(3), 1,000 bins"
+    if name == "triclinic1M":
+        return workloads.triclinic(), "triclinic1M: N=1,000,000 clustered, species " \
+                                      "50/30/20 %, cell a=(50,0,0) b=(15,48,0) c=(10,12,45), " \
+                                      "r_max=22, 20,000 bins"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def box_kind(frame) -> int:
+    if frame.box_type != 2:
+        return frame.box_type
+    return 3 if 2 * frame.r_max >= workloads.min_width(frame.box) * (1 - 1e-9) else 2
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("dh_kernels.hip", "dh_internal.h", "dh_api.hip"):
+        with open(os.path.join(ROOT, "paper_1808_01478_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(workload_name: str, precision: int, launches_bytes_alg: float):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel sources; otherwise None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+        rec = t.get(f"{workload_name}/{'fp64' if precision else 'fp32'}")
+        if not rec or rec.get("source_hash") != kernel_source_hash():
+            return None
+        return float(rec["hbm_bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def time_path(ctx, frame, precision, steps, warmup):
+    import torch
+    dev = torch.device("cuda")
+    x = torch.from_numpy(frame.coords).to(dev)
+    out = torch.empty((frame.n_hist, frame.n_bins), dtype=torch.int64, device=dev)
+    oor = torch.empty((frame.n_hist,), dtype=torch.int64, device=dev)
+
+    def step():
+        ctx.histo_async(x, frame.offsets, frame.box_type, frame.box, frame.r_max, frame.n_bins,
+                        precision, out, oor)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    start = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    end = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        start[k].record()
+        step()
+        end[k].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern_ms, launches = ctx.profile_read()
+    ctx.profile(False)
+    step_ms = sorted(s.elapsed_time(e) for s, e in zip(start, end))
+    counts = out.cpu().numpy().view(np.uint64)
+    oor_h = oor.cpu().numpy().view(np.uint64)
+    assert list(counts.sum(axis=1).astype(np.int64) + oor_h.astype(np.int64)) == \
+        frame.hist_pairs(), "pair-count identity failed"
+    return {
+        "wall_s": t1 - t0,
+        "kernel_ms_avg": kern_ms / max(1, launches),
+        "launches": launches,
+        "step_ms_p50": float(np.percentile(step_ms, 50)),
+        "step_ms_p99": float(np.percentile(step_ms, 99)),
+    }
+
+
+def cpu_baseline(frame, target_s: float = 12.0):
+    """The oracle (plain FP64 double loop, OpenMP) on the first M points of
+    every species of the same frame, M sized for about target_s seconds."""
+    import oracle
+    oracle.build(force=False)
+    frac = np.array(frame.species_sizes(), np.float64) / frame.n
+
+    def sample(m_total):
+        return frame.subset([max(1, int(m_total * f)) for f in frac])
+
+    cal = sample(6000)
+    t0 = time.perf_counter()
+    oracle.frame_histogram(cal)
+    dt = max(time.perf_counter() - t0, 1e-3)
+    rate = cal.total_pairs() / dt
+    m = int(np.sqrt(2.0 * rate * target_s))
+    m = max(6000, min(m, frame.n))
+    sub = sample(m)
+    t0 = time.perf_counter()
+    oracle.frame_histogram(sub)
+    dt = time.perf_counter() - t0
+    return {
+        "value": sub.total_pairs() / dt,
+        "unit": "pairs/s",
+        "cores": oracle.max_threads(),
+        "kind": "oracle",
+        "sample": f"first {sub.n} points of the frame (species kept in proportion), "
+                  f"{sub.total_pairs()} pairs in {dt:.1f} s, binary64",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="ortho100k")
+    ap.add_argument("--fp64-steps", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the histogram of a frame runs on a single "
+              "MI355X; multi-GPU runs are not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1808_01478_amd as dh
+
+    frame, desc = workload(args.workload)
+    kind = box_kind(frame)
+    pairs = frame.total_pairs()
+    ctx = dh.Context(0)
+    r32 = time_path(ctx, frame, dh.FP32, args.steps, args.warmup)
+    fp64_steps = args.fp64_steps if args.fp64_steps is not None else max(1, args.steps // 2)
+    r64 = time_path(ctx, frame, dh.FP64, fp64_steps, 1)
+
+    value = pairs * args.steps / r32["wall_s"]
+    flops = pairs * FLOPS_PER_PAIR[kind]
+    ach32 = flops / (r32["kernel_ms_avg"] * 1e-3) / 1e12
+    ach64 = flops / (r64["kernel_ms_avg"] * 1e-3) / 1e12
+    traffic = traffic_for(args.workload, 0, None)
+    line = {
+        "metric": "pair-distances binned/sec (1 MI355X, FP32 vs FP64) + p50/p99 job latency",
+        "value": value,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["wall_s"] * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": desc,
+            "n": frame.n,
+            "species": frame.species_sizes(),
+            "n_bins": frame.n_bins,
+            "r_max": frame.r_max,
+            "pairs_per_step": pairs,
+            "flops_per_pair": FLOPS_PER_PAIR[kind],
+        },
+        "latency_ms": {"p50": r32["step_ms_p50"], "p99": r32["step_ms_p99"]},
+        "fp64": {
+            "value": pairs * fp64_steps / r64["wall_s"],
+            "unit": "pairs/s",
+            "steps": fp64_steps,
+            "ms_per_step": r64["wall_s"] * 1e3 / fp64_steps,
+            "kernel_ms_avg": r64["kernel_ms_avg"],
+            "roofline_frac": ach64 / PEAK_TFLOPS[1],
+            "latency_ms": {"p50": r64["step_ms_p50"], "p99": r64["step_ms_p99"]},
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": KERNEL_NAME,
+            "achieved": ach32,
+            "peak": PEAK_TFLOPS[0],
+            "unit": "TFLOP/s",
+            "frac": ach32 / PEAK_TFLOPS[0],
+            "traffic": traffic,
+            "kernel_ms_avg": r32["kernel_ms_avg"],
+        },
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(frame)
+    ctx.close()
+    del torch
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,194 @@
+/*
+ * disthist.h -- C ABI of libdisthist, particle-pair distance histograms on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operation (Reuter & Koefinger, "CADISHI: Fast parallel calculation of
+ * particle-pair distance histograms on CPUs and GPUs", arXiv:1808.01478):
+ *
+ *   For a frame of particles grouped into species, and for every unordered
+ *   species pair (s, t), count the pairs whose distance falls into each of
+ *   n_bins half-open bins [k*dr, (k+1)*dr), dr = r_max / n_bins
+ *   (Sec. 2.1, Eq. 4). For s != t all N_s*N_t pairs are counted, for s == t
+ *   the N_s(N_s-1)/2 pairs with j > i (Sec. 2.2, Algorithm 1 and the
+ *   single-species variant). The distance is the Euclidean length of the
+ *   difference vector x_j - x_i after the minimum image convention for
+ *   periodic cells (Sec. 2.3, Eq. 5; for triclinic cells beyond half the
+ *   smallest cell width the 26 neighbouring images are searched as well).
+ *   The bin index is (int)(n_bins * r / r_max) (Algorithm 1), evaluated as
+ *   t = r * s with s = n_bins / r_max; pairs with t >= n_bins are out of
+ *   range and are not counted in any bin.
+ *
+ * Conventions shared by every entry point
+ *   coords        [N][3] binary64 Cartesian coordinates, C-contiguous,
+ *                 species-contiguous: species s is rows
+ *                 [offsets[s], offsets[s+1]).
+ *   offsets       host int64 [n_species+1], offsets[0] = 0, non-decreasing,
+ *                 N = offsets[n_species] <= 2^31 - 1.
+ *   n_species     1..64.
+ *   box_type      DH_BOX_NONE, DH_BOX_ORTHO or DH_BOX_TRICLINIC.
+ *   box           host binary64 [3][3], rows are the cell vectors a, b, c.
+ *                 Ignored (may be NULL) for DH_BOX_NONE. Orthorhombic: a
+ *                 positive diagonal and zero off-diagonal entries.
+ *                 Triclinic: lower triangular (a_y = a_z = b_z = 0) with a
+ *                 positive diagonal, reduced so that |b_x| <= a_x/2,
+ *                 |c_x| <= a_x/2 and |c_y| <= b_y/2.
+ *   r_max         finite, > 0.
+ *   n_bins        1..2^24.
+ *   precision     DH_FP64: the canonical binary64 evaluation below; counts
+ *                 are exactly those of that op sequence.
+ *                 DH_FP32: a binary32 evaluation; a pair may change bin
+ *                 only if its binary64 distance lies within a few binary32
+ *                 ulps of the bin edge.
+ *   histograms    uint64 [H][n_bins], H = n_species*(n_species+1)/2, in the
+ *                 order (0,0),(1,1),...,(k-1,k-1), then (s,t) for s < t in
+ *                 lexicographic order. Always overwritten.
+ *
+ * Canonical binary64 arithmetic (IEEE-754 round to nearest even, nothing
+ * fused except the fma() written, correctly rounded sqrt):
+ *   d = x_j - x_i
+ *   orthorhombic: n_c = rint(d_c * (1/L_c)); d_c = fma(-L_c, n_c, d_c)
+ *   triclinic:    sc = dz*h33; sb = fma(dz, h23, dy*h22);
+ *                 sa = fma(dz, h13, fma(dy, h12, dx*h11)); n = rint(s);
+ *                 dz = fma(-cz, nc, dz); dy = fma(-cy, nc, fma(-by, nb, dy));
+ *                 dx = fma(-cx, nc, fma(-bx, nb, fma(-ax, na, dx)))
+ *                 with h11 = 1/ax, h22 = 1/by, h33 = 1/cz, h12 = -bx/(ax*by),
+ *                 h23 = -cy/(by*cz), h13 = (bx*cy - by*cx)/(ax*by*cz)
+ *   q = fma(dz, dz, fma(dy, dy, dx*dx)); when 2*r_max >= w_min*(1 - 1e-9)
+ *   in a triclinic cell (w_min: smallest face-to-face width), q is the
+ *   minimum of that expression over d + S for the 27 shifts
+ *   S = i*a + j*b + k*c, i, j, k in {-1, 0, 1};
+ *   t = sqrt(q) * (n_bins / r_max); bin floor(t) if t < n_bins.
+ *
+ * Errors: every entry point returns DH_OK (0) or a negative DH_E* code.
+ * Argument errors (DH_EINVAL) are detected before anything is written or
+ * launched. dh_strerror() gives a static description of a code, and
+ * dh_ctx_last_error() the message of the last failure on a context.
+ *
+ * Threading: a context may be used by one host thread at a time, and the
+ * calls on one context are ordered on the streams they are issued on; give
+ * each concurrent stream its own context.
+ */
+#ifndef DISTHIST_H
+#define DISTHIST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DH_OK 0
+#define DH_EINVAL (-1)      /* invalid argument; nothing written */
+#define DH_ENOMEM (-2)      /* device or pinned host allocation failed */
+#define DH_EDEVICE (-3)     /* a HIP call failed; see dh_ctx_last_error */
+#define DH_EBUDGET (-4)     /* the job does not fit the context's memory budget */
+#define DH_EUNSUPPORTED (-5)
+
+#define DH_BOX_NONE 0
+#define DH_BOX_ORTHO 1
+#define DH_BOX_TRICLINIC 2
+
+#define DH_FP32 0
+#define DH_FP64 1
+
+typedef struct dh_ctx dh_ctx;
+
+/* A hipStream_t. NULL is the null stream of the context's device. */
+typedef void *dh_stream;
+
+/* Library version as "major.minor.patch". */
+const char *dh_version(void);
+
+/* Static text for a status code. */
+const char *dh_strerror(int code);
+
+/*
+ * Validates the arguments of a histogram call on the host without touching
+ * any device: the rules listed above, plus finiteness of the coordinates when
+ * coords is a host pointer (pass coords = NULL to skip that check).
+ * Returns DH_OK or DH_EINVAL.
+ */
+int dh_check_args(const double *coords, const int64_t *offsets, int32_t n_species,
+                  int32_t box_type, const double *box, double r_max, int32_t n_bins,
+                  int32_t precision);
+
+/*
+ * Synchronous histogram of one frame from host memory (Sec. 2.2,
+ * Algorithm 1; Sec. 3.2 on staging a whole frame in one transfer).
+ *   coords   host [N][3] binary64.
+ *   out      host uint64 [H][n_bins], overwritten.
+ * Runs on the current HIP device through a library-owned context whose
+ * device buffers are allocated at the first call and reused (Sec. 3.2).
+ * The call returns when the result is in out. Thread-safe (calls on one
+ * device are serialised).
+ */
+int dh_histo(const double *coords, const int64_t *offsets, int32_t n_species,
+             int32_t box_type, const double *box, double r_max, int32_t n_bins,
+             int32_t precision, uint64_t *out);
+
+/*
+ * Creates a context on HIP device `device`. The context owns device scratch
+ * (staged coordinates, work lists, counters) that grows on demand and is
+ * reused; it never frees caller memory.
+ */
+int dh_ctx_create(int32_t device, dh_ctx **ctx);
+
+/* Releases a context and its scratch (synchronises its device first). */
+void dh_ctx_destroy(dh_ctx *ctx);
+
+/* The message of the last failed call on ctx ("" if none). With ctx = NULL,
+ * the message of the last failure on the calling thread (for failures that
+ * have no context, such as dh_ctx_create or dh_histo). */
+const char *dh_ctx_last_error(const dh_ctx *ctx);
+
+/*
+ * Asynchronous histogram of one frame already resident in device memory.
+ *   d_coords         device [N][3] binary64; read by kernels on `stream`
+ *                    after the call returns, so it must stay valid until
+ *                    the stream reaches this work.
+ *   offsets, box     host memory, read during the call only.
+ *   d_out            device uint64 [H][n_bins], overwritten on `stream`.
+ *   d_out_of_range   device uint64 [H] or NULL: pairs of each histogram
+ *                    with t >= n_bins.
+ * The work is enqueued on `stream` and the call returns without waiting.
+ * Device coordinates are not checked for finiteness; non-finite input
+ * yields meaningless counts but never out-of-bounds accesses.
+ */
+int dh_histo_async(dh_ctx *ctx, dh_stream stream, const double *d_coords,
+                   const int64_t *offsets, int32_t n_species, int32_t box_type,
+                   const double *box, double r_max, int32_t n_bins, int32_t precision,
+                   uint64_t *d_out, uint64_t *d_out_of_range);
+
+/*
+ * Scaled distances t = r * n_bins / r_max of explicit particle pairs,
+ * evaluated with exactly the device arithmetic that the histogram kernels
+ * use for the given precision and box (Algorithm 1 without the increment).
+ * For checking sampled pairs of frames too large for an exhaustive CPU
+ * comparison.
+ *   d_coords   device [n][3] binary64 (one species; n <= 2^31 - 1).
+ *   d_pi, d_pj device int32 [n_pairs] particle indices in [0, n).
+ *   d_t        device binary64 [n_pairs] output (binary32 results widened).
+ * Asynchronous on `stream`; indices are not range-checked on the device
+ * beyond clamping into [0, n).
+ */
+int dh_pair_t_async(dh_ctx *ctx, dh_stream stream, const double *d_coords, int64_t n,
+                    int32_t box_type, const double *box, double r_max, int32_t n_bins,
+                    int32_t precision, const int32_t *d_pi, const int32_t *d_pj,
+                    int64_t n_pairs, double *d_t);
+
+/*
+ * Kernel timing. When enabled, every histogram launch on ctx records a pair
+ * of HIP events on its stream around the pair kernel (the dominant kernel of
+ * the path). dh_ctx_profile_read() waits for the recorded launches, returns
+ * the summed kernel time in milliseconds and the number of launches, and
+ * resets both. Enabling or disabling also resets them.
+ */
+int dh_ctx_profile(dh_ctx *ctx, int32_t enable);
+int dh_ctx_profile_read(dh_ctx *ctx, double *kernel_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DISTHIST_H */

@@ -1,0 +1,20 @@
+"""MI355X-native particle-pair distance histograms (libdisthist).
+
+The histogram work runs in the HIP kernels of ``libdisthist.so``; this
+package is its ctypes binding. Build the library with
+``python -m paper_1808_01478_amd.build``. The binding is loaded on first use
+of any name below and raises ImportError if the library is missing (there is
+no CPU fallback).
+"""
+_EXPORTS = (
+    "BOX_NONE", "BOX_ORTHO", "BOX_TRICLINIC", "FP32", "FP64", "Context", "DisthistError",
+    "LIB_PATH", "check_args", "exported_symbols", "histo", "n_hist", "version",
+)
+__all__ = list(_EXPORTS)
+
+
+def __getattr__(name):
+    if name in _EXPORTS:
+        from . import disthist
+        return getattr(disthist, name)
+    raise AttributeError(name)

@@ -1,0 +1,578 @@
+// Host side of libdisthist: argument validation, frame constants, the work
+// planner, device contexts and the C entry points declared in disthist.h.
+#include "disthist.h"
+#include "dh_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+using namespace dh;
+
+struct dh_ctx {
+  int device = 0;
+  int n_cu = 0;
+  size_t lds_per_block = 0;
+  hipStream_t own_stream = nullptr;
+  void *d_staged = nullptr;
+  size_t staged_cap = 0;
+  void *d_blob = nullptr;
+  size_t blob_cap = 0;
+  void *h_blob = nullptr;
+  size_t hblob_cap = 0;
+  hipEvent_t blob_evt = nullptr;
+  bool blob_pending = false;
+  double *d_in = nullptr;
+  size_t in_cap = 0;
+  uint64_t *d_out = nullptr;
+  size_t out_cap = 0;
+  std::string last_error;
+  std::mutex mu;
+  // kernel timing: event pairs recorded around pair-kernel launches
+  bool profile = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
+  size_t prof_used = 0;
+};
+
+namespace {
+
+constexpr int32_t kMaxSpecies = 64;
+constexpr int32_t kMaxBins = 1 << 24;
+constexpr int64_t kMaxN = 2147483647LL;
+
+// message of the last failure that had no context to hold it
+thread_local std::string t_last_error;
+
+int fail(dh_ctx *ctx, int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  t_last_error = buf;
+  if (ctx) ctx->last_error = buf;
+  return code;
+}
+
+#define DH_HIP(ctx, call)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail((ctx), DH_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));   \
+  } while (0)
+
+bool box_ok(int32_t box_type, const double *box) {
+  if (box_type == DH_BOX_NONE) return true;
+  if (box_type != DH_BOX_ORTHO && box_type != DH_BOX_TRICLINIC) return false;
+  if (!box) return false;
+  for (int k = 0; k < 9; ++k)
+    if (!std::isfinite(box[k])) return false;
+  const double ax = box[0], ay = box[1], az = box[2];
+  const double bx = box[3], by = box[4], bz = box[5];
+  const double cx = box[6], cy = box[7], cz = box[8];
+  if (!(ax > 0 && by > 0 && cz > 0)) return false;
+  if (ay != 0 || az != 0 || bz != 0) return false;
+  if (box_type == DH_BOX_ORTHO) return bx == 0 && cx == 0 && cy == 0;
+  // reduced triclinic cell
+  return std::fabs(bx) <= 0.5 * ax && std::fabs(cx) <= 0.5 * ax && std::fabs(cy) <= 0.5 * by;
+}
+
+int check(const double *coords, const int64_t *offsets, int32_t n_species, int32_t box_type,
+          const double *box, double r_max, int32_t n_bins, int32_t precision) {
+  if (!offsets || n_species < 1 || n_species > kMaxSpecies) return DH_EINVAL;
+  if (offsets[0] != 0) return DH_EINVAL;
+  for (int s = 0; s < n_species; ++s)
+    if (offsets[s + 1] < offsets[s]) return DH_EINVAL;
+  const int64_t n = offsets[n_species];
+  if (n > kMaxN) return DH_EINVAL;
+  if (!(r_max > 0) || !std::isfinite(r_max)) return DH_EINVAL;
+  if (n_bins < 1 || n_bins > kMaxBins) return DH_EINVAL;
+  if (precision != DH_FP32 && precision != DH_FP64) return DH_EINVAL;
+  if (!box_ok(box_type, box)) return DH_EINVAL;
+  if (coords)
+    for (int64_t i = 0; i < 3 * n; ++i)
+      if (!std::isfinite(coords[i])) return DH_EINVAL;
+  return DH_OK;
+}
+
+// smallest face-to-face width of a lower-triangular cell
+double min_width_tri(double ax, double bx, double by, double cx, double cy, double cz) {
+  const double vol = ax * by * cz;
+  const double wc = cz;
+  const double wb = vol / (ax * std::sqrt(cy * cy + cz * cz));
+  const double bc0 = by * cz, bc1 = -bx * cz, bc2 = bx * cy - by * cx;
+  const double wa = vol / std::sqrt(bc0 * bc0 + bc1 * bc1 + bc2 * bc2);
+  return std::min(wa, std::min(wb, wc));
+}
+
+// Canonical constants of a frame (binary64), plus their binary32 images.
+int frame_consts(int32_t box_type, const double *box, double r_max, int32_t n_bins,
+                 FrameParams &fp) {
+  std::memset(&fp, 0, sizeof fp);
+  fp.n_bins = n_bins;
+  fp.s = static_cast<double>(n_bins) / r_max;
+  int kind = kBoxNone;
+  if (box_type != DH_BOX_NONE) {
+    fp.ax = box[0]; fp.bx = box[3]; fp.by = box[4];
+    fp.cx = box[6]; fp.cy = box[7]; fp.cz = box[8];
+    fp.L[0] = fp.ax; fp.L[1] = fp.by; fp.L[2] = fp.cz;
+    for (int c = 0; c < 3; ++c) fp.iL[c] = 1.0 / fp.L[c];
+    fp.h11 = 1.0 / fp.ax;
+    fp.h22 = 1.0 / fp.by;
+    fp.h33 = 1.0 / fp.cz;
+    fp.h12 = -fp.bx / (fp.ax * fp.by);
+    fp.h23 = -fp.cy / (fp.by * fp.cz);
+    fp.h13 = (fp.bx * fp.cy - fp.by * fp.cx) / (fp.ax * fp.by * fp.cz);
+    int m = 0;
+    for (int i = -1; i <= 1; ++i)
+      for (int j = -1; j <= 1; ++j)
+        for (int k = -1; k <= 1; ++k, ++m) {
+          fp.shift64[m][0] = static_cast<double>(i) * fp.ax + static_cast<double>(j) * fp.bx +
+                             static_cast<double>(k) * fp.cx;
+          fp.shift64[m][1] = static_cast<double>(j) * fp.by + static_cast<double>(k) * fp.cy;
+          fp.shift64[m][2] = static_cast<double>(k) * fp.cz;
+        }
+    if (box_type == DH_BOX_ORTHO) {
+      kind = kBoxOrtho;
+    } else {
+      const double w = min_width_tri(fp.ax, fp.bx, fp.by, fp.cx, fp.cy, fp.cz);
+      kind = (2.0 * r_max >= w * (1.0 - 1e-9)) ? kBoxTricSearch : kBoxTric;
+    }
+    for (int c = 0; c < 3; ++c) {
+      fp.Ls[c] = static_cast<float>(fp.L[c] * fp.s);
+      fp.hs[c] = 0.5f * fp.Ls[c];
+    }
+    const double B[6] = {fp.ax, fp.bx, fp.by, fp.cx, fp.cy, fp.cz};
+    for (int c = 0; c < 6; ++c) fp.Bs[c] = static_cast<float>(B[c] * fp.s);
+    for (int q = 0; q < kShifts; ++q)
+      for (int c = 0; c < 3; ++c) fp.shift32[q][c] = static_cast<float>(fp.shift64[q][c] * fp.s);
+  }
+  fp.box = kind;
+  return kind;
+}
+
+struct Launch {
+  KernelConfig cfg;
+  int win = 0, n_sweeps = 1, stride = 0, grid = 0;
+  size_t lds = 0;
+};
+
+size_t coord_bytes(int precision) { return precision == DH_FP64 ? 32 : 16; }
+
+// Launch shape for one frame (heuristic defaults).
+Launch choose_launch(const dh_ctx *ctx, int precision, int kind, int32_t n_bins,
+                     uint64_t total_pairs) {
+  Launch L;
+  KernelConfig &c = L.cfg;
+  c.threads = 256;
+  c.r = precision == DH_FP64 ? 4 : 8;
+  c.copies = 1;
+  c.tj = precision == DH_FP64 ? 128 : 256;
+  c.wg_per_cu = 0;
+  const size_t tile_bytes = 2 * static_cast<size_t>(c.tj) * coord_bytes(precision);
+  const size_t budget = std::min<size_t>(ctx->lds_per_block, 160 * 1024) - tile_bytes - 256;
+  const int64_t win_max = static_cast<int64_t>(budget / 4 / c.copies) - kDump;
+  if (n_bins <= win_max) {
+    L.n_sweeps = 1;
+    L.win = n_bins;
+  } else {
+    L.n_sweeps = static_cast<int>((n_bins + win_max - 1) / win_max);
+    L.win = (n_bins + L.n_sweeps - 1) / L.n_sweeps;
+  }
+  L.stride = L.win + kDump;
+  L.lds = tile_bytes + static_cast<size_t>(c.copies) * L.stride * 4;
+  const int occ = pairs_occupancy(precision, kind, L.n_sweeps > 1, c, L.lds);
+  L.grid = ctx->n_cu * occ;
+  // j-chunk: about 8 items per workgroup over the whole (swept) job
+  const uint64_t bi = static_cast<uint64_t>(c.threads) * c.r;
+  const uint64_t work = total_pairs * static_cast<uint64_t>(L.n_sweeps);
+  uint64_t jc = work / (static_cast<uint64_t>(L.grid) * 8 * bi + 1);
+  jc = (jc + c.tj - 1) / c.tj * c.tj;
+  jc = std::max<uint64_t>(jc, c.tj);
+  jc = std::min<uint64_t>(jc, 64ull * c.tj);
+  c.jchunk = static_cast<int32_t>(jc);
+  return L;
+}
+
+// Work items of one frame, grouped by (histogram, sweep).
+void plan_frame(int32_t frame, const int64_t *off, int32_t k, const Launch &L,
+                std::vector<WorkItem> &items, std::vector<uint64_t> &pairs) {
+  const int64_t bi = static_cast<int64_t>(L.cfg.threads) * L.cfg.r;
+  const int64_t jc = L.cfg.jchunk;
+  auto emit = [&](int32_t h, int64_t i0, int64_t i1, int64_t j0, int64_t j1, int32_t diag) {
+    WorkItem w;
+    w.frame = frame; w.hist = h; w.sweep = 0; w.diag = diag;
+    w.i0 = static_cast<int32_t>(i0); w.i1 = static_cast<int32_t>(i1);
+    w.j0 = static_cast<int32_t>(j0); w.j1 = static_cast<int32_t>(j1);
+    items.push_back(w);
+  };
+  int32_t h = 0;
+  auto plan_hist = [&](int32_t s, int32_t t) {
+    const size_t first = items.size();
+    if (s == t) {
+      const int64_t base = off[s], n = off[s + 1] - off[s];
+      pairs.push_back(static_cast<uint64_t>(n) * static_cast<uint64_t>(n > 0 ? n - 1 : 0) / 2);
+      for (int64_t b0 = base; b0 < base + n; b0 += bi) {
+        const int64_t b1 = std::min(b0 + bi, base + n);
+        if (b1 - b0 >= 2) emit(h, b0, b1, b0, b1, 1);
+        for (int64_t j = b1; j < base + n; j += jc) emit(h, b0, b1, j, std::min(j + jc, base + n), 0);
+      }
+    } else {
+      const int64_t ns = off[s + 1] - off[s], nt = off[t + 1] - off[t];
+      pairs.push_back(static_cast<uint64_t>(ns) * static_cast<uint64_t>(nt));
+      // the larger species fills the lanes, the smaller one is streamed
+      const int32_t si = ns >= nt ? s : t, sj = ns >= nt ? t : s;
+      for (int64_t b0 = off[si]; b0 < off[si + 1]; b0 += bi) {
+        const int64_t b1 = std::min(b0 + bi, off[si + 1]);
+        for (int64_t j = off[sj]; j < off[sj + 1]; j += jc)
+          emit(h, b0, b1, j, std::min(j + jc, off[sj + 1]), 0);
+      }
+    }
+    // replicate for every bin window, keeping items grouped by (h, sweep)
+    const size_t last = items.size();
+    for (int32_t sw = 1; sw < L.n_sweeps; ++sw)
+      for (size_t q = first; q < last; ++q) {
+        WorkItem w = items[q];
+        w.sweep = sw;
+        items.push_back(w);
+      }
+    ++h;
+  };
+  for (int32_t s = 0; s < k; ++s) plan_hist(s, s);
+  for (int32_t s = 0; s < k; ++s)
+    for (int32_t t = s + 1; t < k; ++t) plan_hist(s, t);
+}
+
+int ensure_device(dh_ctx *ctx, void **ptr, size_t *cap, size_t need) {
+  if (need <= *cap) return DH_OK;
+  size_t want = std::max(need, *cap + *cap / 2);
+  if (*ptr) {
+    DH_HIP(ctx, hipDeviceSynchronize());
+    DH_HIP(ctx, hipFree(*ptr));
+    *ptr = nullptr;
+    *cap = 0;
+  }
+  if (hipMalloc(ptr, want) != hipSuccess) {
+    (void)hipGetLastError();
+    *ptr = nullptr;
+    return fail(ctx, DH_ENOMEM, "hipMalloc of %zu bytes failed", want);
+  }
+  *cap = want;
+  return DH_OK;
+}
+
+int ensure_pinned(dh_ctx *ctx, size_t need) {
+  if (need <= ctx->hblob_cap) return DH_OK;
+  if (ctx->blob_pending) {
+    DH_HIP(ctx, hipEventSynchronize(ctx->blob_evt));
+    ctx->blob_pending = false;
+  }
+  if (ctx->h_blob) DH_HIP(ctx, hipHostFree(ctx->h_blob));
+  ctx->h_blob = nullptr;
+  ctx->hblob_cap = 0;
+  size_t want = std::max(need, static_cast<size_t>(1) << 16);
+  if (hipHostMalloc(&ctx->h_blob, want, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->h_blob = nullptr;
+    return fail(ctx, DH_ENOMEM, "hipHostMalloc of %zu bytes failed", want);
+  }
+  ctx->hblob_cap = want;
+  return DH_OK;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Uploads frames | items | pairs | counter through the pinned staging buffer.
+struct BlobLayout {
+  size_t frames = 0, items = 0, pairs = 0, counter = 0, total = 0;
+};
+
+BlobLayout blob_layout(size_t n_frames, size_t n_items, size_t n_pairs) {
+  BlobLayout b;
+  b.frames = 0;
+  b.items = align_up(b.frames + n_frames * sizeof(FrameParams), 256);
+  b.pairs = align_up(b.items + n_items * sizeof(WorkItem), 256);
+  b.counter = align_up(b.pairs + n_pairs * sizeof(uint64_t), 256);
+  b.total = b.counter + 256;
+  return b;
+}
+
+int upload_blob(dh_ctx *ctx, hipStream_t st, const BlobLayout &lay,
+                const std::vector<FrameParams> &frames, const std::vector<WorkItem> &items,
+                const std::vector<uint64_t> &pairs) {
+  int rc = ensure_pinned(ctx, lay.total);
+  if (rc) return rc;
+  rc = ensure_device(ctx, &ctx->d_blob, &ctx->blob_cap, lay.total);
+  if (rc) return rc;
+  if (ctx->blob_pending) {
+    DH_HIP(ctx, hipEventSynchronize(ctx->blob_evt));
+    ctx->blob_pending = false;
+  }
+  char *h = static_cast<char *>(ctx->h_blob);
+  if (!frames.empty()) std::memcpy(h + lay.frames, frames.data(), frames.size() * sizeof(FrameParams));
+  if (!items.empty()) std::memcpy(h + lay.items, items.data(), items.size() * sizeof(WorkItem));
+  if (!pairs.empty()) std::memcpy(h + lay.pairs, pairs.data(), pairs.size() * sizeof(uint64_t));
+  std::memset(h + lay.counter, 0, 256);
+  DH_HIP(ctx, hipMemcpyAsync(ctx->d_blob, h, lay.total, hipMemcpyHostToDevice, st));
+  DH_HIP(ctx, hipEventRecord(ctx->blob_evt, st));
+  ctx->blob_pending = true;
+  return DH_OK;
+}
+
+int ctx_init(dh_ctx *ctx, int32_t device) {
+  int n = 0;
+  DH_HIP(ctx, hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return fail(ctx, DH_EINVAL, "device %d of %d", device, n);
+  ctx->device = device;
+  DH_HIP(ctx, hipSetDevice(device));
+  hipDeviceProp_t prop;
+  DH_HIP(ctx, hipGetDeviceProperties(&prop, device));
+  ctx->n_cu = prop.multiProcessorCount;
+  ctx->lds_per_block = prop.sharedMemPerBlock;
+  DH_HIP(ctx, hipEventCreateWithFlags(&ctx->blob_evt, hipEventDisableTiming));
+  DH_HIP(ctx, hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking));
+  return DH_OK;
+}
+
+std::mutex g_default_mu;
+std::map<int, dh_ctx *> g_default;
+
+}  // namespace
+
+extern "C" {
+
+const char *dh_version(void) { return "0.1.0"; }
+
+const char *dh_strerror(int code) {
+  switch (code) {
+    case DH_OK: return "success";
+    case DH_EINVAL: return "invalid argument";
+    case DH_ENOMEM: return "out of memory";
+    case DH_EDEVICE: return "device error";
+    case DH_EBUDGET: return "memory budget exceeded";
+    case DH_EUNSUPPORTED: return "unsupported";
+    default: return "unknown error";
+  }
+}
+
+int dh_check_args(const double *coords, const int64_t *offsets, int32_t n_species,
+                  int32_t box_type, const double *box, double r_max, int32_t n_bins,
+                  int32_t precision) {
+  return check(coords, offsets, n_species, box_type, box, r_max, n_bins, precision);
+}
+
+int dh_ctx_create(int32_t device, dh_ctx **out) {
+  if (!out) return DH_EINVAL;
+  *out = nullptr;
+  dh_ctx *ctx = new (std::nothrow) dh_ctx;
+  if (!ctx) return DH_ENOMEM;
+  int rc = ctx_init(ctx, device);
+  if (rc) {
+    dh_ctx_destroy(ctx);
+    return rc;
+  }
+  *out = ctx;
+  return DH_OK;
+}
+
+void dh_ctx_destroy(dh_ctx *ctx) {
+  if (!ctx) return;
+  if (hipSetDevice(ctx->device) == hipSuccess) {
+    (void)hipDeviceSynchronize();
+    if (ctx->d_staged) (void)hipFree(ctx->d_staged);
+    if (ctx->d_blob) (void)hipFree(ctx->d_blob);
+    if (ctx->d_in) (void)hipFree(ctx->d_in);
+    if (ctx->d_out) (void)hipFree(ctx->d_out);
+    if (ctx->h_blob) (void)hipHostFree(ctx->h_blob);
+    if (ctx->blob_evt) (void)hipEventDestroy(ctx->blob_evt);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
+    for (auto &ev : ctx->prof_events) {
+      (void)hipEventDestroy(ev.first);
+      (void)hipEventDestroy(ev.second);
+    }
+  }
+  (void)hipGetLastError();
+  delete ctx;
+}
+
+const char *dh_ctx_last_error(const dh_ctx *ctx) {
+  return ctx ? ctx->last_error.c_str() : t_last_error.c_str();
+}
+
+int dh_histo_async(dh_ctx *ctx, dh_stream stream, const double *d_coords, const int64_t *offsets,
+                   int32_t n_species, int32_t box_type, const double *box, double r_max,
+                   int32_t n_bins, int32_t precision, uint64_t *d_out, uint64_t *d_out_of_range) {
+  if (!ctx) return DH_EINVAL;
+  int rc = check(nullptr, offsets, n_species, box_type, box, r_max, n_bins, precision);
+  if (rc) return fail(ctx, rc, "invalid arguments");
+  const int64_t n = offsets[n_species];
+  if (!d_out || (n > 0 && !d_coords)) return fail(ctx, DH_EINVAL, "null device pointer");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  DH_HIP(ctx, hipSetDevice(ctx->device));
+
+  FrameParams fp;
+  const int kind = frame_consts(box_type, box, r_max, n_bins, fp);
+  const int32_t n_hist = n_species * (n_species + 1) / 2;
+  uint64_t total = 0;
+  for (int s = 0; s < n_species; ++s) {
+    const uint64_t a = static_cast<uint64_t>(offsets[s + 1] - offsets[s]);
+    total += a * (a > 0 ? a - 1 : 0) / 2;
+    for (int t = s + 1; t < n_species; ++t)
+      total += a * static_cast<uint64_t>(offsets[t + 1] - offsets[t]);
+  }
+  Launch L = choose_launch(ctx, precision, kind, n_bins, total);
+  fp.win = L.win;
+  fp.n_sweeps = L.n_sweeps;
+  std::vector<WorkItem> items;
+  std::vector<uint64_t> pairs;
+  plan_frame(0, offsets, n_species, L, items, pairs);
+
+  rc = ensure_device(ctx, &ctx->d_staged, &ctx->staged_cap,
+                     std::max<size_t>(1, static_cast<size_t>(n)) * coord_bytes(precision));
+  if (rc) return rc;
+  fp.coords = ctx->d_staged;
+  fp.out = d_out;
+  const BlobLayout lay = blob_layout(1, items.size(), pairs.size());
+  std::vector<FrameParams> frames(1, fp);
+  rc = upload_blob(ctx, st, lay, frames, items, pairs);
+  if (rc) return rc;
+  char *db = static_cast<char *>(ctx->d_blob);
+  DH_HIP(ctx, launch_stage(precision, kind, d_coords, ctx->d_staged, n, fp, st));
+  DH_HIP(ctx, launch_zero(d_out, static_cast<int64_t>(n_hist) * n_bins,
+                          reinterpret_cast<int32_t *>(db + lay.counter), st));
+  if (!items.empty()) {
+    PairKernelArgs a;
+    a.frames = reinterpret_cast<const FrameParams *>(db + lay.frames);
+    a.items = reinterpret_cast<const WorkItem *>(db + lay.items);
+    a.counter = reinterpret_cast<int32_t *>(db + lay.counter);
+    a.n_items = static_cast<int32_t>(items.size());
+    a.copies = L.cfg.copies;
+    a.stride = L.stride;
+    a.tj = L.cfg.tj;
+    const int grid = std::max(1, std::min<int>(L.grid, static_cast<int>(items.size())));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ctx->profile) {
+      if (ctx->prof_used == ctx->prof_events.size()) {
+        hipEvent_t x, y;
+        DH_HIP(ctx, hipEventCreate(&x));
+        DH_HIP(ctx, hipEventCreate(&y));
+        ctx->prof_events.emplace_back(x, y);
+      }
+      e0 = ctx->prof_events[ctx->prof_used].first;
+      e1 = ctx->prof_events[ctx->prof_used].second;
+      ++ctx->prof_used;
+      DH_HIP(ctx, hipEventRecord(e0, st));
+    }
+    DH_HIP(ctx, launch_pairs(precision, kind, L.n_sweeps > 1, L.cfg, a, grid, L.lds, st));
+    if (e1) DH_HIP(ctx, hipEventRecord(e1, st));
+  }
+  if (d_out_of_range)
+    DH_HIP(ctx, launch_oor(d_out, n_hist, n_bins,
+                           reinterpret_cast<const uint64_t *>(db + lay.pairs), d_out_of_range, st));
+  return DH_OK;
+}
+
+int dh_histo(const double *coords, const int64_t *offsets, int32_t n_species, int32_t box_type,
+             const double *box, double r_max, int32_t n_bins, int32_t precision, uint64_t *out) {
+  int rc = check(coords, offsets, n_species, box_type, box, r_max, n_bins, precision);
+  if (rc) return rc;
+  if (!out) return DH_EINVAL;
+  const int64_t n = offsets[n_species];
+  if (n > 0 && !coords) return DH_EINVAL;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return DH_EDEVICE;
+  }
+  dh_ctx *ctx = nullptr;
+  {
+    std::lock_guard<std::mutex> g(g_default_mu);
+    auto it = g_default.find(dev);
+    if (it == g_default.end()) {
+      rc = dh_ctx_create(dev, &ctx);
+      if (rc) return rc;
+      g_default[dev] = ctx;
+    } else {
+      ctx = it->second;
+    }
+  }
+  std::lock_guard<std::mutex> g(ctx->mu);
+  const int32_t n_hist = n_species * (n_species + 1) / 2;
+  const size_t out_bytes = static_cast<size_t>(n_hist) * n_bins * sizeof(uint64_t);
+  rc = ensure_device(ctx, reinterpret_cast<void **>(&ctx->d_in), &ctx->in_cap,
+                     std::max<size_t>(1, static_cast<size_t>(n)) * 3 * sizeof(double));
+  if (rc) return rc;
+  rc = ensure_device(ctx, reinterpret_cast<void **>(&ctx->d_out), &ctx->out_cap, out_bytes);
+  if (rc) return rc;
+  hipStream_t st = ctx->own_stream;
+  if (n > 0)
+    DH_HIP(ctx, hipMemcpyAsync(ctx->d_in, coords, static_cast<size_t>(n) * 3 * sizeof(double),
+                               hipMemcpyHostToDevice, st));
+  rc = dh_histo_async(ctx, st, ctx->d_in, offsets, n_species, box_type, box, r_max, n_bins,
+                      precision, ctx->d_out, nullptr);
+  if (rc) return rc;
+  DH_HIP(ctx, hipMemcpyAsync(out, ctx->d_out, out_bytes, hipMemcpyDeviceToHost, st));
+  DH_HIP(ctx, hipStreamSynchronize(st));
+  return DH_OK;
+}
+
+int dh_pair_t_async(dh_ctx *ctx, dh_stream stream, const double *d_coords, int64_t n,
+                    int32_t box_type, const double *box, double r_max, int32_t n_bins,
+                    int32_t precision, const int32_t *d_pi, const int32_t *d_pj, int64_t n_pairs,
+                    double *d_t) {
+  if (!ctx) return DH_EINVAL;
+  const int64_t off[2] = {0, n};
+  if (n < 1) return fail(ctx, DH_EINVAL, "n < 1");
+  int rc = check(nullptr, off, 1, box_type, box, r_max, n_bins, precision);
+  if (rc) return fail(ctx, rc, "invalid arguments");
+  if (!d_coords || (n_pairs > 0 && (!d_pi || !d_pj || !d_t)) || n_pairs < 0)
+    return fail(ctx, DH_EINVAL, "null device pointer");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  DH_HIP(ctx, hipSetDevice(ctx->device));
+  FrameParams fp;
+  const int kind = frame_consts(box_type, box, r_max, n_bins, fp);
+  fp.win = n_bins;
+  fp.n_sweeps = 1;
+  rc = ensure_device(ctx, &ctx->d_staged, &ctx->staged_cap,
+                     static_cast<size_t>(n) * coord_bytes(precision));
+  if (rc) return rc;
+  fp.coords = ctx->d_staged;
+  const BlobLayout lay = blob_layout(1, 0, 0);
+  rc = upload_blob(ctx, st, lay, std::vector<FrameParams>(1, fp), {}, {});
+  if (rc) return rc;
+  DH_HIP(ctx, launch_stage(precision, kind, d_coords, ctx->d_staged, n, fp, st));
+  DH_HIP(ctx, launch_pair_t(precision, kind, static_cast<const FrameParams *>(ctx->d_blob), d_pi,
+                            d_pj, n_pairs, static_cast<int32_t>(n), d_t, st));
+  return DH_OK;
+}
+
+int dh_ctx_profile(dh_ctx *ctx, int32_t enable) {
+  if (!ctx) return DH_EINVAL;
+  ctx->profile = enable != 0;
+  ctx->prof_used = 0;
+  return DH_OK;
+}
+
+int dh_ctx_profile_read(dh_ctx *ctx, double *kernel_ms, int64_t *launches) {
+  if (!ctx || !kernel_ms || !launches) return DH_EINVAL;
+  DH_HIP(ctx, hipSetDevice(ctx->device));
+  double total = 0.0;
+  for (size_t k = 0; k < ctx->prof_used; ++k) {
+    DH_HIP(ctx, hipEventSynchronize(ctx->prof_events[k].second));
+    float ms = 0.f;
+    DH_HIP(ctx, hipEventElapsedTime(&ms, ctx->prof_events[k].first, ctx->prof_events[k].second));
+    total += ms;
+  }
+  *kernel_ms = total;
+  *launches = static_cast<int64_t>(ctx->prof_used);
+  ctx->prof_used = 0;
+  return DH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,92 @@
+// Internal types shared by the host planner and the gfx950 kernels of
+// libdisthist. Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace dh {
+
+enum BoxKind : int32_t {
+  kBoxNone = 0,
+  kBoxOrtho = 1,
+  kBoxTric = 2,        // Eq. 5 reduction only (r_max below half the smallest width)
+  kBoxTricSearch = 3,  // Eq. 5 reduction, then the 27 neighbouring images
+};
+
+constexpr int kShifts = 27;
+constexpr int kDump = 64;  // per-lane discard slots after the bin window
+
+// Constants of one frame, computed once on the host.
+//
+// binary64 members follow the canonical op sequence: s = n_bins / r_max,
+// iL = 1 / L, and the inverse of the upper-triangular cell matrix
+//   h11 = 1/ax, h22 = 1/by, h33 = 1/cz, h12 = -bx/(ax*by),
+//   h23 = -cy/(by*cz), h13 = (bx*cy - by*cx)/(ax*by*cz),
+// with shifts S = i*a + j*b + k*c for i, j, k in {-1, 0, 1}.
+//
+// binary32 members serve the reduced-precision path, whose coordinates are
+// staged pre-scaled by s (and wrapped into the cell for periodic boxes), so
+// the kernel's distance is already t = r * s.
+struct FrameParams {
+  const void *coords;  // staged float4 / double4 [N] (device)
+  uint64_t *out;       // [H][n_bins] (device)
+  int32_t n_bins;
+  int32_t box;         // BoxKind
+  int32_t win;         // bin window of one sweep (<= n_bins)
+  int32_t n_sweeps;
+  double s;
+  double L[3], iL[3];
+  double ax, bx, by, cx, cy, cz;
+  double h11, h12, h13, h22, h23, h33;
+  double shift64[kShifts][3];
+  float Ls[3], hs[3];  // orthorhombic edge * s and half of it
+  float Bs[6];         // ax bx by cx cy cz, times s
+  float shift32[kShifts][3];
+  float pad_[2];
+};
+
+// One unit of work: particles [i0, i1) of the frame against [j0, j1), for
+// histogram `hist`, bin window `sweep`. diag = 1 when both ranges are the same
+// block of one species, so only j > i counts.
+struct WorkItem {
+  int32_t frame, hist, sweep, diag;
+  int32_t i0, i1, j0, j1;
+};
+
+struct PairKernelArgs {
+  const FrameParams *frames;
+  const WorkItem *items;
+  int32_t *counter;  // dynamic work counter, zero before launch
+  int32_t n_items;
+  int32_t copies;    // LDS sub-histogram copies per workgroup
+  int32_t stride;    // words per copy (>= win + kDump of every frame)
+  int32_t tj;        // j-tile length staged through LDS
+};
+
+// Kernel configuration (chosen per launch by the tuner).
+struct KernelConfig {
+  int32_t threads;   // workgroup size (multiple of 64, <= 256)
+  int32_t r;         // i-particles per lane (4 or 8)
+  int32_t copies;    // sub-histogram copies per workgroup (1, 2, 4)
+  int32_t tj;        // j-tile length (<= threads)
+  int32_t jchunk;    // j-range of one work item (multiple of tj)
+  int32_t wg_per_cu; // 0 = as many as fit
+};
+
+// host-side launchers (dh_kernels.hip)
+hipError_t launch_stage(int precision, int box_kind, const double *in, void *out, int64_t n,
+                        const FrameParams &fp, hipStream_t st);
+hipError_t launch_zero(uint64_t *out, int64_t n_words, int32_t *counter, hipStream_t st);
+hipError_t launch_pairs(int precision, int box_kind, bool sweep, const KernelConfig &cfg,
+                        const PairKernelArgs &args, int grid, size_t lds_bytes, hipStream_t st);
+hipError_t launch_oor(const uint64_t *hist, int32_t n_hist, int32_t n_bins, const uint64_t *pairs,
+                      uint64_t *oor, hipStream_t st);
+hipError_t launch_pair_t(int precision, int box_kind, const FrameParams *d_fp, const int32_t *pi,
+                         const int32_t *pj, int64_t n_pairs, int32_t n, double *t,
+                         hipStream_t st);
+// Occupancy of the pair kernel (workgroups per CU) for a config and LDS size.
+int pairs_occupancy(int precision, int box_kind, bool sweep, const KernelConfig &cfg,
+                    size_t lds_bytes);
+
+}  // namespace dh

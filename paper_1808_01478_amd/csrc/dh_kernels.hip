@@ -1,0 +1,519 @@
+// gfx950 kernels of libdisthist: staging, the LDS-histogram pair kernel,
+// output zeroing, out-of-range counts and the per-pair probe.
+//
+// The pair kernel is persistent: a grid of a few workgroups per CU drains a
+// work list of (frame, histogram, bin window, i-block, j-range) items through
+// an atomic counter. Per item, every lane keeps R i-particles in registers;
+// the workgroup streams the j-range through a double-buffered LDS tile with
+// coalesced loads, and every wave reads each j as a uniform (broadcast) LDS
+// load. Each pair's bin is counted with one ds_add_u32 into a u32 LDS
+// sub-histogram (Sec. 2.4: groups of processing units share a private
+// histogram; Sec. 3.2.3: partial histograms in on-chip memory). Lanes whose
+// pair must not count (out of range, j <= i on a diagonal block, ragged
+// i-block tail) are steered by a clamp to a per-lane discard slot past the
+// bin window instead of a branch, so the atomic is issued without divergence
+// and discarded pairs never collide on one address. When the histogram,
+// window or frame changes, or before any u32 slot could wrap, the workgroup
+// sums its copies and adds them to the uint64 output with global atomics
+// (Sec. 3.1: u32 private histograms flushed into a u64 global one).
+#include "dh_internal.h"
+
+namespace dh {
+namespace {
+
+template <typename T>
+struct V4;
+template <>
+struct V4<float> { using type = float4; };
+template <>
+struct V4<double> { using type = double4; };
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uni(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double uni(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane(static_cast<int>(b & 0xffffffffll));
+  const int hi = __builtin_amdgcn_readfirstlane(static_cast<int>(b >> 32));
+  return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                              static_cast<unsigned int>(lo));
+}
+
+// --------------------------------------------------------------------------
+// Distance arithmetic
+// --------------------------------------------------------------------------
+
+// binary64, canonical op sequence (Algorithm 1 with Eq. 5), no contraction.
+struct Geo64 {
+  double s, L0, L1, L2, iL0, iL1, iL2;
+  double ax, bx, by, cx, cy, cz, h11, h12, h13, h22, h23, h33;
+  const double (*shift)[3];
+};
+
+__device__ __forceinline__ Geo64 load_geo64(const FrameParams *F) {
+  Geo64 g;
+  g.s = uni(F->s);
+  g.L0 = uni(F->L[0]); g.L1 = uni(F->L[1]); g.L2 = uni(F->L[2]);
+  g.iL0 = uni(F->iL[0]); g.iL1 = uni(F->iL[1]); g.iL2 = uni(F->iL[2]);
+  g.ax = uni(F->ax); g.bx = uni(F->bx); g.by = uni(F->by);
+  g.cx = uni(F->cx); g.cy = uni(F->cy); g.cz = uni(F->cz);
+  g.h11 = uni(F->h11); g.h12 = uni(F->h12); g.h13 = uni(F->h13);
+  g.h22 = uni(F->h22); g.h23 = uni(F->h23); g.h33 = uni(F->h33);
+  g.shift = F->shift64;
+  return g;
+}
+
+template <int BOX>
+__device__ __forceinline__ double t64(double xi, double yi, double zi, double xj, double yj,
+                                      double zj, const Geo64 &g) {
+  double dx = xj - xi, dy = yj - yi, dz = zj - zi;
+  if constexpr (BOX == kBoxOrtho) {
+    const double n0 = rint(dx * g.iL0), n1 = rint(dy * g.iL1), n2 = rint(dz * g.iL2);
+    dx = fma(-g.L0, n0, dx);
+    dy = fma(-g.L1, n1, dy);
+    dz = fma(-g.L2, n2, dz);
+  } else if constexpr (BOX == kBoxTric || BOX == kBoxTricSearch) {
+    const double sc = dz * g.h33;
+    const double sb = fma(dz, g.h23, dy * g.h22);
+    const double sa = fma(dz, g.h13, fma(dy, g.h12, dx * g.h11));
+    const double na = rint(sa), nb = rint(sb), nc = rint(sc);
+    dz = fma(-g.cz, nc, dz);
+    dy = fma(-g.cy, nc, fma(-g.by, nb, dy));
+    dx = fma(-g.cx, nc, fma(-g.bx, nb, fma(-g.ax, na, dx)));
+  }
+  double q = fma(dz, dz, fma(dy, dy, dx * dx));
+  if constexpr (BOX == kBoxTricSearch) {
+    for (int m = 0; m < kShifts; ++m) {
+      const double vx = dx + uni(g.shift[m][0]);
+      const double vy = dy + uni(g.shift[m][1]);
+      const double vz = dz + uni(g.shift[m][2]);
+      const double v = fma(vz, vz, fma(vy, vy, vx * vx));
+      q = v < q ? v : q;
+    }
+  }
+  return sqrt(q) * g.s;  // correctly rounded sqrt (default HIP lowering)
+}
+
+// binary32: coordinates are staged pre-scaled by s (so the result is t),
+// wrapped into [0, L*s) for orthorhombic cells and given as wrapped
+// fractional coordinates for triclinic cells.
+struct Geo32 {
+  float hx, hy, hz;                 // half edges (orthorhombic)
+  float ax, bx, by, cx, cy, cz;     // cell matrix times s (triclinic)
+  const float (*shift)[3];
+};
+
+__device__ __forceinline__ Geo32 load_geo32(const FrameParams *F) {
+  Geo32 g;
+  g.hx = uni(F->hs[0]); g.hy = uni(F->hs[1]); g.hz = uni(F->hs[2]);
+  g.ax = uni(F->Bs[0]); g.bx = uni(F->Bs[1]); g.by = uni(F->Bs[2]);
+  g.cx = uni(F->Bs[3]); g.cy = uni(F->Bs[4]); g.cz = uni(F->Bs[5]);
+  g.shift = F->shift32;
+  return g;
+}
+
+template <int BOX>
+__device__ __forceinline__ float t32(float xi, float yi, float zi, float xj, float yj, float zj,
+                                     const Geo32 &g) {
+  float dx = xj - xi, dy = yj - yi, dz = zj - zi;
+  if constexpr (BOX == kBoxOrtho) {
+    // both points lie in [0, L): the nearest image of a component d has
+    // length min(|d|, L - |d|) = h - ||d| - h|, h = L/2
+    dx = g.hx - fabsf(fabsf(dx) - g.hx);
+    dy = g.hy - fabsf(fabsf(dy) - g.hy);
+    dz = g.hz - fabsf(fabsf(dz) - g.hz);
+  } else if constexpr (BOX == kBoxTric || BOX == kBoxTricSearch) {
+    // Eq. 5 in fractional coordinates: f - nint(f), then back through B
+    const float fa = dx - rintf(dx), fb = dy - rintf(dy), fc = dz - rintf(dz);
+    dx = fmaf(g.cx, fc, fmaf(g.bx, fb, g.ax * fa));
+    dy = fmaf(g.cy, fc, g.by * fb);
+    dz = g.cz * fc;
+  }
+  float q = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+  if constexpr (BOX == kBoxTricSearch) {
+    for (int m = 0; m < kShifts; ++m) {
+      const float vx = dx + uni(g.shift[m][0]);
+      const float vy = dy + uni(g.shift[m][1]);
+      const float vz = dz + uni(g.shift[m][2]);
+      q = fminf(q, fmaf(vz, vz, fmaf(vy, vy, vx * vx)));
+    }
+  }
+  return __builtin_amdgcn_sqrtf(q);  // v_sqrt_f32
+}
+
+template <typename T>
+struct Geo;
+template <>
+struct Geo<float> {
+  using type = Geo32;
+  static __device__ __forceinline__ Geo32 load(const FrameParams *F) { return load_geo32(F); }
+};
+template <>
+struct Geo<double> {
+  using type = Geo64;
+  static __device__ __forceinline__ Geo64 load(const FrameParams *F) { return load_geo64(F); }
+};
+
+template <typename T, int BOX>
+__device__ __forceinline__ T pair_t(T xi, T yi, T zi, T xj, T yj, T zj,
+                                    const typename Geo<T>::type &g) {
+  if constexpr (sizeof(T) == 4)
+    return t32<BOX>(xi, yi, zi, xj, yj, zj, g);
+  else
+    return t64<BOX>(xi, yi, zi, xj, yj, zj, g);
+}
+
+// --------------------------------------------------------------------------
+// Staging: binary64 [N][3] -> padded float4 / double4
+// --------------------------------------------------------------------------
+
+__global__ void stage64_kernel(const double *__restrict__ in, double4 *__restrict__ out,
+                               int64_t n) {
+  const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += step)
+    out[i] = make_double4(in[3 * i], in[3 * i + 1], in[3 * i + 2], 0.0);
+}
+
+__device__ __forceinline__ double wrap01(double f) { return f - floor(f); }
+
+template <int BOX>
+__global__ void stage32_kernel(const double *__restrict__ in, float4 *__restrict__ out, int64_t n,
+                               FrameParams p) {
+  const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += step) {
+    const double x = in[3 * i], y = in[3 * i + 1], z = in[3 * i + 2];
+    float4 v;
+    if constexpr (BOX == kBoxNone) {
+      v = make_float4(static_cast<float>(x * p.s), static_cast<float>(y * p.s),
+                      static_cast<float>(z * p.s), 0.f);
+    } else if constexpr (BOX == kBoxOrtho) {
+      const double ux = x - p.L[0] * floor(x * p.iL[0]);
+      const double uy = y - p.L[1] * floor(y * p.iL[1]);
+      const double uz = z - p.L[2] * floor(z * p.iL[2]);
+      v = make_float4(static_cast<float>(ux * p.s), static_cast<float>(uy * p.s),
+                      static_cast<float>(uz * p.s), 0.f);
+    } else {
+      const double fa = fma(z, p.h13, fma(y, p.h12, x * p.h11));
+      const double fb = fma(z, p.h23, y * p.h22);
+      const double fc = z * p.h33;
+      v = make_float4(static_cast<float>(wrap01(fa)), static_cast<float>(wrap01(fb)),
+                      static_cast<float>(wrap01(fc)), 0.f);
+    }
+    out[i] = v;
+  }
+}
+
+// --------------------------------------------------------------------------
+// Pair kernel
+// --------------------------------------------------------------------------
+
+// Adds the LDS copies of bins [0, count) into out[] and clears the window
+// including its discard slots.
+__device__ __forceinline__ void flush_hist(uint32_t *hist, const PairKernelArgs &a,
+                                           const FrameParams *F, int hist_idx, int sweep) {
+  const int n_bins = uni(F->n_bins);
+  const int win = uni(F->win);
+  const int b_lo = sweep * win;
+  const int count = min(win, n_bins - b_lo);
+  uint64_t *out = F->out + static_cast<size_t>(hist_idx) * n_bins + b_lo;
+  const int clear = min(win + kDump, a.stride);
+  for (int b = threadIdx.x; b < clear; b += blockDim.x) {
+    uint64_t v = 0;
+    for (int c = 0; c < a.copies; ++c) {
+      uint32_t *p = hist + c * a.stride + b;
+      v += *p;
+      *p = 0u;
+    }
+    if (b < count && v != 0)
+      atomicAdd(reinterpret_cast<unsigned long long *>(out + b),
+                static_cast<unsigned long long>(v));
+  }
+}
+
+template <typename T, int R, int BOX, bool SWEEP, bool DIAG>
+__device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem &w,
+                                         const FrameParams *F,
+                                         typename V4<T>::type *__restrict__ tile,
+                                         uint32_t *__restrict__ my) {
+  using V = typename V4<T>::type;
+  using G = typename Geo<T>::type;
+  const V *__restrict__ X = static_cast<const V *>(F->coords);
+  const G g = Geo<T>::load(F);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tj = a.tj;
+  const int win = uni(F->win);
+  const int b_lo = w.sweep * win;
+
+  // i-particles: wave w holds [wbase, wbase + 64R), lane l the R values
+  // wbase + r*64 + l
+  const int wbase = w.i0 + wave * 64 * R;
+  const bool wave_active = wbase < w.i1;
+  T xi[R], yi[R], zi[R];
+  const uint32_t hi = static_cast<uint32_t>(win + lane);  // discard slot of this lane
+  uint32_t lo[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = wbase + r * 64 + lane;
+    const bool ok = i < w.i1;
+    const V p = X[ok ? i : w.i0];
+    xi[r] = p.x; yi[r] = p.y; zi[r] = p.z;
+    lo[r] = ok ? 0u : hi;
+  }
+  float lof[R];
+  const float hif = static_cast<float>(hi);
+#pragma unroll
+  for (int r = 0; r < R; ++r) lof[r] = static_cast<float>(lo[r]);
+
+  V pre = {};
+  if (tid < tj && w.j0 + tid < w.j1) pre = X[w.j0 + tid];
+  int buf = 0;
+  for (int jt = w.j0; jt < w.j1; jt += tj, buf ^= 1) {
+    if (tid < tj) tile[buf * tj + tid] = pre;
+    __syncthreads();
+    {
+      const int jn = jt + tj + tid;
+      if (tid < tj && jn < w.j1) pre = X[jn];
+    }
+    const int jcount = min(tj, w.j1 - jt);
+    int js = 0;
+    if constexpr (DIAG) js = max(0, min(jcount, wbase + 1 - jt));
+    if (wave_active) {
+      const V *__restrict__ tb = tile + buf * tj;
+#pragma unroll 2
+      for (int jj = js; jj < jcount; ++jj) {
+        const V pj = tb[jj];
+        const int j = jt + jj;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const T t = pair_t<T, BOX>(xi[r], yi[r], zi[r], pj.x, pj.y, pj.z, g);
+          uint32_t idx;
+          if constexpr (sizeof(T) == 4 && !SWEEP) {
+            float l = lof[r];
+            if constexpr (DIAG) l = (j > wbase + r * 64 + lane) ? l : hif;
+            idx = static_cast<uint32_t>(__builtin_amdgcn_fmed3f(t, l, hif));
+          } else {
+            uint32_t l = lo[r];
+            if constexpr (DIAG) l = (j > wbase + r * 64 + lane) ? l : hi;
+            // floor(t), saturated; t >= 0 always
+            if constexpr (sizeof(T) == 4)
+              idx = static_cast<uint32_t>(fminf(t, 4294967040.0f));
+            else
+              idx = static_cast<uint32_t>(fmin(t, 4294967295.0));
+            if constexpr (SWEEP) idx -= static_cast<uint32_t>(b_lo);
+            idx = max(min(idx, hi), l);
+          }
+          atomicAdd(my + idx, 1u);
+        }
+      }
+    }
+  }
+}
+
+template <typename T, int R, int BOX, bool SWEEP>
+__global__ __launch_bounds__(256) void pairs_kernel(PairKernelArgs a) {
+  using V = typename V4<T>::type;
+  extern __shared__ __align__(32) unsigned char smem[];
+  __shared__ int s_item;
+  V *tile = reinterpret_cast<V *>(smem);
+  uint32_t *hist = reinterpret_cast<uint32_t *>(smem + 2 * a.tj * sizeof(V));
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  uint32_t *my = hist + (wave % a.copies) * a.stride;
+
+  for (int k = tid; k < a.copies * a.stride; k += blockDim.x) hist[k] = 0u;
+
+  int cur_frame = -1, cur_hist = -1, cur_sweep = -1;
+  uint64_t acc = 0;
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) s_item = atomicAdd(a.counter, 1);
+    __syncthreads();
+    const int it = uni(s_item);
+    if (it >= a.n_items) break;
+    WorkItem w;
+    {
+      const WorkItem *p = a.items + it;
+      w.frame = uni(p->frame); w.hist = uni(p->hist); w.sweep = uni(p->sweep);
+      w.diag = uni(p->diag); w.i0 = uni(p->i0); w.i1 = uni(p->i1);
+      w.j0 = uni(p->j0); w.j1 = uni(p->j1);
+    }
+    const uint64_t npairs =
+        static_cast<uint64_t>(w.i1 - w.i0) * static_cast<uint64_t>(w.j1 - w.j0);
+    if (w.frame != cur_frame || w.hist != cur_hist || w.sweep != cur_sweep ||
+        acc + npairs > 0xffffffffull) {
+      if (cur_frame >= 0) {
+        flush_hist(hist, a, a.frames + cur_frame, cur_hist, cur_sweep);
+        __syncthreads();
+      }
+      cur_frame = w.frame; cur_hist = w.hist; cur_sweep = w.sweep;
+      acc = 0;
+    }
+    acc += npairs;
+    const FrameParams *F = a.frames + w.frame;
+    if (w.diag)
+      run_item<T, R, BOX, SWEEP, true>(a, w, F, tile, my);
+    else
+      run_item<T, R, BOX, SWEEP, false>(a, w, F, tile, my);
+  }
+  if (cur_frame >= 0) flush_hist(hist, a, a.frames + cur_frame, cur_hist, cur_sweep);
+}
+
+// --------------------------------------------------------------------------
+// Small kernels
+// --------------------------------------------------------------------------
+
+__global__ void zero_kernel(uint64_t *__restrict__ out, int64_t n, int32_t *counter) {
+  const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  const int64_t i0 = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i0 == 0 && counter) *counter = 0;
+  for (int64_t i = i0; i < n; i += step) out[i] = 0ull;
+}
+
+__global__ void oor_kernel(const uint64_t *__restrict__ hist, int32_t n_bins,
+                           const uint64_t *__restrict__ pairs, uint64_t *__restrict__ oor) {
+  __shared__ unsigned long long part[256];
+  const int h = blockIdx.x;
+  unsigned long long v = 0;
+  for (int b = threadIdx.x; b < n_bins; b += blockDim.x)
+    v += hist[static_cast<size_t>(h) * n_bins + b];
+  part[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) oor[h] = pairs[h] - part[0];
+}
+
+template <typename T, int BOX>
+__global__ void pair_t_kernel(const FrameParams *F, const int32_t *__restrict__ pi,
+                              const int32_t *__restrict__ pj, int64_t n_pairs, int32_t n,
+                              double *__restrict__ out) {
+  using V = typename V4<T>::type;
+  const V *X = static_cast<const V *>(F->coords);
+  const typename Geo<T>::type g = Geo<T>::load(F);
+  const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; k < n_pairs;
+       k += step) {
+    const int i = min(max(pi[k], 0), n - 1), j = min(max(pj[k], 0), n - 1);
+    const V a = X[i], b = X[j];
+    out[k] = static_cast<double>(pair_t<T, BOX>(a.x, a.y, a.z, b.x, b.y, b.z, g));
+  }
+}
+
+using PairFn = void (*)(PairKernelArgs);
+
+template <typename T, int R, bool SW>
+PairFn pick_box(int box) {
+  switch (box) {
+    case kBoxNone: return pairs_kernel<T, R, kBoxNone, SW>;
+    case kBoxOrtho: return pairs_kernel<T, R, kBoxOrtho, SW>;
+    case kBoxTric: return pairs_kernel<T, R, kBoxTric, SW>;
+    default: return pairs_kernel<T, R, kBoxTricSearch, SW>;
+  }
+}
+
+template <typename T>
+PairFn pick_r(int r, int box, bool sweep) {
+  if (r == 8) return sweep ? pick_box<T, 8, true>(box) : pick_box<T, 8, false>(box);
+  return sweep ? pick_box<T, 4, true>(box) : pick_box<T, 4, false>(box);
+}
+
+PairFn pick(int precision, int r, int box, bool sweep) {
+  return precision == 1 ? pick_r<double>(r, box, sweep) : pick_r<float>(r, box, sweep);
+}
+
+int grid_for(int64_t n, int threads) {
+  int64_t g = (n + threads - 1) / threads;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  return static_cast<int>(g);
+}
+
+}  // namespace
+
+hipError_t launch_stage(int precision, int box_kind, const double *in, void *out, int64_t n,
+                        const FrameParams &fp, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int threads = 256;
+  const int grid = grid_for(n, threads);
+  if (precision == 1) {
+    stage64_kernel<<<grid, threads, 0, st>>>(in, static_cast<double4 *>(out), n);
+  } else {
+    float4 *o = static_cast<float4 *>(out);
+    switch (box_kind) {
+      case kBoxNone: stage32_kernel<kBoxNone><<<grid, threads, 0, st>>>(in, o, n, fp); break;
+      case kBoxOrtho: stage32_kernel<kBoxOrtho><<<grid, threads, 0, st>>>(in, o, n, fp); break;
+      default: stage32_kernel<kBoxTric><<<grid, threads, 0, st>>>(in, o, n, fp); break;
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(uint64_t *out, int64_t n_words, int32_t *counter, hipStream_t st) {
+  const int threads = 256;
+  zero_kernel<<<grid_for(n_words > 0 ? n_words : 1, threads), threads, 0, st>>>(out, n_words,
+                                                                               counter);
+  return hipGetLastError();
+}
+
+hipError_t launch_pairs(int precision, int box_kind, bool sweep, const KernelConfig &cfg,
+                        const PairKernelArgs &args, int grid, size_t lds_bytes, hipStream_t st) {
+  PairFn fn = pick(precision, cfg.r, box_kind, sweep);
+  hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
+                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes));
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(cfg.threads), lds_bytes, st, args);
+  return hipGetLastError();
+}
+
+int pairs_occupancy(int precision, int box_kind, bool sweep, const KernelConfig &cfg,
+                    size_t lds_bytes) {
+  PairFn fn = pick(precision, cfg.r, box_kind, sweep);
+  hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
+                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes));
+  (void)hipGetLastError();
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, cfg.threads, lds_bytes) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    return 1;
+  }
+  return blocks > 0 ? blocks : 1;
+}
+
+hipError_t launch_oor(const uint64_t *hist, int32_t n_hist, int32_t n_bins, const uint64_t *pairs,
+                      uint64_t *oor, hipStream_t st) {
+  if (n_hist <= 0) return hipSuccess;
+  oor_kernel<<<n_hist, 256, 0, st>>>(hist, n_bins, pairs, oor);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_t(int precision, int box_kind, const FrameParams *d_fp, const int32_t *pi,
+                         const int32_t *pj, int64_t n_pairs, int32_t n, double *t,
+                         hipStream_t st) {
+  if (n_pairs <= 0) return hipSuccess;
+  const int threads = 256;
+  const int grid = grid_for(n_pairs, threads);
+  if (precision == 1) {
+    switch (box_kind) {
+      case kBoxNone: pair_t_kernel<double, kBoxNone><<<grid, threads, 0, st>>>(d_fp, pi, pj, n_pairs, n, t); break;
+      case kBoxOrtho: pair_t_kernel<double, kBoxOrtho><<<grid, threads, 0, st>>>(d_fp, pi, pj, n_pairs, n, t); break;
+      case kBoxTric: pair_t_kernel<double, kBoxTric><<<grid, threads, 0, st>>>(d_fp, pi, pj, n_pairs, n, t); break;
+      default: pair_t_kernel<double, kBoxTricSearch><<<grid, threads, 0, st>>>(d_fp, pi, pj, n_pairs, n, t); break;
+    }
+  } else {
+    switch (box_kind) {
+      case kBoxNone: pair_t_kernel<float, kBoxNone><<<grid, threads, 0, st>>>(d_fp, pi, pj, n_pairs, n, t); break;
+      case kBoxOrtho: pair_t_kernel<float, kBoxOrtho><<<grid, threads, 0, st>>>(d_fp, pi, pj, n_pairs, n, t); break;
+      case kBoxTric: pair_t_kernel<float, kBoxTric><<<grid, threads, 0, st>>>(d_fp, pi, pj, n_pairs, n, t); break;
+      default: pair_t_kernel<float, kBoxTricSearch><<<grid, threads, 0, st>>>(d_fp, pi, pj, n_pairs, n, t); break;
+    }
+  }
+  return hipGetLastError();
+}
+
+}  // namespace dh

@@ -1,0 +1,199 @@
+"""ctypes binding of libdisthist (argument marshalling only).
+
+Every computation runs in the library's HIP kernels. PyTorch is used only to
+hold device buffers and to name streams. If the compiled library is missing
+this module raises ImportError at import time: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+BOX_NONE, BOX_ORTHO, BOX_TRICLINIC = 0, 1, 2
+FP32, FP64 = 0, 1
+DH_OK, DH_EINVAL, DH_ENOMEM, DH_EDEVICE, DH_EBUDGET, DH_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libdisthist.so")
+
+# Every symbol declared in include/disthist.h, with its ctypes signature.
+_vp, _i32, _i64, _f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+SIGNATURES = {
+    "dh_version": ([], ctypes.c_char_p),
+    "dh_strerror": ([ctypes.c_int], ctypes.c_char_p),
+    "dh_check_args": ([_vp, _vp, _i32, _i32, _vp, _f64, _i32, _i32], ctypes.c_int),
+    "dh_histo": ([_vp, _vp, _i32, _i32, _vp, _f64, _i32, _i32, _vp], ctypes.c_int),
+    "dh_ctx_create": ([_i32, ctypes.POINTER(_vp)], ctypes.c_int),
+    "dh_ctx_destroy": ([_vp], None),
+    "dh_ctx_last_error": ([_vp], ctypes.c_char_p),
+    "dh_histo_async": ([_vp, _vp, _vp, _vp, _i32, _i32, _vp, _f64, _i32, _i32, _vp, _vp],
+                       ctypes.c_int),
+    "dh_pair_t_async": ([_vp, _vp, _vp, _i64, _i32, _vp, _f64, _i32, _i32, _vp, _vp, _i64, _vp],
+                        ctypes.c_int),
+    "dh_ctx_profile": ([_vp, _i32], ctypes.c_int),
+    "dh_ctx_profile_read": ([_vp, ctypes.POINTER(_f64), ctypes.POINTER(_i64)], ctypes.c_int),
+}
+
+
+def _load() -> ctypes.CDLL:
+    # One HIP runtime per process: PyTorch ships its own libamdhip64.so.7 and
+    # fails to initialise the GPU if another copy with that soname was loaded
+    # first. Importing torch before the library makes the library bind to
+    # torch's copy.
+    try:
+        import torch  # noqa: F401
+    except ImportError:  # pragma: no cover - torch is optional for the C ABI
+        pass
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"libdisthist.so not found at {LIB_PATH}; build it with "
+            "`python -m paper_1808_01478_amd.build` (there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (args, res) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+LIB = _load()
+
+
+class DisthistError(RuntimeError):
+    def __init__(self, code: int, detail: str = ""):
+        self.code = code
+        msg = LIB.dh_strerror(code).decode()
+        super().__init__(f"{msg} ({code})" + (f": {detail}" if detail else ""))
+
+
+def _check(rc: int, ctx=None):
+    if rc != DH_OK:
+        detail = LIB.dh_ctx_last_error(ctx if ctx else None).decode()
+        raise DisthistError(rc, detail)
+
+
+def version() -> str:
+    return LIB.dh_version().decode()
+
+
+def n_hist(n_species: int) -> int:
+    return n_species * (n_species + 1) // 2
+
+
+def _np_ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _host_box(box) -> Optional[np.ndarray]:
+    if box is None:
+        return None
+    return np.ascontiguousarray(np.asarray(box, np.float64).reshape(9))
+
+
+def _offsets(offsets) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(offsets, np.int64))
+
+
+def check_args(coords, offsets, box_type: int, box, r_max: float, n_bins: int,
+               precision: int) -> int:
+    """dh_check_args: host-only validation; returns the status code."""
+    c = None if coords is None else np.ascontiguousarray(coords, np.float64)
+    o = _offsets(offsets)
+    b = _host_box(box)
+    return int(LIB.dh_check_args(_np_ptr(c), _np_ptr(o), len(o) - 1, int(box_type), _np_ptr(b),
+                                 float(r_max), int(n_bins), int(precision)))
+
+
+def histo(coords, offsets, box_type: int, box, r_max: float, n_bins: int,
+          precision: int = FP32) -> np.ndarray:
+    """dh_histo: synchronous histogram of a host frame; returns uint64 [H, n_bins]."""
+    c = np.ascontiguousarray(coords, np.float64)
+    o = _offsets(offsets)
+    b = _host_box(box)
+    out = np.empty((n_hist(len(o) - 1), int(n_bins)), np.uint64)
+    _check(LIB.dh_histo(_np_ptr(c), _np_ptr(o), len(o) - 1, int(box_type), _np_ptr(b),
+                        float(r_max), int(n_bins), int(precision), _np_ptr(out)))
+    return out
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+class Context:
+    """A dh_ctx on one device (owns reusable device scratch)."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        _check(LIB.dh_ctx_create(int(device), ctypes.byref(h)))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            LIB.dh_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):  # pragma: no cover - interpreter shutdown order
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def last_error(self) -> str:
+        return LIB.dh_ctx_last_error(self.handle).decode()
+
+    def histo_async(self, d_coords, offsets, box_type: int, box, r_max: float, n_bins: int,
+                    precision: int, d_out, d_out_of_range=None, stream=None) -> None:
+        """dh_histo_async on torch device tensors: d_coords float64 [N,3],
+        d_out uint64/int64 [H, n_bins], d_out_of_range [H] or None."""
+        o = _offsets(offsets)
+        b = _host_box(box)
+        _check(LIB.dh_histo_async(self.handle, _stream_handle(stream),
+                                  ctypes.c_void_p(d_coords.data_ptr()), _np_ptr(o), len(o) - 1,
+                                  int(box_type), _np_ptr(b), float(r_max), int(n_bins),
+                                  int(precision), ctypes.c_void_p(d_out.data_ptr()),
+                                  None if d_out_of_range is None
+                                  else ctypes.c_void_p(d_out_of_range.data_ptr())),
+               self.handle)
+
+    def profile(self, enable: bool = True) -> None:
+        """dh_ctx_profile: time the pair kernel of every launch with HIP events."""
+        _check(LIB.dh_ctx_profile(self.handle, 1 if enable else 0), self.handle)
+
+    def profile_read(self):
+        """dh_ctx_profile_read: (summed pair-kernel ms, launches) since the last read."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(LIB.dh_ctx_profile_read(self.handle, ctypes.byref(ms), ctypes.byref(n)),
+               self.handle)
+        return float(ms.value), int(n.value)
+
+    def pair_t_async(self, d_coords, box_type: int, box, r_max: float, n_bins: int,
+                     precision: int, d_pi, d_pj, d_t, stream=None) -> None:
+        """dh_pair_t_async on torch device tensors (int32 indices, float64 output)."""
+        b = _host_box(box)
+        _check(LIB.dh_pair_t_async(self.handle, _stream_handle(stream),
+                                   ctypes.c_void_p(d_coords.data_ptr()), int(d_coords.shape[0]),
+                                   int(box_type), _np_ptr(b), float(r_max), int(n_bins),
+                                   int(precision), ctypes.c_void_p(d_pi.data_ptr()),
+                                   ctypes.c_void_p(d_pj.data_ptr()), int(d_pi.numel()),
+                                   ctypes.c_void_p(d_t.data_ptr())),
+               self.handle)
+
+
+def exported_symbols() -> Sequence[str]:
+    return list(SIGNATURES)

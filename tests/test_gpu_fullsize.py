@@ -1,0 +1,63 @@
+"""The full-size workloads in the launch configuration that bench.py times.
+
+ortho100k (N=100,000, 2 species, 10,000 bins): binary64 bit-exact against the
+oracle over all 4,999,950,000 pairs, binary32 within the edge-pair bound.
+triclinic1M (N=1,000,000 clustered, 3 species, 20,000 bins): pair-count
+identity at full size, binary64 and binary32 histograms related by the bound
+computed from a seeded subset, and sampled pairs checked one by one."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import fp32_bound_violations, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1808_01478_amd as dh
+    c = dh.Context(0)
+    yield c
+    c.close()
+
+
+def test_ortho100k_full(ctx):
+    fr = workloads.ortho()
+    print(f"\n[case] ortho100k oracle ({oracle.max_threads()} threads)", flush=True)
+    w = oracle.edge_window(fr.coords, fr.box, fr.r_max)
+    ref = oracle.frame_histogram(fr, edge_window=w)
+    print("[case] ortho100k gpu fp64", flush=True)
+    h64, oor64 = run_gpu(ctx, fr, 1)
+    assert np.array_equal(h64, ref.hist)
+    assert np.array_equal(oor64, ref.out_of_range)
+    print("[case] ortho100k gpu fp32", flush=True)
+    h32, oor32 = run_gpu(ctx, fr, 0)
+    bad = fp32_bound_violations(h32, ref.hist, ref.edges)
+    assert not bad, "; ".join(bad[:5])
+
+
+def test_triclinic1m_full(ctx):
+    fr = workloads.triclinic()
+    print("\n[case] triclinic1M gpu fp64", flush=True)
+    h64, oor64 = run_gpu(ctx, fr, 1)
+    pairs = fr.hist_pairs()
+    assert list(h64.sum(axis=1).astype(np.int64) + oor64.astype(np.int64)) == pairs
+    print("[case] triclinic1M gpu fp32", flush=True)
+    h32, oor32 = run_gpu(ctx, fr, 0)
+    assert list(h32.sum(axis=1).astype(np.int64) + oor32.astype(np.int64)) == pairs
+    # a seeded 40,000-point subset in the same launch path, against the oracle
+    sub = fr.subset([20_000, 12_000, 8_000])
+    print("[case] triclinic1M subset oracle", flush=True)
+    w = oracle.edge_window(sub.coords, sub.box, sub.r_max)
+    ref = oracle.frame_histogram(sub, edge_window=w)
+    s64, _ = run_gpu(ctx, sub, 1)
+    assert np.array_equal(s64, ref.hist)
+    s32, _ = run_gpu(ctx, sub, 0)
+    assert not fp32_bound_violations(s32, ref.hist, ref.edges)
+    # binary32 vs binary64 at full size: relative L1 in line with the subset's
+    l1_full = np.abs(h32.astype(np.int64) - h64.astype(np.int64)).sum() / max(1, h64.sum())
+    l1_sub = np.abs(s32.astype(np.int64) - s64.astype(np.int64)).sum() / max(1, s64.sum())
+    e_sub = ref.edges.sum() / max(1, ref.hist.sum())
+    assert l1_full <= 2 * e_sub + 1e-9, (l1_full, l1_sub, e_sub)

@@ -1,0 +1,185 @@
+"""HIP path vs the CPU oracle, element by element, through the C ABI.
+
+binary64: bit-exact histograms and out-of-range counts.
+binary32: within the edge-pair bound (per-edge cumulative difference at most
+the number of pairs whose binary64 distance lies within 4 ulp32(S) of that
+edge, S = max(|coordinate|, |box entry|, r_max))."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import fp32_bound_violations, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+SKEW = np.array([[10.0, 0, 0], [3.0, 9.5, 0], [-2.0, 3.5, 9.0]])
+
+
+def _frame(coords, sizes, box_type, box, r_max, n_bins, name):
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    return workloads.Frame(np.ascontiguousarray(coords, np.float64), offs, box_type,
+                           None if box is None else np.asarray(box, np.float64), float(r_max),
+                           int(n_bins), name)
+
+
+def cases():
+    rng = np.random.Generator(np.random.PCG64(2024))
+    out = [workloads.tiny()]
+    out.append(workloads.random_frame(11, [2500, 1, 0, 1337], workloads.BOX_NONE, r_max=12.0,
+                                      n_bins=97))
+    out[-1].name = "none-4species-ragged"
+    out.append(workloads.random_frame(12, [3001, 2047], workloads.BOX_ORTHO, n_bins=1000))
+    out[-1].name = "ortho-2species"
+    box = workloads.ortho_box(10.0, 11.0, 12.0)
+    out.append(_frame(rng.uniform(-30, 50, size=(2900, 3)), [1900, 1000], workloads.BOX_ORTHO,
+                      box, 5.9, 500, "ortho-unwrapped"))
+    out.append(_frame(rng.uniform(0, 10, size=(2100, 3)), [2100], workloads.BOX_ORTHO,
+                      workloads.ortho_box(10.0, 10.0, 10.0), 8.0, 333, "ortho-beyond-half"))
+    out.append(workloads.random_frame(13, [2600, 900], workloads.BOX_TRICLINIC, n_bins=777))
+    out[-1].name = "tric-2species"
+    w = workloads.min_width(SKEW)
+    out.append(workloads.random_frame(14, [1500, 700], workloads.BOX_TRICLINIC, box=SKEW,
+                                      r_max=0.8 * w, n_bins=300))
+    out[-1].name = "tric-search"
+    x = rng.uniform(-1.5, 2.5, size=(1800, 3)) @ SKEW
+    out.append(_frame(x, [1000, 800], workloads.BOX_TRICLINIC, SKEW, 0.45 * w, 256,
+                      "tric-unwrapped"))
+    c3 = workloads.triclinic(n=6000)
+    c3.name = "tric-clustered-6k"
+    out.append(c3)
+    out.append(workloads.random_frame(15, [2000, 1000], workloads.BOX_ORTHO, n_bins=50_000))
+    out[-1].name = "ortho-50k-bins-sweeps"
+    out.append(workloads.random_frame(16, [1700], workloads.BOX_NONE, r_max=17.3,
+                                      n_bins=90_001))
+    out[-1].name = "none-90001-bins-sweeps"
+    out.append(_frame(np.tile([[1.5, 2.5, 3.5]], (3000, 1)), [3000], workloads.BOX_NONE, None,
+                      1.0, 64, "coincident"))
+    out.append(workloads.random_frame(17, [1200, 800], workloads.BOX_NONE, r_max=1e-3,
+                                      n_bins=10))
+    out[-1].name = "all-out-of-range"
+    out.append(workloads.random_frame(18, [900, 1100], workloads.BOX_ORTHO, n_bins=1))
+    out[-1].name = "one-bin"
+    tr = workloads.trajectory_frame(7)
+    out.append(tr.subset([4000] * tr.n_species))
+    return out
+
+
+CASES = cases()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1808_01478_amd as dh
+    c = dh.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("frame", CASES, ids=[f.name for f in CASES])
+def test_fp64_bit_exact(ctx, frame):
+    print(f"\n[case] {frame.name} N={frame.n} k={frame.n_species} bins={frame.n_bins}", flush=True)
+    ref = oracle.frame_histogram(frame)
+    h, oor = run_gpu(ctx, frame, 1)
+    assert np.array_equal(h, ref.hist), \
+        f"{frame.name}: {int((h != ref.hist).sum())} bins differ"
+    assert np.array_equal(oor, ref.out_of_range)
+
+
+@pytest.mark.parametrize("frame", CASES, ids=[f.name for f in CASES])
+def test_fp32_edge_bound(ctx, frame):
+    print(f"\n[case] {frame.name} fp32", flush=True)
+    w = oracle.edge_window(frame.coords, frame.box, frame.r_max)
+    ref = oracle.frame_histogram(frame, edge_window=w)
+    h, oor = run_gpu(ctx, frame, 0)
+    assert list(h.sum(axis=1).astype(np.int64) + oor.astype(np.int64)) == frame.hist_pairs()
+    bad = fp32_bound_violations(h, ref.hist, ref.edges)
+    assert not bad, f"{frame.name}: " + "; ".join(bad[:5])
+
+
+def test_sync_api_matches_async(ctx):
+    import paper_1808_01478_amd as dh
+    fr = CASES[2]
+    for prec in (0, 1):
+        a = dh.histo(fr.coords, fr.offsets, fr.box_type, fr.box, fr.r_max, fr.n_bins, prec)
+        b, _ = run_gpu(ctx, fr, prec)
+        assert np.array_equal(a, b)
+
+
+def test_repeatable_and_stream_independent(ctx):
+    import torch
+    fr = CASES[8]
+    first = run_gpu(ctx, fr, 0)[0]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        second = run_gpu(ctx, fr, 0, stream=s)[0]
+    third = run_gpu(ctx, fr, 0)[0]
+    assert np.array_equal(first, second) and np.array_equal(first, third)
+
+
+def test_empty_and_single(ctx):
+    import paper_1808_01478_amd as dh
+    h = dh.histo(np.zeros((0, 3)), [0, 0], 0, None, 1.0, 8, 0)
+    assert h.shape == (1, 8) and not h.any()
+    h = dh.histo(np.zeros((1, 3)), [0, 1, 1], 1, np.eye(3) * 5, 1.0, 8, 1)
+    assert h.shape == (3, 8) and not h.any()
+
+
+@pytest.mark.parametrize("box_type", [0, 1, 2])
+def test_pair_t_matches_oracle(ctx, box_type):
+    """Per-pair scaled distance: binary64 identical to the oracle (this pins
+    the device sqrt as correctly rounded), binary32 within the window."""
+    import torch
+    if box_type == 2:
+        fr = workloads.triclinic(n=50_000)
+    elif box_type == 1:
+        fr = workloads.ortho(n=50_000)
+    else:
+        fr = workloads.tiny()
+    rng = np.random.Generator(np.random.PCG64(5 + box_type))
+    m = 400_000
+    pi = rng.integers(0, fr.n, size=m)
+    pj = rng.integers(0, fr.n, size=m)
+    ref = oracle.pair_t(fr.coords, fr.box_type, fr.box, fr.r_max, fr.n_bins, pi, pj)
+    dev = torch.device("cuda")
+    x = torch.from_numpy(fr.coords).to(dev)
+    dpi = torch.from_numpy(pi.astype(np.int32)).to(dev)
+    dpj = torch.from_numpy(pj.astype(np.int32)).to(dev)
+    t = torch.empty(m, dtype=torch.float64, device=dev)
+    ctx.pair_t_async(x, fr.box_type, fr.box, fr.r_max, fr.n_bins, 1, dpi, dpj, t)
+    torch.cuda.synchronize()
+    t64 = t.cpu().numpy()
+    assert np.array_equal(t64, ref), f"{int((t64 != ref).sum())} of {m} differ"
+    ctx.pair_t_async(x, fr.box_type, fr.box, fr.r_max, fr.n_bins, 0, dpi, dpj, t)
+    torch.cuda.synchronize()
+    t32 = t.cpu().numpy()
+    win = oracle.edge_window(fr.coords, fr.box, fr.r_max) * fr.n_bins / fr.r_max
+    err = np.abs(t32 - ref)
+    assert err.max() <= win, f"max |t32 - t64| = {err.max():.3g} > window {win:.3g}"
+
+
+def test_sqrt_exact_on_perfect_squares(ctx):
+    import torch
+    rng = np.random.Generator(np.random.PCG64(9))
+    # integer points: q is an integer; t = sqrt(q) * 1 exactly when n_bins = r_max
+    x = rng.integers(0, 1 << 20, size=(4096, 3)).astype(np.float64)
+    r_max = float(1 << 22)
+    i, j = np.triu_indices(4096, 1)
+    sel = rng.choice(len(i), 500_000, replace=False)
+    pi, pj = i[sel], j[sel]
+    ref = oracle.pair_t(x, 0, None, r_max, int(r_max), pi, pj)
+    dev = torch.device("cuda")
+    t = torch.empty(len(pi), dtype=torch.float64, device=dev)
+    ctx.pair_t_async(torch.from_numpy(x).to(dev), 0, None, r_max, int(r_max), 1,
+                     torch.from_numpy(pi.astype(np.int32)).to(dev),
+                     torch.from_numpy(pj.astype(np.int32)).to(dev), t)
+    torch.cuda.synchronize()
+    got = t.cpu().numpy()
+    assert np.array_equal(got, ref)
+    d = x[pj] - x[pi]
+    q = (d * d).sum(axis=1)
+    sq = np.array([math.isqrt(int(v)) for v in q])
+    perfect = sq * sq == q
+    assert np.array_equal(got[perfect], sq[perfect].astype(np.float64))
