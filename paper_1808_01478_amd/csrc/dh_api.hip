@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -144,12 +145,10 @@ int frame_consts(int32_t box_type, const double *box, double r_max, int32_t n_bi
       const double w = min_width_tri(fp.ax, fp.bx, fp.by, fp.cx, fp.cy, fp.cz);
       kind = (2.0 * r_max >= w * (1.0 - 1e-9)) ? kBoxTricSearch : kBoxTric;
     }
-    for (int c = 0; c < 3; ++c) {
-      fp.Ls[c] = static_cast<float>(fp.L[c] * fp.s);
-      fp.hs[c] = 0.5f * fp.Ls[c];
-    }
+    constexpr double kTwo32 = 4294967296.0;
+    for (int c = 0; c < 3; ++c) fp.k32[c] = static_cast<float>(fp.L[c] * fp.s / kTwo32);
     const double B[6] = {fp.ax, fp.bx, fp.by, fp.cx, fp.cy, fp.cz};
-    for (int c = 0; c < 6; ++c) fp.Bs[c] = static_cast<float>(B[c] * fp.s);
+    for (int c = 0; c < 6; ++c) fp.Bk[c] = static_cast<float>(B[c] * fp.s / kTwo32);
     for (int q = 0; q < kShifts; ++q)
       for (int c = 0; c < 3; ++c) fp.shift32[q][c] = static_cast<float>(fp.shift64[q][c] * fp.s);
   }
@@ -157,19 +156,37 @@ int frame_consts(int32_t box_type, const double *box, double r_max, int32_t n_bi
   return kind;
 }
 
+// Upper bound of t = r * s over all pairs of a periodic frame (the minimum
+// image is at most the longest half-diagonal of the cell); 0 without a box.
+double t_bound(const FrameParams &fp) {
+  if (fp.box == kBoxNone) return 0.0;
+  double best = 0.0;
+  for (int sa = -1; sa <= 1; sa += 2)
+    for (int sb = -1; sb <= 1; sb += 2)
+      for (int sc = -1; sc <= 1; sc += 2) {
+        const double vx = 0.5 * (sa * fp.ax + sb * fp.bx + sc * fp.cx);
+        const double vy = 0.5 * (sb * fp.by + sc * fp.cy);
+        const double vz = 0.5 * (sc * fp.cz);
+        best = std::max(best, std::sqrt(vx * vx + vy * vy + vz * vz));
+      }
+  return best * fp.s;
+}
+
 struct Launch {
   KernelConfig cfg;
   int win = 0, n_sweeps = 1, stride = 0, grid = 0;
+  bool noclamp = false;
   size_t lds = 0;
 };
 
 size_t coord_bytes(int precision) { return precision == DH_FP64 ? 32 : 16; }
 
 // Launch shape for one frame (heuristic defaults).
-Launch choose_launch(const dh_ctx *ctx, int precision, int kind, int32_t n_bins,
+Launch choose_launch(const dh_ctx *ctx, int precision, const FrameParams &fp,
                      uint64_t total_pairs) {
   Launch L;
   KernelConfig &c = L.cfg;
+  const int32_t n_bins = fp.n_bins;
   c.threads = 256;
   c.r = precision == DH_FP64 ? 4 : 8;
   c.copies = 1;
@@ -186,8 +203,22 @@ Launch choose_launch(const dh_ctx *ctx, int precision, int kind, int32_t n_bins,
     L.win = (n_bins + L.n_sweeps - 1) / L.n_sweeps;
   }
   L.stride = L.win + kDump;
+  // Without clamping, every t of a periodic frame must index a slot below the
+  // stride: slots = floor(bound * (1 + 1e-4)) + 2 covers the rounding of the
+  // minimum image and of the distance.
+  L.noclamp = false;
+  const char *env = std::getenv("DH_NOCLAMP");
+  const bool allow = !(env && env[0] == '0');
+  const double tb = t_bound(fp);
+  if (allow && L.n_sweeps == 1 && tb > 0) {
+    const int64_t slots = static_cast<int64_t>(tb * (1.0 + 1e-4)) + 2;
+    if (slots <= win_max + kDump) {
+      L.noclamp = true;
+      L.stride = static_cast<int>(std::max<int64_t>(L.stride, slots));
+    }
+  }
   L.lds = tile_bytes + static_cast<size_t>(c.copies) * L.stride * 4;
-  const int occ = pairs_occupancy(precision, kind, L.n_sweeps > 1, c, L.lds);
+  const int occ = pairs_occupancy(precision, fp.box, L.n_sweeps > 1, c, L.lds);
   L.grid = ctx->n_cu * occ;
   // j-chunk: about 8 items per workgroup over the whole (swept) job
   const uint64_t bi = static_cast<uint64_t>(c.threads) * c.r;
@@ -207,7 +238,8 @@ void plan_frame(int32_t frame, const int64_t *off, int32_t k, const Launch &L,
   const int64_t jc = L.cfg.jchunk;
   auto emit = [&](int32_t h, int64_t i0, int64_t i1, int64_t j0, int64_t j1, int32_t diag) {
     WorkItem w;
-    w.frame = frame; w.hist = h; w.sweep = 0; w.diag = diag;
+    w.frame = frame; w.hist = h; w.sweep = 0;
+    w.flags = (diag ? kItemDiag : 0) | (i1 - i0 == bi ? kItemFull : 0);
     w.i0 = static_cast<int32_t>(i0); w.i1 = static_cast<int32_t>(i1);
     w.j0 = static_cast<int32_t>(j0); w.j1 = static_cast<int32_t>(j1);
     items.push_back(w);
@@ -417,7 +449,9 @@ int dh_histo_async(dh_ctx *ctx, dh_stream stream, const double *d_coords, const 
   DH_HIP(ctx, hipSetDevice(ctx->device));
 
   FrameParams fp;
-  const int kind = frame_consts(box_type, box, r_max, n_bins, fp);
+  int kind = frame_consts(box_type, box, r_max, n_bins, fp);
+  if (precision == DH_FP32 && kind == kBoxOrtho && fp.L[0] == fp.L[1] && fp.L[1] == fp.L[2])
+    fp.box = kind = kBoxCube;
   const int32_t n_hist = n_species * (n_species + 1) / 2;
   uint64_t total = 0;
   for (int s = 0; s < n_species; ++s) {
@@ -426,9 +460,10 @@ int dh_histo_async(dh_ctx *ctx, dh_stream stream, const double *d_coords, const 
     for (int t = s + 1; t < n_species; ++t)
       total += a * static_cast<uint64_t>(offsets[t + 1] - offsets[t]);
   }
-  Launch L = choose_launch(ctx, precision, kind, n_bins, total);
+  Launch L = choose_launch(ctx, precision, fp, total);
   fp.win = L.win;
   fp.n_sweeps = L.n_sweeps;
+  fp.noclamp = L.noclamp ? 1 : 0;
   std::vector<WorkItem> items;
   std::vector<uint64_t> pairs;
   plan_frame(0, offsets, n_species, L, items, pairs);
@@ -536,7 +571,9 @@ int dh_pair_t_async(dh_ctx *ctx, dh_stream stream, const double *d_coords, int64
   hipStream_t st = static_cast<hipStream_t>(stream);
   DH_HIP(ctx, hipSetDevice(ctx->device));
   FrameParams fp;
-  const int kind = frame_consts(box_type, box, r_max, n_bins, fp);
+  int kind = frame_consts(box_type, box, r_max, n_bins, fp);
+  if (precision == DH_FP32 && kind == kBoxOrtho && fp.L[0] == fp.L[1] && fp.L[1] == fp.L[2])
+    fp.box = kind = kBoxCube;
   fp.win = n_bins;
   fp.n_sweeps = 1;
   rc = ensure_device(ctx, &ctx->d_staged, &ctx->staged_cap,

@@ -12,7 +12,12 @@ enum BoxKind : int32_t {
   kBoxOrtho = 1,
   kBoxTric = 2,        // Eq. 5 reduction only (r_max below half the smallest width)
   kBoxTricSearch = 3,  // Eq. 5 reduction, then the 27 neighbouring images
+  kBoxCube = 4,        // binary32 only: orthorhombic cell with equal edges
 };
+
+// WorkItem::flags
+constexpr int32_t kItemDiag = 1;  // i- and j-range are the same block: count j > i only
+constexpr int32_t kItemFull = 2;  // every lane holds a valid i-particle
 
 constexpr int kShifts = 27;
 constexpr int kDump = 64;  // per-lane discard slots after the bin window
@@ -25,9 +30,12 @@ constexpr int kDump = 64;  // per-lane discard slots after the bin window
 //   h23 = -cy/(by*cz), h13 = (bx*cy - by*cx)/(ax*by*cz),
 // with shifts S = i*a + j*b + k*c for i, j, k in {-1, 0, 1}.
 //
-// binary32 members serve the reduced-precision path, whose coordinates are
-// staged pre-scaled by s (and wrapped into the cell for periodic boxes), so
-// the kernel's distance is already t = r * s.
+// binary32 members serve the reduced-precision path. Without a box the
+// coordinates are staged pre-scaled by s. With a periodic cell they are
+// staged as 32-bit fixed-point fractional coordinates u = 2^32 * (f mod 1),
+// f = B^-1 x: the wrapped difference u_j - u_i read as a signed integer is
+// 2^32 * (f_j - f_i - nint(f_j - f_i)), the reduced vector of Eq. 5 in
+// fractional form, and the cell matrix scaled by s / 2^32 maps it to t units.
 struct FrameParams {
   const void *coords;  // staged float4 / double4 [N] (device)
   uint64_t *out;       // [H][n_bins] (device)
@@ -40,17 +48,17 @@ struct FrameParams {
   double ax, bx, by, cx, cy, cz;
   double h11, h12, h13, h22, h23, h33;
   double shift64[kShifts][3];
-  float Ls[3], hs[3];  // orthorhombic edge * s and half of it
-  float Bs[6];         // ax bx by cx cy cz, times s
-  float shift32[kShifts][3];
-  float pad_[2];
+  float k32[3];        // orthorhombic: L_c * s / 2^32 (cube: k32[0])
+  float Bk[6];         // ax bx by cx cy cz, times s / 2^32
+  float shift32[kShifts][3];  // image shifts times s
+  int32_t noclamp;     // 1: every t of a full block fits below `stride` slots
+  int32_t pad_;
 };
 
 // One unit of work: particles [i0, i1) of the frame against [j0, j1), for
-// histogram `hist`, bin window `sweep`. diag = 1 when both ranges are the same
-// block of one species, so only j > i counts.
+// histogram `hist`, bin window `sweep`; flags: kItemDiag, kItemFull.
 struct WorkItem {
-  int32_t frame, hist, sweep, diag;
+  int32_t frame, hist, sweep, flags;
   int32_t i0, i1, j0, j1;
 };
 

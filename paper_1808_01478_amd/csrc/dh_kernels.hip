@@ -68,7 +68,7 @@ template <int BOX>
 __device__ __forceinline__ double t64(double xi, double yi, double zi, double xj, double yj,
                                       double zj, const Geo64 &g) {
   double dx = xj - xi, dy = yj - yi, dz = zj - zi;
-  if constexpr (BOX == kBoxOrtho) {
+  if constexpr (BOX == kBoxOrtho || BOX == kBoxCube) {
     const double n0 = rint(dx * g.iL0), n1 = rint(dy * g.iL1), n2 = rint(dz * g.iL2);
     dx = fma(-g.L0, n0, dx);
     dy = fma(-g.L1, n1, dy);
@@ -95,51 +95,61 @@ __device__ __forceinline__ double t64(double xi, double yi, double zi, double xj
   return sqrt(q) * g.s;  // correctly rounded sqrt (default HIP lowering)
 }
 
-// binary32: coordinates are staged pre-scaled by s (so the result is t),
-// wrapped into [0, L*s) for orthorhombic cells and given as wrapped
-// fractional coordinates for triclinic cells.
+// binary32. Without a box the staged coordinates are x * s, so the
+// Euclidean length is already t. With a periodic cell they are 32-bit
+// fixed-point fractional coordinates: the wrapped difference u_j - u_i read as
+// a signed integer is 2^32 times the Eq. 5 reduced fractional difference, so
+// the minimum image costs one integer subtraction per axis; converting it to
+// float and applying the cell matrix scaled by s / 2^32 gives t units.
 struct Geo32 {
-  float hx, hy, hz;                 // half edges (orthorhombic)
-  float ax, bx, by, cx, cy, cz;     // cell matrix times s (triclinic)
-  const float (*shift)[3];
+  float kx, ky, kz;                 // orthorhombic: L_c * s / 2^32
+  float ax, bx, by, cx, cy, cz;     // triclinic: cell matrix * s / 2^32
+  const float (*shift)[3];          // image shifts * s
 };
 
 __device__ __forceinline__ Geo32 load_geo32(const FrameParams *F) {
   Geo32 g;
-  g.hx = uni(F->hs[0]); g.hy = uni(F->hs[1]); g.hz = uni(F->hs[2]);
-  g.ax = uni(F->Bs[0]); g.bx = uni(F->Bs[1]); g.by = uni(F->Bs[2]);
-  g.cx = uni(F->Bs[3]); g.cy = uni(F->Bs[4]); g.cz = uni(F->Bs[5]);
+  g.kx = uni(F->k32[0]); g.ky = uni(F->k32[1]); g.kz = uni(F->k32[2]);
+  g.ax = uni(F->Bk[0]); g.bx = uni(F->Bk[1]); g.by = uni(F->Bk[2]);
+  g.cx = uni(F->Bk[3]); g.cy = uni(F->Bk[4]); g.cz = uni(F->Bk[5]);
   g.shift = F->shift32;
   return g;
+}
+
+// reduced fractional difference, units of 2^-32 of the cell vector
+__device__ __forceinline__ float frac_diff(float ui, float uj) {
+  return static_cast<float>(static_cast<int32_t>(__float_as_uint(uj) - __float_as_uint(ui)));
 }
 
 template <int BOX>
 __device__ __forceinline__ float t32(float xi, float yi, float zi, float xj, float yj, float zj,
                                      const Geo32 &g) {
-  float dx = xj - xi, dy = yj - yi, dz = zj - zi;
-  if constexpr (BOX == kBoxOrtho) {
-    // both points lie in [0, L): the nearest image of a component d has
-    // length min(|d|, L - |d|) = h - ||d| - h|, h = L/2
-    dx = g.hx - fabsf(fabsf(dx) - g.hx);
-    dy = g.hy - fabsf(fabsf(dy) - g.hy);
-    dz = g.hz - fabsf(fabsf(dz) - g.hz);
-  } else if constexpr (BOX == kBoxTric || BOX == kBoxTricSearch) {
-    // Eq. 5 in fractional coordinates: f - nint(f), then back through B
-    const float fa = dx - rintf(dx), fb = dy - rintf(dy), fc = dz - rintf(dz);
-    dx = fmaf(g.cx, fc, fmaf(g.bx, fb, g.ax * fa));
-    dy = fmaf(g.cy, fc, g.by * fb);
-    dz = g.cz * fc;
-  }
-  float q = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-  if constexpr (BOX == kBoxTricSearch) {
-    for (int m = 0; m < kShifts; ++m) {
-      const float vx = dx + uni(g.shift[m][0]);
-      const float vy = dy + uni(g.shift[m][1]);
-      const float vz = dz + uni(g.shift[m][2]);
-      q = fminf(q, fmaf(vz, vz, fmaf(vy, vy, vx * vx)));
+  if constexpr (BOX == kBoxNone) {
+    const float dx = xj - xi, dy = yj - yi, dz = zj - zi;
+    return __builtin_amdgcn_sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));  // v_sqrt_f32
+  } else {
+    const float fa = frac_diff(xi, xj), fb = frac_diff(yi, yj), fc = frac_diff(zi, zj);
+    if constexpr (BOX == kBoxCube) {
+      return __builtin_amdgcn_sqrtf(fmaf(fc, fc, fmaf(fb, fb, fa * fa))) * g.kx;
+    } else if constexpr (BOX == kBoxOrtho) {
+      const float dx = fa * g.kx, dy = fb * g.ky, dz = fc * g.kz;
+      return __builtin_amdgcn_sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+    } else {
+      const float dx = fmaf(g.cx, fc, fmaf(g.bx, fb, g.ax * fa));
+      const float dy = fmaf(g.cy, fc, g.by * fb);
+      const float dz = g.cz * fc;
+      float q = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+      if constexpr (BOX == kBoxTricSearch) {
+        for (int m = 0; m < kShifts; ++m) {
+          const float vx = dx + uni(g.shift[m][0]);
+          const float vy = dy + uni(g.shift[m][1]);
+          const float vz = dz + uni(g.shift[m][2]);
+          q = fminf(q, fmaf(vz, vz, fmaf(vy, vy, vx * vx)));
+        }
+      }
+      return __builtin_amdgcn_sqrtf(q);
     }
   }
-  return __builtin_amdgcn_sqrtf(q);  // v_sqrt_f32
 }
 
 template <typename T>
@@ -176,7 +186,12 @@ __global__ void stage64_kernel(const double *__restrict__ in, double4 *__restric
     out[i] = make_double4(in[3 * i], in[3 * i + 1], in[3 * i + 2], 0.0);
 }
 
-__device__ __forceinline__ double wrap01(double f) { return f - floor(f); }
+// 32-bit fixed-point image of a fractional coordinate: floor(2^32 * (f mod 1))
+__device__ __forceinline__ float fixfrac(double f) {
+  const double w = f - floor(f);
+  const uint64_t u = static_cast<uint64_t>(w * 4294967296.0);
+  return __uint_as_float(static_cast<uint32_t>(u));
+}
 
 template <int BOX>
 __global__ void stage32_kernel(const double *__restrict__ in, float4 *__restrict__ out, int64_t n,
@@ -190,17 +205,12 @@ __global__ void stage32_kernel(const double *__restrict__ in, float4 *__restrict
       v = make_float4(static_cast<float>(x * p.s), static_cast<float>(y * p.s),
                       static_cast<float>(z * p.s), 0.f);
     } else if constexpr (BOX == kBoxOrtho) {
-      const double ux = x - p.L[0] * floor(x * p.iL[0]);
-      const double uy = y - p.L[1] * floor(y * p.iL[1]);
-      const double uz = z - p.L[2] * floor(z * p.iL[2]);
-      v = make_float4(static_cast<float>(ux * p.s), static_cast<float>(uy * p.s),
-                      static_cast<float>(uz * p.s), 0.f);
+      v = make_float4(fixfrac(x * p.iL[0]), fixfrac(y * p.iL[1]), fixfrac(z * p.iL[2]), 0.f);
     } else {
       const double fa = fma(z, p.h13, fma(y, p.h12, x * p.h11));
       const double fb = fma(z, p.h23, y * p.h22);
       const double fc = z * p.h33;
-      v = make_float4(static_cast<float>(wrap01(fa)), static_cast<float>(wrap01(fb)),
-                      static_cast<float>(wrap01(fc)), 0.f);
+      v = make_float4(fixfrac(fa), fixfrac(fb), fixfrac(fc), 0.f);
     }
     out[i] = v;
   }
@@ -233,7 +243,10 @@ __device__ __forceinline__ void flush_hist(uint32_t *hist, const PairKernelArgs 
   }
 }
 
-template <typename T, int R, int BOX, bool SWEEP, bool DIAG>
+// CLAMP = false: the host proved that every t of this frame is below the LDS
+// stride and the block has no invalid lanes, so the bin index needs no clamp
+// (out-of-range pairs land in slots [n_bins, stride) that are never flushed).
+template <typename T, int R, int BOX, bool SWEEP, bool DIAG, bool CLAMP>
 __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem &w,
                                          const FrameParams *F,
                                          typename V4<T>::type *__restrict__ tile,
@@ -290,7 +303,9 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
         for (int r = 0; r < R; ++r) {
           const T t = pair_t<T, BOX>(xi[r], yi[r], zi[r], pj.x, pj.y, pj.z, g);
           uint32_t idx;
-          if constexpr (sizeof(T) == 4 && !SWEEP) {
+          if constexpr (!CLAMP) {
+            idx = static_cast<uint32_t>(t);
+          } else if constexpr (sizeof(T) == 4 && !SWEEP) {
             float l = lof[r];
             if constexpr (DIAG) l = (j > wbase + r * 64 + lane) ? l : hif;
             idx = static_cast<uint32_t>(__builtin_amdgcn_fmed3f(t, l, hif));
@@ -337,7 +352,7 @@ __global__ __launch_bounds__(256) void pairs_kernel(PairKernelArgs a) {
     {
       const WorkItem *p = a.items + it;
       w.frame = uni(p->frame); w.hist = uni(p->hist); w.sweep = uni(p->sweep);
-      w.diag = uni(p->diag); w.i0 = uni(p->i0); w.i1 = uni(p->i1);
+      w.flags = uni(p->flags); w.i0 = uni(p->i0); w.i1 = uni(p->i1);
       w.j0 = uni(p->j0); w.j1 = uni(p->j1);
     }
     const uint64_t npairs =
@@ -353,10 +368,16 @@ __global__ __launch_bounds__(256) void pairs_kernel(PairKernelArgs a) {
     }
     acc += npairs;
     const FrameParams *F = a.frames + w.frame;
-    if (w.diag)
-      run_item<T, R, BOX, SWEEP, true>(a, w, F, tile, my);
-    else
-      run_item<T, R, BOX, SWEEP, false>(a, w, F, tile, my);
+    if (w.flags & kItemDiag) {
+      run_item<T, R, BOX, SWEEP, true, true>(a, w, F, tile, my);
+    } else {
+      bool clamp = true;
+      if constexpr (!SWEEP) clamp = !((w.flags & kItemFull) && uni(F->noclamp));
+      if (clamp)
+        run_item<T, R, BOX, SWEEP, false, true>(a, w, F, tile, my);
+      else if constexpr (!SWEEP)
+        run_item<T, R, BOX, false, false, false>(a, w, F, tile, my);
+    }
   }
   if (cur_frame >= 0) flush_hist(hist, a, a.frames + cur_frame, cur_hist, cur_sweep);
 }
@@ -412,6 +433,9 @@ PairFn pick_box(int box) {
     case kBoxNone: return pairs_kernel<T, R, kBoxNone, SW>;
     case kBoxOrtho: return pairs_kernel<T, R, kBoxOrtho, SW>;
     case kBoxTric: return pairs_kernel<T, R, kBoxTric, SW>;
+    case kBoxCube:
+      if constexpr (sizeof(T) == 4) return pairs_kernel<T, R, kBoxCube, SW>;
+      return pairs_kernel<T, R, kBoxOrtho, SW>;
     default: return pairs_kernel<T, R, kBoxTricSearch, SW>;
   }
 }
@@ -446,7 +470,8 @@ hipError_t launch_stage(int precision, int box_kind, const double *in, void *out
     float4 *o = static_cast<float4 *>(out);
     switch (box_kind) {
       case kBoxNone: stage32_kernel<kBoxNone><<<grid, threads, 0, st>>>(in, o, n, fp); break;
-      case kBoxOrtho: stage32_kernel<kBoxOrtho><<<grid, threads, 0, st>>>(in, o, n, fp); break;
+      case kBoxOrtho:
+      case kBoxCube: stage32_kernel<kBoxOrtho><<<grid, threads, 0, st>>>(in, o, n, fp); break;
       default: stage32_kernel<kBoxTric><<<grid, threads, 0, st>>>(in, o, n, fp); break;
     }
   }
@@ -501,7 +526,8 @@ hipError_t launch_pair_t(int precision, int box_kind, const FrameParams *d_fp, c
   if (precision == 1) {
     switch (box_kind) {
       case kBoxNone: pair_t_kernel<double, kBoxNone><<<grid, threads, 0, st>>>(d_fp, pi, pj, n_pairs, n, t); break;
-      case kBoxOrtho: pair_t_kernel<double, kBoxOrtho><<<grid, threads, 0, st>>>(d_fp, pi, pj, n_pairs, n, t); break;
+      case kBoxOrtho:
+      case kBoxCube: pair_t_kernel<double, kBoxOrtho><<<grid, threads, 0, st>>>(d_fp, pi, pj, n_pairs, n, t); break;
       case kBoxTric: pair_t_kernel<double, kBoxTric><<<grid, threads, 0, st>>>(d_fp, pi, pj, n_pairs, n, t); break;
       default: pair_t_kernel<double, kBoxTricSearch><<<grid, threads, 0, st>>>(d_fp, pi, pj, n_pairs, n, t); break;
     }
@@ -509,6 +535,7 @@ hipError_t launch_pair_t(int precision, int box_kind, const FrameParams *d_fp, c
     switch (box_kind) {
       case kBoxNone: pair_t_kernel<float, kBoxNone><<<grid, threads, 0, st>>>(d_fp, pi, pj, n_pairs, n, t); break;
       case kBoxOrtho: pair_t_kernel<float, kBoxOrtho><<<grid, threads, 0, st>>>(d_fp, pi, pj, n_pairs, n, t); break;
+      case kBoxCube: pair_t_kernel<float, kBoxCube><<<grid, threads, 0, st>>>(d_fp, pi, pj, n_pairs, n, t); break;
       case kBoxTric: pair_t_kernel<float, kBoxTric><<<grid, threads, 0, st>>>(d_fp, pi, pj, n_pairs, n, t); break;
       default: pair_t_kernel<float, kBoxTricSearch><<<grid, threads, 0, st>>>(d_fp, pi, pj, n_pairs, n, t); break;
     }
