@@ -29,6 +29,11 @@ template <>
 struct V4<double> { using type = double4; };
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// s_waitcnt immediates (gfx9 encoding: vmcnt bits [3:0] and [15:14], expcnt
+// [6:4], lgkmcnt [11:8]); a field at its maximum does not wait.
+constexpr int kWaitVm0 = 0x0F70;    // vmcnt(0)
+constexpr int kWaitLgkm0 = 0xC07F;  // lgkmcnt(0)
 __device__ __forceinline__ float uni(float v) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
@@ -279,6 +284,10 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
   const float hif = static_cast<float>(hi);
 #pragma unroll
   for (int r = 0; r < R; ++r) lof[r] = static_cast<float>(lo[r]);
+  // The i-particles are complete before the tile loop, so the only global
+  // load in flight inside it is the next tile's prefetch, which the j-loop
+  // never reads.
+  __builtin_amdgcn_s_waitcnt(kWaitVm0);
 
   V pre = {};
   if (tid < tj && w.j0 + tid < w.j1) pre = X[w.j0 + tid];
@@ -293,12 +302,10 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
     const int jcount = min(tj, w.j1 - jt);
     int js = 0;
     if constexpr (DIAG) js = max(0, min(jcount, wbase + 1 - jt));
-    if (wave_active) {
+    if (wave_active && js < jcount) {
       const V *__restrict__ tb = tile + buf * tj;
-#pragma unroll 2
-      for (int jj = js; jj < jcount; ++jj) {
-        const V pj = tb[jj];
-        const int j = jt + jj;
+      // R pairs of one j: distance, bin, one LDS atomic each
+      auto pairs_of = [&](const V &pj, int j) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const T t = pair_t<T, BOX>(xi[r], yi[r], zi[r], pj.x, pj.y, pj.z, g);
@@ -322,7 +329,25 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
           }
           atomicAdd(my + idx, 1u);
         }
+      };
+      // Ping-pong over two j registers: the read of the next j is issued
+      // before the current j's atomics. LDS operations complete in order, so
+      // a read issued after the atomics would wait for all of them
+      // (bank-conflicted) before the arithmetic could start.
+      V pa = tb[js];
+      __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+      int jj = js;
+      for (; jj + 1 < jcount; jj += 2) {
+        const V pb = tb[jj + 1];
+        // binary32: pin the read ahead of the atomics (measured faster);
+        // binary64 has enough arithmetic per j to hide it unpinned
+        if constexpr (sizeof(T) == 4) __builtin_amdgcn_sched_barrier(0);
+        pairs_of(pa, jt + jj);
+        pa = tb[min(jj + 2, jcount - 1)];
+        if constexpr (sizeof(T) == 4) __builtin_amdgcn_sched_barrier(0);
+        pairs_of(pb, jt + jj + 1);
       }
+      if (jj < jcount) pairs_of(pa, jt + jj);
     }
   }
 }
