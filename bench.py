@@ -122,6 +122,57 @@ def time_path(ctx, frame, precision, steps, warmup):
     }
 
 
+def bench_trajectory(ctx, n_frames: int, steps: int):
+    """The trajectory workload (512 orthorhombic frames, N log-uniform in
+    [1e4, 2e5], 1-4 species, 4,096 bins) in binary32: one batched graph
+    replay per step against one dh_histo_async call per frame."""
+    import torch
+    import paper_1808_01478_amd as dh
+    frames = workloads.trajectory(n_frames)
+    dev = torch.device("cuda")
+    bufs = []
+    for f in frames:
+        bufs.append({"d_coords": torch.from_numpy(f.coords).to(dev), "offsets": f.offsets,
+                     "box_type": f.box_type, "box": f.box, "r_max": f.r_max, "n_bins": f.n_bins,
+                     "d_out": torch.empty((f.n_hist, f.n_bins), dtype=torch.int64, device=dev)})
+    pairs = sum(f.total_pairs() for f in frames)
+    batch = dh.Batch(ctx, bufs, dh.FP32, graph=True)
+    batch.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        batch.launch()
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / steps
+    snap = [b["d_out"].clone() for b in bufs[:8]]
+
+    def per_frame():
+        for f, b in zip(frames, bufs):
+            ctx.histo_async(b["d_coords"], f.offsets, f.box_type, f.box, f.r_max, f.n_bins,
+                            dh.FP32, b["d_out"])
+    per_frame()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        per_frame()
+    torch.cuda.synchronize()
+    t_frames = (time.perf_counter() - t0) / steps
+    same = all(torch.equal(a, b["d_out"]) for a, b in zip(snap, bufs[:8]))
+    info = batch.info()
+    batch.close()
+    return {
+        "workload": f"trajectory: {n_frames} orthorhombic frames, N log-uniform [1e4, 2e5], "
+                    "1-4 species, r_max = half the shortest edge, 4,096 bins, binary32",
+        "pairs_per_run": pairs,
+        "batched_graph": {"value": pairs / t_batch, "unit": "pairs/s", "ms_per_run": t_batch * 1e3,
+                          "items": info["items"], "pair_launches": info["launches"]},
+        "per_frame_launches": {"value": pairs / t_frames, "unit": "pairs/s",
+                               "ms_per_run": t_frames * 1e3, "launches": n_frames},
+        "speedup": t_frames / t_batch,
+        "identical_results": bool(same),
+    }
+
+
 def cpu_baseline(frame, target_s: float = 12.0):
     """The oracle (plain FP64 double loop, OpenMP) on the first M points of
     every species of the same frame, M sized for about target_s seconds."""
@@ -140,16 +191,21 @@ def cpu_baseline(frame, target_s: float = 12.0):
     m = int(np.sqrt(2.0 * rate * target_s))
     m = max(6000, min(m, frame.n))
     sub = sample(m)
+    reps, done = 0, 0.0
     t0 = time.perf_counter()
-    oracle.frame_histogram(sub)
-    dt = time.perf_counter() - t0
+    while reps == 0 or done < 0.5 * target_s:
+        oracle.frame_histogram(sub)
+        reps += 1
+        done = time.perf_counter() - t0
+    what = "the whole frame" if sub.n == frame.n else \
+        f"the first {sub.n} points of the frame (species kept in proportion)"
     return {
-        "value": sub.total_pairs() / dt,
+        "value": sub.total_pairs() * reps / done,
         "unit": "pairs/s",
         "cores": oracle.max_threads(),
         "kind": "oracle",
-        "sample": f"first {sub.n} points of the frame (species kept in proportion), "
-                  f"{sub.total_pairs()} pairs in {dt:.1f} s, binary64",
+        "sample": f"{what}, {reps} run(s), {sub.total_pairs() * reps} pairs in {done:.1f} s, "
+                  "binary64",
     }
 
 
@@ -161,6 +217,8 @@ def main():
     ap.add_argument("--workload", default="ortho100k")
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--trajectory-frames", type=int, default=512,
+                    help="frames of the batched trajectory comparison (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the histogram of a frame runs on a single "
@@ -227,6 +285,8 @@ def main():
         },
         "cpu_baseline": None,
     }
+    if args.trajectory_frames > 0:
+        line["trajectory"] = bench_trajectory(ctx, args.trajectory_frames, max(1, args.steps // 5))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(frame)
     ctx.close()

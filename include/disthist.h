@@ -177,10 +177,59 @@ int dh_pair_t_async(dh_ctx *ctx, dh_stream stream, const double *d_coords, int64
                     int32_t precision, const int32_t *d_pi, const int32_t *d_pj,
                     int64_t n_pairs, double *d_t);
 
+/* ---------------------------------------------------------------------------
+ * Batches: many frames (a trajectory, or frames of unrelated jobs) planned
+ * once and run as one graph of launches. All species pairs of all frames
+ * become work items of persistent pair kernels (one launch per class of
+ * frames with the same minimum-image kind and bin-window mode), so frames of
+ * very different sizes share the GPU without a launch per frame (the paper
+ * launches per coordinate tile and keeps frames independent, Sec. 3.2.2 and
+ * Sec. 3.2.4). Items of large frames are scheduled first.
+ */
+typedef struct dh_batch dh_batch;
+
+typedef struct {
+  const double *d_coords;      /* device [N][3] binary64; read at every launch   */
+  const int64_t *offsets;      /* host [n_species+1]; copied at creation         */
+  int32_t n_species;
+  int32_t box_type;
+  const double *box;           /* host [3][3] or NULL; copied at creation        */
+  double r_max;
+  int32_t n_bins;
+  uint64_t *d_out;             /* device [H][n_bins]; overwritten at every launch */
+  uint64_t *d_out_of_range;    /* device [H] or NULL                              */
+} dh_frame_desc;
+
+/* dh_batch_create flags */
+#define DH_BATCH_GRAPH 1       /* capture the launch sequence in a hipGraph */
+
+/*
+ * Plans a batch of n_frames (1..65535) frames in one precision. The device
+ * pointers of every frame are baked into the plan: each dh_batch_launch reads
+ * the coordinates currently in d_coords and overwrites d_out, so a caller
+ * streams a trajectory by refilling the same buffers between launches.
+ * Frame shapes (species sizes, box, r_max, n_bins) are fixed at creation.
+ * Validation as for dh_histo_async (DH_EINVAL before anything is allocated).
+ * The batch owns its device memory (staged coordinates, work list); it keeps
+ * a reference to ctx, which must outlive it.
+ */
+int dh_batch_create(dh_ctx *ctx, const dh_frame_desc *frames, int32_t n_frames,
+                    int32_t precision, int32_t flags, dh_batch **batch);
+
+/* Enqueues the whole batch on `stream` (a graph replay with DH_BATCH_GRAPH). */
+int dh_batch_launch(dh_batch *batch, dh_stream stream);
+
+/* Work items, pair-kernel launches per run, and pairs per run of a batch. */
+int dh_batch_info(const dh_batch *batch, int64_t *n_items, int32_t *n_launches,
+                  double *total_pairs);
+
+/* Releases a batch (synchronises its device first). */
+void dh_batch_destroy(dh_batch *batch);
+
 /*
  * Kernel timing. When enabled, every histogram launch on ctx records a pair
  * of HIP events on its stream around the pair kernel (the dominant kernel of
- * the path). dh_ctx_profile_read() waits for the recorded launches, returns
+ * the path); batches are not timed this way. dh_ctx_profile_read() waits for the recorded launches, returns
  * the summed kernel time in milliseconds and the number of launches, and
  * resets both. Enabling or disabling also resets them.
  */

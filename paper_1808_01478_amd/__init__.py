@@ -7,7 +7,7 @@ of any name below and raises ImportError if the library is missing (there is
 no CPU fallback).
 """
 _EXPORTS = (
-    "BOX_NONE", "BOX_ORTHO", "BOX_TRICLINIC", "FP32", "FP64", "Context", "DisthistError",
+    "BOX_NONE", "BOX_ORTHO", "BOX_TRICLINIC", "FP32", "FP64", "Batch", "Context", "DisthistError",
     "LIB_PATH", "check_args", "exported_symbols", "histo", "n_hist", "version",
 )
 __all__ = list(_EXPORTS)

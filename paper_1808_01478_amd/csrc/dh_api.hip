@@ -41,6 +41,31 @@ struct dh_ctx {
   size_t prof_used = 0;
 };
 
+struct dh_batch {
+  struct Group {
+    int kind = 0;
+    bool sweep = false;
+    KernelConfig cfg{};
+    int stride = 0, grid = 0;
+    size_t lds = 0;
+    size_t item_begin = 0, item_count = 0;
+  };
+  dh_ctx *ctx = nullptr;
+  int precision = 0;
+  int32_t n_frames = 0;
+  int64_t max_points = 0, max_words = 0;
+  int32_t max_hist = 0;
+  bool any_oor = false;
+  void *d_staged = nullptr;
+  void *d_blob = nullptr;
+  size_t off_frames = 0, off_items = 0, off_counters = 0;
+  std::vector<Group> groups;
+  int64_t n_items = 0;
+  double total_pairs = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
 namespace {
 
 constexpr int32_t kMaxSpecies = 64;
@@ -231,6 +256,37 @@ Launch choose_launch(const dh_ctx *ctx, int precision, const FrameParams &fp,
   return L;
 }
 
+// Base kernel configuration and LDS budget of a precision.
+struct BaseConfig {
+  KernelConfig cfg;
+  size_t tile_bytes;
+  int64_t win_max;  // widest bin window that fits the LDS budget
+};
+
+BaseConfig base_config(const dh_ctx *ctx, int precision) {
+  BaseConfig b;
+  KernelConfig &c = b.cfg;
+  c.threads = 256;
+  c.r = precision == DH_FP64 ? 4 : 8;
+  c.copies = 1;
+  c.tj = precision == DH_FP64 ? 128 : 256;
+  c.wg_per_cu = 0;
+  c.jchunk = c.tj;
+  b.tile_bytes = 2 * static_cast<size_t>(c.tj) * coord_bytes(precision);
+  const size_t budget = std::min<size_t>(ctx->lds_per_block, 160 * 1024) - b.tile_bytes - 256;
+  b.win_max = static_cast<int64_t>(budget / 4 / c.copies) - kDump;
+  return b;
+}
+
+int32_t jchunk_for(const KernelConfig &c, int grid, uint64_t work) {
+  const uint64_t bi = static_cast<uint64_t>(c.threads) * c.r;
+  uint64_t jc = work / (static_cast<uint64_t>(grid) * 8 * bi + 1);
+  jc = (jc + c.tj - 1) / c.tj * c.tj;
+  jc = std::max<uint64_t>(jc, c.tj);
+  jc = std::min<uint64_t>(jc, 64ull * c.tj);
+  return static_cast<int32_t>(jc);
+}
+
 // Work items of one frame, grouped by (histogram, sweep).
 void plan_frame(int32_t frame, const int64_t *off, int32_t k, const Launch &L,
                 std::vector<WorkItem> &items, std::vector<uint64_t> &pairs) {
@@ -376,6 +432,35 @@ std::mutex g_default_mu;
 std::map<int, dh_ctx *> g_default;
 
 }  // namespace
+
+// The launch sequence of a batch: stage, zero, one persistent pair kernel per
+// class of frames, out-of-range counts. Recorded once into a graph, or issued
+// directly.
+static int dh_batch_launch_direct(dh_batch *b, hipStream_t st) {
+  dh_ctx *ctx = b->ctx;
+  char *db = static_cast<char *>(b->d_blob);
+  const FrameParams *d_frames = reinterpret_cast<const FrameParams *>(db + b->off_frames);
+  int32_t *counters = reinterpret_cast<int32_t *>(db + b->off_counters);
+  DH_HIP(ctx, launch_stage_batch(b->precision, d_frames, b->n_frames, b->max_points, st));
+  DH_HIP(ctx, launch_zero_batch(d_frames, b->n_frames, b->max_words, counters,
+                                static_cast<int32_t>(b->groups.size()), st));
+  for (size_t k = 0; k < b->groups.size(); ++k) {
+    const dh_batch::Group &g = b->groups[k];
+    if (g.item_count == 0) continue;
+    PairKernelArgs a;
+    a.frames = d_frames;
+    a.items = reinterpret_cast<const WorkItem *>(db + b->off_items) + g.item_begin;
+    a.counter = counters + k;
+    a.n_items = static_cast<int32_t>(g.item_count);
+    a.copies = g.cfg.copies;
+    a.stride = g.stride;
+    a.tj = g.cfg.tj;
+    const int grid = std::max(1, std::min<int>(g.grid, a.n_items));
+    DH_HIP(ctx, launch_pairs(b->precision, g.kind, g.sweep, g.cfg, a, grid, g.lds, st));
+  }
+  if (b->any_oor) DH_HIP(ctx, launch_oor_batch(d_frames, b->n_frames, b->max_hist, st));
+  return DH_OK;
+}
 
 extern "C" {
 
@@ -587,6 +672,219 @@ int dh_pair_t_async(dh_ctx *ctx, dh_stream stream, const double *d_coords, int64
   DH_HIP(ctx, launch_pair_t(precision, kind, static_cast<const FrameParams *>(ctx->d_blob), d_pi,
                             d_pj, n_pairs, static_cast<int32_t>(n), d_t, st));
   return DH_OK;
+}
+
+int dh_batch_create(dh_ctx *ctx, const dh_frame_desc *frames, int32_t n_frames, int32_t precision,
+                    int32_t flags, dh_batch **out) {
+  if (!ctx || !out) return DH_EINVAL;
+  *out = nullptr;
+  if (!frames || n_frames < 1 || n_frames > 65535)
+    return fail(ctx, DH_EINVAL, "n_frames must be in 1..65535");
+  if (precision != DH_FP32 && precision != DH_FP64) return fail(ctx, DH_EINVAL, "precision");
+  struct FrameInfo {
+    FrameParams fp;
+    bool sweep = false, noclamp_ok = false;
+    int64_t slots = 0;
+    uint64_t pairs = 0;
+    std::vector<int64_t> offsets;
+    std::vector<uint64_t> hist_pairs;
+  };
+  std::vector<FrameInfo> info(n_frames);
+  const BaseConfig base = base_config(ctx, precision);
+  for (int32_t f = 0; f < n_frames; ++f) {
+    const dh_frame_desc &d = frames[f];
+    int rc = check(nullptr, d.offsets, d.n_species, d.box_type, d.box, d.r_max, d.n_bins,
+                   precision);
+    if (rc) return fail(ctx, rc, "frame %d: invalid arguments", f);
+    const int64_t n = d.offsets[d.n_species];
+    if (!d.d_out || (n > 0 && !d.d_coords)) return fail(ctx, DH_EINVAL, "frame %d: null pointer", f);
+    FrameInfo &fi = info[f];
+    int kind = frame_consts(d.box_type, d.box, d.r_max, d.n_bins, fi.fp);
+    if (precision == DH_FP32 && kind == kBoxOrtho && fi.fp.L[0] == fi.fp.L[1] &&
+        fi.fp.L[1] == fi.fp.L[2])
+      fi.fp.box = kind = kBoxCube;
+    fi.offsets.assign(d.offsets, d.offsets + d.n_species + 1);
+    if (d.n_bins <= base.win_max) {
+      fi.fp.win = d.n_bins;
+      fi.fp.n_sweeps = 1;
+    } else {
+      fi.fp.n_sweeps = static_cast<int32_t>((d.n_bins + base.win_max - 1) / base.win_max);
+      fi.fp.win = (d.n_bins + fi.fp.n_sweeps - 1) / fi.fp.n_sweeps;
+      fi.sweep = true;
+    }
+    const double tb = t_bound(fi.fp);
+    const char *env = std::getenv("DH_NOCLAMP");
+    if (!(env && env[0] == '0') && !fi.sweep && tb > 0) {
+      fi.slots = static_cast<int64_t>(tb * (1.0 + 1e-4)) + 2;
+      fi.noclamp_ok = fi.slots <= base.win_max + kDump;
+    }
+    fi.fp.n_points = n;
+    fi.fp.n_hist = d.n_species * (d.n_species + 1) / 2;
+    fi.fp.in = d.d_coords;
+    fi.fp.out = d.d_out;
+    fi.fp.oor = d.d_out_of_range;
+  }
+
+  dh_batch *b = new (std::nothrow) dh_batch;
+  if (!b) return DH_ENOMEM;
+  b->ctx = ctx;
+  b->precision = precision;
+  b->n_frames = n_frames;
+  auto bail = [&](int rc) {
+    dh_batch_destroy(b);
+    return rc;
+  };
+  if (hipSetDevice(ctx->device) != hipSuccess) return bail(fail(ctx, DH_EDEVICE, "hipSetDevice"));
+
+  // classes of frames that share one persistent launch
+  std::map<std::pair<int, int>, std::vector<int32_t>> classes;
+  for (int32_t f = 0; f < n_frames; ++f)
+    classes[{info[f].fp.box, info[f].sweep ? 1 : 0}].push_back(f);
+
+  std::vector<WorkItem> items;
+  std::vector<uint64_t> pairs;
+  std::vector<size_t> pairs_base(n_frames, 0);
+  for (auto &kv : classes) {
+    std::vector<int32_t> &fs = kv.second;
+    dh_batch::Group g;
+    g.kind = kv.first.first;
+    g.sweep = kv.first.second != 0;
+    g.cfg = base.cfg;
+    int64_t stride = 0;
+    uint64_t work = 0;
+    for (int32_t f : fs) {
+      FrameInfo &fi = info[f];
+      int64_t need = fi.fp.win + kDump;
+      if (fi.noclamp_ok) need = std::max<int64_t>(need, fi.slots);
+      stride = std::max(stride, need);
+      for (int s = 0; s < frames[f].n_species; ++s) {
+        const uint64_t a = static_cast<uint64_t>(fi.offsets[s + 1] - fi.offsets[s]);
+        fi.pairs += a * (a > 0 ? a - 1 : 0) / 2;
+        for (int t = s + 1; t < frames[f].n_species; ++t)
+          fi.pairs += a * static_cast<uint64_t>(fi.offsets[t + 1] - fi.offsets[t]);
+      }
+      work += fi.pairs * static_cast<uint64_t>(fi.fp.n_sweeps);
+    }
+    for (int32_t f : fs) info[f].fp.noclamp = (info[f].noclamp_ok && info[f].slots <= stride) ? 1 : 0;
+    g.stride = static_cast<int>(stride);
+    g.lds = base.tile_bytes + static_cast<size_t>(g.cfg.copies) * g.stride * 4;
+    g.grid = ctx->n_cu * pairs_occupancy(precision, g.kind, g.sweep, g.cfg, g.lds);
+    g.cfg.jchunk = jchunk_for(g.cfg, g.grid, work);
+    // large frames first: the tail of the work list is made of small items
+    std::stable_sort(fs.begin(), fs.end(),
+                     [&](int32_t x, int32_t y) { return info[x].pairs > info[y].pairs; });
+    g.item_begin = items.size();
+    Launch L;
+    L.cfg = g.cfg;
+    for (int32_t f : fs) {
+      L.n_sweeps = info[f].fp.n_sweeps;
+      pairs_base[f] = pairs.size();
+      plan_frame(f, info[f].offsets.data(), frames[f].n_species, L, items, pairs);
+    }
+    g.item_count = items.size() - g.item_begin;
+    b->groups.push_back(g);
+    b->total_pairs += static_cast<double>(work);
+  }
+  b->n_items = static_cast<int64_t>(items.size());
+
+  // staged coordinates
+  std::vector<size_t> staged_off(n_frames);
+  size_t staged_bytes = 0;
+  for (int32_t f = 0; f < n_frames; ++f) {
+    staged_off[f] = staged_bytes;
+    staged_bytes += align_up(std::max<int64_t>(1, info[f].fp.n_points) * coord_bytes(precision), 256);
+    b->max_points = std::max(b->max_points, info[f].fp.n_points);
+    b->max_words = std::max(b->max_words, static_cast<int64_t>(info[f].fp.n_hist) * frames[f].n_bins);
+    b->max_hist = std::max(b->max_hist, info[f].fp.n_hist);
+    b->any_oor = b->any_oor || frames[f].d_out_of_range != nullptr;
+  }
+  if (hipMalloc(&b->d_staged, staged_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    b->d_staged = nullptr;
+    return bail(fail(ctx, DH_ENOMEM, "hipMalloc of %zu bytes failed", staged_bytes));
+  }
+  // blob: frames | items | pairs | counters
+  b->off_frames = 0;
+  b->off_items = align_up(n_frames * sizeof(FrameParams), 256);
+  const size_t off_pairs = align_up(b->off_items + items.size() * sizeof(WorkItem), 256);
+  b->off_counters = align_up(off_pairs + pairs.size() * sizeof(uint64_t), 256);
+  const size_t blob_bytes = b->off_counters + align_up(b->groups.size() * sizeof(int32_t), 256);
+  if (hipMalloc(&b->d_blob, blob_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    b->d_blob = nullptr;
+    return bail(fail(ctx, DH_ENOMEM, "hipMalloc of %zu bytes failed", blob_bytes));
+  }
+  char *db = static_cast<char *>(b->d_blob);
+  std::vector<char> host(blob_bytes, 0);
+  for (int32_t f = 0; f < n_frames; ++f) {
+    FrameParams fp = info[f].fp;
+    fp.coords = static_cast<char *>(b->d_staged) + staged_off[f];
+    fp.pairs = reinterpret_cast<const uint64_t *>(db + off_pairs) + pairs_base[f];
+    std::memcpy(host.data() + b->off_frames + f * sizeof(FrameParams), &fp, sizeof fp);
+  }
+  if (!items.empty())
+    std::memcpy(host.data() + b->off_items, items.data(), items.size() * sizeof(WorkItem));
+  if (!pairs.empty())
+    std::memcpy(host.data() + off_pairs, pairs.data(), pairs.size() * sizeof(uint64_t));
+  if (hipMemcpy(b->d_blob, host.data(), blob_bytes, hipMemcpyHostToDevice) != hipSuccess)
+    return bail(fail(ctx, DH_EDEVICE, "hipMemcpy of the batch plan failed"));
+
+  if (flags & DH_BATCH_GRAPH) {
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+      return bail(fail(ctx, DH_EDEVICE, "hipStreamCreate failed"));
+    int rc = DH_OK;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      rc = fail(ctx, DH_EDEVICE, "hipStreamBeginCapture failed");
+    } else {
+      int erc = dh_batch_launch_direct(b, cs);
+      hipGraph_t graph = nullptr;
+      hipError_t e = hipStreamEndCapture(cs, &graph);
+      if (erc) rc = erc;
+      else if (e != hipSuccess) rc = fail(ctx, DH_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+      b->graph = graph;
+      if (!rc && hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess)
+        rc = fail(ctx, DH_EDEVICE, "hipGraphInstantiate failed");
+    }
+    (void)hipStreamDestroy(cs);
+    (void)hipGetLastError();
+    if (rc) return bail(rc);
+  }
+  *out = b;
+  return DH_OK;
+}
+
+int dh_batch_launch(dh_batch *b, dh_stream stream) {
+  if (!b) return DH_EINVAL;
+  dh_ctx *ctx = b->ctx;
+  DH_HIP(ctx, hipSetDevice(ctx->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (b->exec) {
+    DH_HIP(ctx, hipGraphLaunch(b->exec, st));
+    return DH_OK;
+  }
+  return dh_batch_launch_direct(b, st);
+}
+
+int dh_batch_info(const dh_batch *b, int64_t *n_items, int32_t *n_launches, double *total_pairs) {
+  if (!b) return DH_EINVAL;
+  if (n_items) *n_items = b->n_items;
+  if (n_launches) *n_launches = static_cast<int32_t>(b->groups.size());
+  if (total_pairs) *total_pairs = b->total_pairs;
+  return DH_OK;
+}
+
+void dh_batch_destroy(dh_batch *b) {
+  if (!b) return;
+  if (b->ctx && hipSetDevice(b->ctx->device) == hipSuccess) {
+    (void)hipDeviceSynchronize();
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->d_staged) (void)hipFree(b->d_staged);
+    if (b->d_blob) (void)hipFree(b->d_blob);
+  }
+  (void)hipGetLastError();
+  delete b;
 }
 
 int dh_ctx_profile(dh_ctx *ctx, int32_t enable) {

@@ -39,6 +39,12 @@ constexpr int kDump = 64;  // per-lane discard slots after the bin window
 struct FrameParams {
   const void *coords;  // staged float4 / double4 [N] (device)
   uint64_t *out;       // [H][n_bins] (device)
+  const double *in;    // caller's binary64 [N][3] (device)
+  uint64_t *oor;       // caller's out-of-range counts [H] or null (device)
+  const uint64_t *pairs;  // pairs per histogram [H] (device)
+  int64_t n_points;
+  int32_t n_hist;
+  int32_t pad0_;
   int32_t n_bins;
   int32_t box;         // BoxKind
   int32_t win;         // bin window of one sweep (<= n_bins)
@@ -90,6 +96,13 @@ hipError_t launch_pairs(int precision, int box_kind, bool sweep, const KernelCon
                         const PairKernelArgs &args, int grid, size_t lds_bytes, hipStream_t st);
 hipError_t launch_oor(const uint64_t *hist, int32_t n_hist, int32_t n_bins, const uint64_t *pairs,
                       uint64_t *oor, hipStream_t st);
+// batched staging / zeroing / out-of-range over a device table of frames
+hipError_t launch_stage_batch(int precision, const FrameParams *d_frames, int32_t n_frames,
+                              int64_t max_points, hipStream_t st);
+hipError_t launch_zero_batch(const FrameParams *d_frames, int32_t n_frames, int64_t max_words,
+                             int32_t *counters, int32_t n_counters, hipStream_t st);
+hipError_t launch_oor_batch(const FrameParams *d_frames, int32_t n_frames, int32_t max_hist,
+                            hipStream_t st);
 hipError_t launch_pair_t(int precision, int box_kind, const FrameParams *d_fp, const int32_t *pi,
                          const int32_t *pj, int64_t n_pairs, int32_t n, double *t,
                          hipStream_t st);

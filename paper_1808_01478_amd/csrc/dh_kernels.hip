@@ -18,6 +18,8 @@
 // (Sec. 3.1: u32 private histograms flushed into a u64 global one).
 #include "dh_internal.h"
 
+#include <algorithm>
+
 namespace dh {
 namespace {
 
@@ -198,35 +200,91 @@ __device__ __forceinline__ float fixfrac(double f) {
   return __uint_as_float(static_cast<uint32_t>(u));
 }
 
+// One staged binary32 point (see FrameParams for the formats).
+template <int BOX>
+__device__ __forceinline__ float4 stage_point32(double x, double y, double z,
+                                                const FrameParams &p) {
+  if constexpr (BOX == kBoxNone) {
+    return make_float4(static_cast<float>(x * p.s), static_cast<float>(y * p.s),
+                       static_cast<float>(z * p.s), 0.f);
+  } else if constexpr (BOX == kBoxOrtho) {
+    return make_float4(fixfrac(x * p.iL[0]), fixfrac(y * p.iL[1]), fixfrac(z * p.iL[2]), 0.f);
+  } else {
+    const double fa = fma(z, p.h13, fma(y, p.h12, x * p.h11));
+    const double fb = fma(z, p.h23, y * p.h22);
+    const double fc = z * p.h33;
+    return make_float4(fixfrac(fa), fixfrac(fb), fixfrac(fc), 0.f);
+  }
+}
+
 template <int BOX>
 __global__ void stage32_kernel(const double *__restrict__ in, float4 *__restrict__ out, int64_t n,
                                FrameParams p) {
   const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += step)
+    out[i] = stage_point32<BOX>(in[3 * i], in[3 * i + 1], in[3 * i + 2], p);
+}
+
+// Batched staging: blockIdx.y selects the frame.
+template <int PREC>
+__global__ void stage_batch_kernel(const FrameParams *__restrict__ frames) {
+  const FrameParams &p = frames[blockIdx.y];
+  const int64_t n = p.n_points;
+  const double *__restrict__ in = p.in;
+  const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += step) {
     const double x = in[3 * i], y = in[3 * i + 1], z = in[3 * i + 2];
-    float4 v;
-    if constexpr (BOX == kBoxNone) {
-      v = make_float4(static_cast<float>(x * p.s), static_cast<float>(y * p.s),
-                      static_cast<float>(z * p.s), 0.f);
-    } else if constexpr (BOX == kBoxOrtho) {
-      v = make_float4(fixfrac(x * p.iL[0]), fixfrac(y * p.iL[1]), fixfrac(z * p.iL[2]), 0.f);
+    if constexpr (PREC == 1) {
+      static_cast<double4 *>(const_cast<void *>(p.coords))[i] = make_double4(x, y, z, 0.0);
     } else {
-      const double fa = fma(z, p.h13, fma(y, p.h12, x * p.h11));
-      const double fb = fma(z, p.h23, y * p.h22);
-      const double fc = z * p.h33;
-      v = make_float4(fixfrac(fa), fixfrac(fb), fixfrac(fc), 0.f);
+      float4 v;
+      if (p.box == kBoxNone)
+        v = stage_point32<kBoxNone>(x, y, z, p);
+      else if (p.box == kBoxOrtho || p.box == kBoxCube)
+        v = stage_point32<kBoxOrtho>(x, y, z, p);
+      else
+        v = stage_point32<kBoxTric>(x, y, z, p);
+      static_cast<float4 *>(const_cast<void *>(p.coords))[i] = v;
     }
-    out[i] = v;
   }
+}
+
+// Batched zeroing of every frame's histograms, plus the work counters.
+__global__ void zero_batch_kernel(const FrameParams *__restrict__ frames, int32_t *counters,
+                                  int32_t n_counters) {
+  const FrameParams &p = frames[blockIdx.y];
+  const int64_t n = static_cast<int64_t>(p.n_hist) * p.n_bins;
+  const int64_t i0 = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (blockIdx.y == 0 && i0 < n_counters) counters[i0] = 0;
+  const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = i0; i < n; i += step) p.out[i] = 0ull;
+}
+
+// Batched out-of-range counts: blockIdx.x = histogram, blockIdx.y = frame.
+__global__ void oor_batch_kernel(const FrameParams *__restrict__ frames) {
+  __shared__ unsigned long long part[256];
+  const FrameParams &p = frames[blockIdx.y];
+  const int h = blockIdx.x;
+  if (p.oor == nullptr || h >= p.n_hist) return;
+  unsigned long long v = 0;
+  for (int b = threadIdx.x; b < p.n_bins; b += blockDim.x)
+    v += p.out[static_cast<size_t>(h) * p.n_bins + b];
+  part[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) part[threadIdx.x] += part[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) p.oor[h] = p.pairs[h] - part[0];
 }
 
 // --------------------------------------------------------------------------
 // Pair kernel
 // --------------------------------------------------------------------------
 
-// Adds the LDS copies of bins [0, count) into out[] and clears the window
-// including its discard slots.
+// Adds the LDS copies of bins [0, count) into out[] and clears every slot.
 __device__ __forceinline__ void flush_hist(uint32_t *hist, const PairKernelArgs &a,
                                            const FrameParams *F, int hist_idx, int sweep) {
   const int n_bins = uni(F->n_bins);
@@ -234,7 +292,9 @@ __device__ __forceinline__ void flush_hist(uint32_t *hist, const PairKernelArgs 
   const int b_lo = sweep * win;
   const int count = min(win, n_bins - b_lo);
   uint64_t *out = F->out + static_cast<size_t>(hist_idx) * n_bins + b_lo;
-  const int clear = min(win + kDump, a.stride);
+  // the whole stride: slots past the window may hold counts of out-of-range
+  // pairs of unclamped items, and the next frame may use a wider window
+  const int clear = a.stride;
   for (int b = threadIdx.x; b < clear; b += blockDim.x) {
     uint64_t v = 0;
     for (int c = 0; c < a.copies; ++c) {
@@ -539,6 +599,36 @@ hipError_t launch_oor(const uint64_t *hist, int32_t n_hist, int32_t n_bins, cons
                       uint64_t *oor, hipStream_t st) {
   if (n_hist <= 0) return hipSuccess;
   oor_kernel<<<n_hist, 256, 0, st>>>(hist, n_bins, pairs, oor);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage_batch(int precision, const FrameParams *d_frames, int32_t n_frames,
+                              int64_t max_points, hipStream_t st) {
+  if (n_frames <= 0 || max_points <= 0) return hipSuccess;
+  const int threads = 256;
+  int gx = static_cast<int>(std::min<int64_t>((max_points + threads - 1) / threads, 64));
+  dim3 grid(gx, n_frames);
+  if (precision == 1)
+    stage_batch_kernel<1><<<grid, threads, 0, st>>>(d_frames);
+  else
+    stage_batch_kernel<0><<<grid, threads, 0, st>>>(d_frames);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_batch(const FrameParams *d_frames, int32_t n_frames, int64_t max_words,
+                             int32_t *counters, int32_t n_counters, hipStream_t st) {
+  if (n_frames <= 0) return hipSuccess;
+  const int threads = 256;
+  int64_t need = std::max<int64_t>(max_words, n_counters);
+  int gx = static_cast<int>(std::min<int64_t>(std::max<int64_t>((need + threads - 1) / threads, 1), 64));
+  zero_batch_kernel<<<dim3(gx, n_frames), threads, 0, st>>>(d_frames, counters, n_counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_oor_batch(const FrameParams *d_frames, int32_t n_frames, int32_t max_hist,
+                            hipStream_t st) {
+  if (n_frames <= 0 || max_hist <= 0) return hipSuccess;
+  oor_batch_kernel<<<dim3(max_hist, n_frames), 256, 0, st>>>(d_frames);
   return hipGetLastError();
 }
 

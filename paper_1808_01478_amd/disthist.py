@@ -33,9 +33,24 @@ SIGNATURES = {
                        ctypes.c_int),
     "dh_pair_t_async": ([_vp, _vp, _vp, _i64, _i32, _vp, _f64, _i32, _i32, _vp, _vp, _i64, _vp],
                         ctypes.c_int),
+    "dh_batch_create": ([_vp, _vp, _i32, _i32, _i32, ctypes.POINTER(_vp)], ctypes.c_int),
+    "dh_batch_launch": ([_vp, _vp], ctypes.c_int),
+    "dh_batch_info": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32), ctypes.POINTER(_f64)],
+                      ctypes.c_int),
+    "dh_batch_destroy": ([_vp], None),
     "dh_ctx_profile": ([_vp, _i32], ctypes.c_int),
     "dh_ctx_profile_read": ([_vp, ctypes.POINTER(_f64), ctypes.POINTER(_i64)], ctypes.c_int),
 }
+
+
+class FrameDesc(ctypes.Structure):
+    """dh_frame_desc."""
+    _fields_ = [("d_coords", _vp), ("offsets", _vp), ("n_species", _i32), ("box_type", _i32),
+                ("box", _vp), ("r_max", _f64), ("n_bins", _i32), ("d_out", _vp),
+                ("d_out_of_range", _vp)]
+
+
+BATCH_GRAPH = 1
 
 
 def _load() -> ctypes.CDLL:
@@ -193,6 +208,59 @@ class Context:
                                    ctypes.c_void_p(d_pj.data_ptr()), int(d_pi.numel()),
                                    ctypes.c_void_p(d_t.data_ptr())),
                self.handle)
+
+
+class Batch:
+    """dh_batch: many frames planned once and run as one graph of launches.
+
+    ``frames`` is a sequence of dicts with keys d_coords (torch float64 [N,3]
+    on the device), offsets, box_type, box, r_max, n_bins, d_out (torch
+    int64/uint64 [H, n_bins]) and optionally d_out_of_range ([H]). The device
+    tensors must stay alive and at the same address for the batch's life; each
+    launch reads their current contents."""
+
+    def __init__(self, ctx: Context, frames, precision: int, graph: bool = True):
+        self.ctx = ctx
+        self._keep = []
+        descs = (FrameDesc * len(frames))()
+        for k, f in enumerate(frames):
+            o = _offsets(f["offsets"])
+            b = _host_box(f.get("box"))
+            self._keep += [o, b, f["d_coords"], f["d_out"], f.get("d_out_of_range")]
+            descs[k].d_coords = f["d_coords"].data_ptr()
+            descs[k].offsets = o.ctypes.data
+            descs[k].n_species = len(o) - 1
+            descs[k].box_type = int(f["box_type"])
+            descs[k].box = None if b is None else b.ctypes.data
+            descs[k].r_max = float(f["r_max"])
+            descs[k].n_bins = int(f["n_bins"])
+            descs[k].d_out = f["d_out"].data_ptr()
+            oor = f.get("d_out_of_range")
+            descs[k].d_out_of_range = None if oor is None else oor.data_ptr()
+        h = ctypes.c_void_p()
+        _check(LIB.dh_batch_create(ctx.handle, ctypes.cast(descs, _vp), len(frames),
+                                   int(precision), BATCH_GRAPH if graph else 0,
+                                   ctypes.byref(h)), ctx.handle)
+        self.handle = h
+
+    def launch(self, stream=None) -> None:
+        _check(LIB.dh_batch_launch(self.handle, _stream_handle(stream)), self.ctx.handle)
+
+    def info(self):
+        n, l, p = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_double()
+        _check(LIB.dh_batch_info(self.handle, ctypes.byref(n), ctypes.byref(l), ctypes.byref(p)))
+        return {"items": int(n.value), "launches": int(l.value), "pairs": float(p.value)}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            LIB.dh_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def exported_symbols() -> Sequence[str]:

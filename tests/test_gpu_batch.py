@@ -1,0 +1,149 @@
+"""Batched launches (one plan, one graph) against per-frame launches and the
+oracle: every frame of a batch must be bit-identical to its own
+dh_histo_async result (the same arithmetic; integer sums do not depend on
+order), and binary64 frames identical to the oracle. Graph replays are
+checked one by one, with new coordinates and unrelated eager work between
+them."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import run_gpu
+
+pytestmark = pytest.mark.gpu
+
+SKEW = np.array([[10.0, 0, 0], [3.0, 9.5, 0], [-2.0, 3.5, 9.0]])
+
+
+def mixed_frames():
+    w = workloads.min_width(SKEW)
+    fr = [
+        workloads.random_frame(401, [3000, 1200], workloads.BOX_ORTHO, n_bins=900),
+        workloads.random_frame(402, [2500], workloads.BOX_ORTHO,
+                               box=workloads.ortho_box(12.0, 12.0, 12.0), r_max=6.0, n_bins=4096),
+        workloads.random_frame(403, [1500, 700, 300], workloads.BOX_TRICLINIC, box=SKEW,
+                               r_max=0.45 * w, n_bins=512),
+        workloads.random_frame(404, [1100, 900], workloads.BOX_TRICLINIC, box=SKEW,
+                               r_max=0.8 * w, n_bins=300),
+        workloads.random_frame(405, [2200, 5], workloads.BOX_NONE, r_max=9.0, n_bins=777),
+        workloads.random_frame(406, [1800, 1000], workloads.BOX_ORTHO, n_bins=60_000),
+        workloads.random_frame(407, [1], workloads.BOX_NONE, n_bins=16),
+        workloads.random_frame(408, [0, 700], workloads.BOX_ORTHO, n_bins=128),
+        workloads.trajectory_frame(3).subset([3000] * 4),
+        workloads.tiny(n=2048),
+    ]
+    return fr
+
+
+def _alloc(frames):
+    import torch
+    dev = torch.device("cuda")
+    out = []
+    for f in frames:
+        out.append({
+            "d_coords": torch.from_numpy(np.ascontiguousarray(f.coords)).to(dev),
+            "offsets": f.offsets, "box_type": f.box_type, "box": f.box, "r_max": f.r_max,
+            "n_bins": f.n_bins,
+            "d_out": torch.full((f.n_hist, f.n_bins), -1, dtype=torch.int64, device=dev),
+            "d_out_of_range": torch.full((f.n_hist,), -1, dtype=torch.int64, device=dev),
+        })
+    return out
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1808_01478_amd as dh
+    c = dh.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_matches_per_frame(ctx, precision, graph):
+    import torch
+    import paper_1808_01478_amd as dh
+    frames = mixed_frames()
+    print(f"\n[case] batch prec={precision} graph={graph} frames={len(frames)}", flush=True)
+    bufs = _alloc(frames)
+    batch = dh.Batch(ctx, bufs, precision, graph=graph)
+    info = batch.info()
+    assert info["items"] > 0 and info["launches"] >= 4
+    for rep in range(3):
+        # unrelated eager work on the same stream between replays
+        junk = torch.ones(1 << 20, device="cuda").cumsum(0)
+        for b in bufs:
+            b["d_out"].fill_(-1)
+            b["d_out_of_range"].fill_(-1)
+        batch.launch()
+        torch.cuda.synchronize()
+        assert float(junk[-1]) == float(1 << 20)
+        for f, b in zip(frames, bufs):
+            ref_h, ref_o = run_gpu(ctx, f, precision)
+            got_h = b["d_out"].cpu().numpy().view(np.uint64)
+            got_o = b["d_out_of_range"].cpu().numpy().view(np.uint64)
+            assert np.array_equal(got_h, ref_h), f"replay {rep}: {f.name} differs from per-frame"
+            assert np.array_equal(got_o, ref_o), f"replay {rep}: {f.name} out-of-range differs"
+    if precision == 1:
+        for f, b in zip(frames, bufs):
+            ref = oracle.frame_histogram(f)
+            assert np.array_equal(b["d_out"].cpu().numpy().view(np.uint64), ref.hist), f.name
+    batch.close()
+
+
+def test_graph_replay_follows_new_coordinates(ctx):
+    """A trajectory: refill the same device buffers, replay, compare."""
+    import torch
+    import paper_1808_01478_amd as dh
+    shape_frames = [workloads.trajectory_frame(f) for f in (11, 12)]
+    frames = [f.subset([2500] * f.n_species) for f in shape_frames]
+    bufs = _alloc(frames)
+    batch = dh.Batch(ctx, bufs, 0, graph=True)
+    rng = np.random.Generator(np.random.PCG64(99))
+    for step in range(3):
+        new = []
+        for f, b in zip(frames, bufs):
+            edge = np.diag(f.box)
+            x = rng.uniform(0, 1, size=f.coords.shape) * edge
+            nf = workloads.Frame(np.ascontiguousarray(x), f.offsets, f.box_type, f.box, f.r_max,
+                                 f.n_bins, f"{f.name}-step{step}")
+            b["d_coords"].copy_(torch.from_numpy(nf.coords))
+            new.append(nf)
+        batch.launch()
+        torch.cuda.synchronize()
+        for nf, b in zip(new, bufs):
+            ref_h, _ = run_gpu(ctx, nf, 0)
+            assert np.array_equal(b["d_out"].cpu().numpy().view(np.uint64), ref_h), nf.name
+    batch.close()
+
+
+def test_trajectory_subset_batched(ctx):
+    """32 frames of the trajectory workload at full size: batched binary64
+    equals the oracle for two of them and per-frame launches for all."""
+    import paper_1808_01478_amd as dh
+    import torch
+    frames = [workloads.trajectory_frame(f) for f in range(32)]
+    bufs = _alloc(frames)
+    for prec in (0, 1):
+        batch = dh.Batch(ctx, bufs, prec, graph=True)
+        batch.launch()
+        torch.cuda.synchronize()
+        for f, b in zip(frames, bufs):
+            ref_h, _ = run_gpu(ctx, f, prec)
+            assert np.array_equal(b["d_out"].cpu().numpy().view(np.uint64), ref_h), f.name
+        if prec == 1:
+            for k in (0, 5):
+                ref = oracle.frame_histogram(frames[k])
+                assert np.array_equal(bufs[k]["d_out"].cpu().numpy().view(np.uint64), ref.hist)
+        batch.close()
+
+
+def test_batch_rejects_bad_frame(ctx):
+    import paper_1808_01478_amd as dh
+    frames = mixed_frames()[:2]
+    bufs = _alloc(frames)
+    bufs[1]["r_max"] = -1.0
+    with pytest.raises(dh.DisthistError) as e:
+        dh.Batch(ctx, bufs, 0)
+    assert e.value.code == -1 and "frame 1" in str(e.value)
