@@ -217,6 +217,8 @@ def main():
     ap.add_argument("--workload", default="ortho100k")
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="built-in launch shape instead of tuning on the first warm-up call")
     ap.add_argument("--trajectory-frames", type=int, default=512,
                     help="frames of the batched trajectory comparison (0 = skip)")
     args = ap.parse_args()
@@ -232,9 +234,13 @@ def main():
     kind = box_kind(frame)
     pairs = frame.total_pairs()
     ctx = dh.Context(0)
-    r32 = time_path(ctx, frame, dh.FP32, args.steps, args.warmup)
+    if not args.no_tune:
+        ctx.set_tuning(dh.TUNE_ON)     # the first warm-up call of each precision tunes
+    r32 = time_path(ctx, frame, dh.FP32, args.steps, max(1, args.warmup))
+    shape32 = ctx.last_config()
     fp64_steps = args.fp64_steps if args.fp64_steps is not None else max(1, args.steps // 2)
     r64 = time_path(ctx, frame, dh.FP64, fp64_steps, 1)
+    shape64 = ctx.last_config()
 
     value = pairs * args.steps / r32["wall_s"]
     flops = pairs * FLOPS_PER_PAIR[kind]
@@ -262,6 +268,8 @@ def main():
             "r_max": frame.r_max,
             "pairs_per_step": pairs,
             "flops_per_pair": FLOPS_PER_PAIR[kind],
+            "launch_shape": shape32,
+            "tuned": not args.no_tune,
         },
         "latency_ms": {"p50": r32["step_ms_p50"], "p99": r32["step_ms_p99"]},
         "fp64": {
@@ -271,6 +279,7 @@ def main():
             "ms_per_step": r64["wall_s"] * 1e3 / fp64_steps,
             "kernel_ms_avg": r64["kernel_ms_avg"],
             "roofline_frac": ach64 / PEAK_TFLOPS[1],
+            "launch_shape": shape64,
             "latency_ms": {"p50": r64["step_ms_p50"], "p99": r64["step_ms_p99"]},
         },
         "roofline": {

@@ -226,6 +226,41 @@ int dh_batch_info(const dh_batch *batch, int64_t *n_items, int32_t *n_launches,
 /* Releases a batch (synchronises its device first). */
 void dh_batch_destroy(dh_batch *batch);
 
+/* ---------------------------------------------------------------------------
+ * Launch tuning. The launch shape of a frame (i-particles per lane, LDS
+ * sub-histogram copies, j-tile length, unclamped interior blocks, workgroups
+ * per CU, work items per workgroup) changes speed only: every shape gives
+ * the same counts (the paper picks its block size and kernel by fixed
+ * heuristics, Sec. 3.2.4 and Sec. 4.2).
+ *
+ *   DH_TUNE_OFF     built-in defaults
+ *   DH_TUNE_CACHED  use cached shapes, never measure
+ *   DH_TUNE_ON      on a cache miss, time candidate shapes on the call's own
+ *                   frame (the call blocks until done), cache the fastest
+ * Shapes are cached per bucket (architecture, precision, minimum-image
+ * kind, ceil(log2 n_bins), ceil(log2 N), species up to 4). With a
+ * cache_path, existing entries are loaded now and new ones saved as JSON.
+ * Environment defaults for new contexts: DH_TUNE (mode), DH_TUNE_CACHE.
+ */
+#define DH_TUNE_OFF 0
+#define DH_TUNE_CACHED 1
+#define DH_TUNE_ON 2
+int dh_ctx_set_tuning(dh_ctx *ctx, int32_t mode, const char *cache_path);
+
+/*
+ * Forces a launch shape for every later call on ctx (NULL restores tuning):
+ * knobs[6] = {r (4|8), copies (1|2|4), tj (128|256), noclamp (0|1),
+ * occ_cap (0..16, 0 = as many as fit), items_per_wg (1..64)}.
+ * Invalid knob values give DH_EINVAL.
+ */
+int dh_ctx_set_config(dh_ctx *ctx, const int32_t *knobs);
+
+/*
+ * The shape of the last single-frame launch on ctx: out[10] = the six knobs,
+ * then grid size, LDS bytes per workgroup, bin-window sweeps, work items.
+ */
+int dh_ctx_last_config(const dh_ctx *ctx, int32_t *out);
+
 /*
  * Kernel timing. When enabled, every histogram launch on ctx records a pair
  * of HIP events on its stream around the pair kernel (the dominant kernel of

@@ -4,6 +4,9 @@
 #include "dh_internal.h"
 
 #include <algorithm>
+#include <array>
+#include <fstream>
+#include <sstream>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -35,6 +38,14 @@ struct dh_ctx {
   size_t out_cap = 0;
   std::string last_error;
   std::mutex mu;
+  std::string arch;
+  // launch tuning (see dh_ctx_set_tuning)
+  int tune_mode = 0;
+  std::string tune_path;
+  std::map<std::string, std::array<int32_t, 6>> tune_cache;
+  bool forced = false;
+  std::array<int32_t, 6> forced_knobs{};
+  std::array<int32_t, 10> last_config{};
   // kernel timing: event pairs recorded around pair-kernel launches
   bool profile = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
@@ -207,24 +218,94 @@ struct Launch {
 size_t coord_bytes(int precision) { return precision == DH_FP64 ? 32 : 16; }
 
 // Launch shape for one frame (heuristic defaults).
-Launch choose_launch(const dh_ctx *ctx, int precision, const FrameParams &fp,
-                     uint64_t total_pairs) {
-  Launch L;
-  KernelConfig &c = L.cfg;
-  const int32_t n_bins = fp.n_bins;
+// Launch knobs. Every choice yields identical counts; they only change speed.
+struct Knobs {
+  int32_t r = 8;             // i-particles per lane: 4 or 8
+  int32_t copies = 1;        // interleaved LDS copies: 1, 2 or 4
+  int32_t tj = 256;          // j-tile length: 128 or 256
+  int32_t noclamp = 1;       // allow unclamped interior blocks
+  int32_t occ_cap = 0;       // workgroups per CU at most (0: as many as fit)
+  int32_t items_per_wg = 8;  // work items per workgroup (sets the j-chunk)
+  std::array<int32_t, 6> pack() const { return {r, copies, tj, noclamp, occ_cap, items_per_wg}; }
+  static Knobs unpack(const std::array<int32_t, 6> &v) {
+    Knobs k;
+    k.r = v[0]; k.copies = v[1]; k.tj = v[2]; k.noclamp = v[3]; k.occ_cap = v[4];
+    k.items_per_wg = v[5];
+    return k;
+  }
+  bool valid() const {
+    return (r == 4 || r == 8) && (copies == 1 || copies == 2 || copies == 4) &&
+           (tj == 128 || tj == 256) && (noclamp == 0 || noclamp == 1) && occ_cap >= 0 &&
+           occ_cap <= 16 && items_per_wg >= 1 && items_per_wg <= 64;
+  }
+};
+
+Knobs default_knobs(int precision) {
+  Knobs k;
+  if (precision == DH_FP64) {
+    k.r = 4;
+    k.tj = 128;
+  }
+  return k;
+}
+
+// Base kernel configuration and LDS budget of a precision and knob set.
+struct BaseConfig {
+  KernelConfig cfg;
+  size_t tile_bytes;
+  int64_t win_max;  // widest bin window that fits the LDS budget
+  int occ_cap;
+  int items_per_wg;
+  bool noclamp;
+};
+
+BaseConfig base_config(const dh_ctx *ctx, int precision, const Knobs &k) {
+  BaseConfig b;
+  KernelConfig &c = b.cfg;
   c.threads = 256;
-  c.r = precision == DH_FP64 ? 4 : 8;
-  c.copies = 1;
-  c.tj = precision == DH_FP64 ? 128 : 256;
-  c.wg_per_cu = 0;
-  const size_t tile_bytes = 2 * static_cast<size_t>(c.tj) * coord_bytes(precision);
-  const size_t budget = std::min<size_t>(ctx->lds_per_block, 160 * 1024) - tile_bytes - 256;
-  const int64_t win_max = static_cast<int64_t>(budget / 4 / c.copies) - kDump;
-  if (n_bins <= win_max) {
+  c.r = k.r;
+  c.copies = k.copies;
+  c.tj = k.tj;
+  c.wg_per_cu = k.occ_cap;
+  c.jchunk = c.tj;
+  b.tile_bytes = 2 * static_cast<size_t>(c.tj) * coord_bytes(precision);
+  const size_t budget = std::min<size_t>(ctx->lds_per_block, 160 * 1024) - b.tile_bytes - 256;
+  b.win_max = static_cast<int64_t>(budget / 4 / c.copies) - kDump;
+  b.occ_cap = k.occ_cap;
+  b.items_per_wg = k.items_per_wg;
+  const char *env = std::getenv("DH_NOCLAMP");
+  b.noclamp = k.noclamp && !(env && env[0] == '0');
+  return b;
+}
+
+int32_t jchunk_for(const KernelConfig &c, int grid, uint64_t work, int items_per_wg) {
+  const uint64_t bi = static_cast<uint64_t>(c.threads) * c.r;
+  uint64_t jc = work / (static_cast<uint64_t>(grid) * items_per_wg * bi + 1);
+  jc = (jc + c.tj - 1) / c.tj * c.tj;
+  jc = std::max<uint64_t>(jc, c.tj);
+  jc = std::min<uint64_t>(jc, 64ull * c.tj);
+  return static_cast<int32_t>(jc);
+}
+
+int grid_for_config(const dh_ctx *ctx, int precision, int kind, bool sweep, const BaseConfig &b,
+                    size_t lds) {
+  int occ = pairs_occupancy(precision, kind, sweep, b.cfg, lds);
+  if (b.occ_cap > 0) occ = std::min(occ, b.occ_cap);
+  return ctx->n_cu * std::max(1, occ);
+}
+
+// Launch shape for one frame.
+Launch choose_launch(const dh_ctx *ctx, int precision, const FrameParams &fp,
+                     uint64_t total_pairs, const Knobs &k) {
+  Launch L;
+  const BaseConfig b = base_config(ctx, precision, k);
+  L.cfg = b.cfg;
+  const int32_t n_bins = fp.n_bins;
+  if (n_bins <= b.win_max) {
     L.n_sweeps = 1;
     L.win = n_bins;
   } else {
-    L.n_sweeps = static_cast<int>((n_bins + win_max - 1) / win_max);
+    L.n_sweeps = static_cast<int>((n_bins + b.win_max - 1) / b.win_max);
     L.win = (n_bins + L.n_sweeps - 1) / L.n_sweeps;
   }
   L.stride = L.win + kDump;
@@ -232,59 +313,19 @@ Launch choose_launch(const dh_ctx *ctx, int precision, const FrameParams &fp,
   // stride: slots = floor(bound * (1 + 1e-4)) + 2 covers the rounding of the
   // minimum image and of the distance.
   L.noclamp = false;
-  const char *env = std::getenv("DH_NOCLAMP");
-  const bool allow = !(env && env[0] == '0');
   const double tb = t_bound(fp);
-  if (allow && L.n_sweeps == 1 && tb > 0) {
+  if (b.noclamp && L.n_sweeps == 1 && tb > 0) {
     const int64_t slots = static_cast<int64_t>(tb * (1.0 + 1e-4)) + 2;
-    if (slots <= win_max + kDump) {
+    if (slots <= b.win_max + kDump) {
       L.noclamp = true;
       L.stride = static_cast<int>(std::max<int64_t>(L.stride, slots));
     }
   }
-  L.lds = tile_bytes + static_cast<size_t>(c.copies) * L.stride * 4;
-  const int occ = pairs_occupancy(precision, fp.box, L.n_sweeps > 1, c, L.lds);
-  L.grid = ctx->n_cu * occ;
-  // j-chunk: about 8 items per workgroup over the whole (swept) job
-  const uint64_t bi = static_cast<uint64_t>(c.threads) * c.r;
-  const uint64_t work = total_pairs * static_cast<uint64_t>(L.n_sweeps);
-  uint64_t jc = work / (static_cast<uint64_t>(L.grid) * 8 * bi + 1);
-  jc = (jc + c.tj - 1) / c.tj * c.tj;
-  jc = std::max<uint64_t>(jc, c.tj);
-  jc = std::min<uint64_t>(jc, 64ull * c.tj);
-  c.jchunk = static_cast<int32_t>(jc);
+  L.lds = b.tile_bytes + static_cast<size_t>(L.cfg.copies) * L.stride * 4;
+  L.grid = grid_for_config(ctx, precision, fp.box, L.n_sweeps > 1, b, L.lds);
+  L.cfg.jchunk = jchunk_for(L.cfg, L.grid, total_pairs * static_cast<uint64_t>(L.n_sweeps),
+                            b.items_per_wg);
   return L;
-}
-
-// Base kernel configuration and LDS budget of a precision.
-struct BaseConfig {
-  KernelConfig cfg;
-  size_t tile_bytes;
-  int64_t win_max;  // widest bin window that fits the LDS budget
-};
-
-BaseConfig base_config(const dh_ctx *ctx, int precision) {
-  BaseConfig b;
-  KernelConfig &c = b.cfg;
-  c.threads = 256;
-  c.r = precision == DH_FP64 ? 4 : 8;
-  c.copies = 1;
-  c.tj = precision == DH_FP64 ? 128 : 256;
-  c.wg_per_cu = 0;
-  c.jchunk = c.tj;
-  b.tile_bytes = 2 * static_cast<size_t>(c.tj) * coord_bytes(precision);
-  const size_t budget = std::min<size_t>(ctx->lds_per_block, 160 * 1024) - b.tile_bytes - 256;
-  b.win_max = static_cast<int64_t>(budget / 4 / c.copies) - kDump;
-  return b;
-}
-
-int32_t jchunk_for(const KernelConfig &c, int grid, uint64_t work) {
-  const uint64_t bi = static_cast<uint64_t>(c.threads) * c.r;
-  uint64_t jc = work / (static_cast<uint64_t>(grid) * 8 * bi + 1);
-  jc = (jc + c.tj - 1) / c.tj * c.tj;
-  jc = std::max<uint64_t>(jc, c.tj);
-  jc = std::min<uint64_t>(jc, 64ull * c.tj);
-  return static_cast<int32_t>(jc);
 }
 
 // Work items of one frame, grouped by (histogram, sweep).
@@ -413,6 +454,8 @@ int upload_blob(dh_ctx *ctx, hipStream_t st, const BlobLayout &lay,
   return DH_OK;
 }
 
+int load_tune_cache(dh_ctx *ctx);
+
 int ctx_init(dh_ctx *ctx, int32_t device) {
   int n = 0;
   DH_HIP(ctx, hipGetDeviceCount(&n));
@@ -422,10 +465,218 @@ int ctx_init(dh_ctx *ctx, int32_t device) {
   hipDeviceProp_t prop;
   DH_HIP(ctx, hipGetDeviceProperties(&prop, device));
   ctx->n_cu = prop.multiProcessorCount;
+  ctx->arch = prop.gcnArchName;
+  ctx->arch = ctx->arch.substr(0, ctx->arch.find(':'));
+  if (const char *m = std::getenv("DH_TUNE")) ctx->tune_mode = std::atoi(m);
+  if (ctx->tune_mode < DH_TUNE_OFF || ctx->tune_mode > DH_TUNE_ON) ctx->tune_mode = DH_TUNE_OFF;
+  if (const char *pth = std::getenv("DH_TUNE_CACHE")) {
+    ctx->tune_path = pth;
+    int rc = load_tune_cache(ctx);
+    if (rc) return rc;
+  }
   ctx->lds_per_block = prop.sharedMemPerBlock;
   DH_HIP(ctx, hipEventCreateWithFlags(&ctx->blob_evt, hipEventDisableTiming));
   DH_HIP(ctx, hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking));
   return DH_OK;
+}
+
+// One single-frame histogram call, prepared on the host.
+struct FrameJob {
+  const double *d_coords = nullptr;
+  const int64_t *offsets = nullptr;
+  int32_t n_species = 0;
+  int precision = 0;
+  int kind = 0;
+  FrameParams fp{};
+  uint64_t total = 0;
+  uint64_t *d_out = nullptr;
+  uint64_t *d_oor = nullptr;
+};
+
+// Plans and enqueues one frame with the given knobs: stage (optional), zero,
+// pair kernel (between e0 and e1 when given), out-of-range counts.
+int run_frame(dh_ctx *ctx, hipStream_t st, const FrameJob &job, const Knobs &k, bool stage,
+              hipEvent_t e0, hipEvent_t e1) {
+  FrameParams fp = job.fp;
+  const int64_t n = job.offsets[job.n_species];
+  const int32_t n_hist = job.n_species * (job.n_species + 1) / 2;
+  Launch L = choose_launch(ctx, job.precision, fp, job.total, k);
+  fp.win = L.win;
+  fp.n_sweeps = L.n_sweeps;
+  fp.noclamp = L.noclamp ? 1 : 0;
+  std::vector<WorkItem> items;
+  std::vector<uint64_t> pairs;
+  plan_frame(0, job.offsets, job.n_species, L, items, pairs);
+  fp.coords = ctx->d_staged;
+  fp.out = job.d_out;
+  const BlobLayout lay = blob_layout(1, items.size(), pairs.size());
+  std::vector<FrameParams> frames(1, fp);
+  int rc = upload_blob(ctx, st, lay, frames, items, pairs);
+  if (rc) return rc;
+  char *db = static_cast<char *>(ctx->d_blob);
+  if (stage) DH_HIP(ctx, launch_stage(job.precision, job.kind, job.d_coords, ctx->d_staged, n, fp, st));
+  DH_HIP(ctx, launch_zero(job.d_out, static_cast<int64_t>(n_hist) * fp.n_bins,
+                          reinterpret_cast<int32_t *>(db + lay.counter), st));
+  const int grid = std::max(1, std::min<int>(L.grid, static_cast<int>(items.size())));
+  if (e0) DH_HIP(ctx, hipEventRecord(e0, st));
+  if (!items.empty()) {
+    PairKernelArgs a;
+    a.frames = reinterpret_cast<const FrameParams *>(db + lay.frames);
+    a.items = reinterpret_cast<const WorkItem *>(db + lay.items);
+    a.counter = reinterpret_cast<int32_t *>(db + lay.counter);
+    a.n_items = static_cast<int32_t>(items.size());
+    a.copies = L.cfg.copies;
+    a.stride = L.stride;
+    a.tj = L.cfg.tj;
+    DH_HIP(ctx, launch_pairs(job.precision, job.kind, L.n_sweeps > 1, L.cfg, a, grid, L.lds, st));
+  }
+  if (e1) DH_HIP(ctx, hipEventRecord(e1, st));
+  if (job.d_oor)
+    DH_HIP(ctx, launch_oor(job.d_out, n_hist, fp.n_bins,
+                           reinterpret_cast<const uint64_t *>(db + lay.pairs), job.d_oor, st));
+  const std::array<int32_t, 6> kp = k.pack();
+  for (int q = 0; q < 6; ++q) ctx->last_config[q] = kp[q];
+  ctx->last_config[6] = items.empty() ? 0 : grid;
+  ctx->last_config[7] = static_cast<int32_t>(L.lds);
+  ctx->last_config[8] = L.n_sweeps;
+  ctx->last_config[9] = static_cast<int32_t>(items.size());
+  return DH_OK;
+}
+
+int ilog2_ceil(uint64_t v) {
+  int e = 0;
+  while ((1ull << e) < v) ++e;
+  return e;
+}
+
+// Cache bucket of a frame: architecture, precision, minimum-image kind,
+// ceil(log2 n_bins), ceil(log2 N), species (capped at 4).
+std::string tune_key(const dh_ctx *ctx, const FrameJob &job) {
+  char buf[160];
+  snprintf(buf, sizeof buf, "%s|p%d|b%d|nb%d|n%d|k%d", ctx->arch.c_str(), job.precision, job.kind,
+           ilog2_ceil(static_cast<uint64_t>(job.fp.n_bins)),
+           ilog2_ceil(static_cast<uint64_t>(std::max<int64_t>(1, job.offsets[job.n_species]))),
+           std::min(job.n_species, 4));
+  return buf;
+}
+
+int save_tune_cache(dh_ctx *ctx) {
+  if (ctx->tune_path.empty()) return DH_OK;
+  std::ostringstream o;
+  o << "{\"version\": 1, \"knobs\": [\"r\", \"copies\", \"tj\", \"noclamp\", \"occ_cap\", "
+       "\"items_per_wg\"], \"entries\": {";
+  bool first = true;
+  for (const auto &kv : ctx->tune_cache) {
+    o << (first ? "\n  " : ",\n  ") << '"' << kv.first << "\": [";
+    for (int q = 0; q < 6; ++q) o << (q ? ", " : "") << kv.second[q];
+    o << ']';
+    first = false;
+  }
+  o << "\n}}\n";
+  const std::string tmp = ctx->tune_path + ".tmp";
+  {
+    std::ofstream f(tmp);
+    if (!f) return fail(ctx, DH_EINVAL, "cannot write %s", tmp.c_str());
+    f << o.str();
+  }
+  if (std::rename(tmp.c_str(), ctx->tune_path.c_str()) != 0)
+    return fail(ctx, DH_EINVAL, "cannot replace %s", ctx->tune_path.c_str());
+  return DH_OK;
+}
+
+// Reads entries written by save_tune_cache ("key": [6 integers]).
+int load_tune_cache(dh_ctx *ctx) {
+  std::ifstream f(ctx->tune_path);
+  if (!f) return DH_OK;  // no cache yet
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string t = ss.str();
+  size_t pos = t.find("\"entries\"");
+  if (pos != std::string::npos) pos = t.find('{', pos);
+  if (pos == std::string::npos) return fail(ctx, DH_EINVAL, "malformed tuning cache");
+  while (true) {
+    const size_t q0 = t.find('"', pos + 1);
+    if (q0 == std::string::npos) break;
+    const size_t q1 = t.find('"', q0 + 1);
+    if (q1 == std::string::npos) break;
+    const size_t lb = t.find('[', q1);
+    if (lb == std::string::npos) break;
+    const size_t rb = t.find(']', lb);
+    if (rb == std::string::npos) break;
+    const std::string key = t.substr(q0 + 1, q1 - q0 - 1);
+    std::array<int32_t, 6> v{};
+    std::istringstream in(t.substr(lb + 1, rb - lb - 1));
+    int q = 0;
+    std::string tok;
+    try {
+      while (q < 6 && std::getline(in, tok, ',')) v[q++] = static_cast<int32_t>(std::stol(tok));
+    } catch (...) {
+      return fail(ctx, DH_EINVAL, "malformed tuning cache entry %s", key.c_str());
+    }
+    if (q == 6 && Knobs::unpack(v).valid()) ctx->tune_cache[key] = v;
+    pos = rb;
+  }
+  return DH_OK;
+}
+
+// Times the pair kernel of candidate knob sets on this frame (coordinate
+// descent from the defaults, one knob at a time) and keeps the fastest.
+// Every candidate computes the same counts.
+int tune_frame(dh_ctx *ctx, hipStream_t st, const FrameJob &job, const std::string &key,
+               Knobs &best) {
+  const int64_t n = job.offsets[job.n_species];
+  FrameParams fp = job.fp;
+  fp.coords = ctx->d_staged;
+  DH_HIP(ctx, launch_stage(job.precision, job.kind, job.d_coords, ctx->d_staged, n, fp, st));
+  hipEvent_t e0, e1;
+  DH_HIP(ctx, hipEventCreate(&e0));
+  DH_HIP(ctx, hipEventCreate(&e1));
+  auto time_of = [&](const Knobs &k, float *ms) -> int {
+    float bestms = 1e30f;
+    for (int rep = 0; rep < 2; ++rep) {
+      int rc = run_frame(ctx, st, job, k, false, e0, e1);
+      if (rc) return rc;
+      DH_HIP(ctx, hipEventSynchronize(e1));
+      float v = 0.f;
+      DH_HIP(ctx, hipEventElapsedTime(&v, e0, e1));
+      bestms = std::min(bestms, v);
+    }
+    *ms = bestms;
+    return DH_OK;
+  };
+  best = default_knobs(job.precision);
+  float best_ms = 0.f;
+  int rc = time_of(best, &best_ms);
+  const std::vector<std::vector<int32_t>> choices = {
+      {0, 1},        // noclamp
+      {1, 2, 4},     // copies
+      {4, 8},        // r
+      {0, 1, 2},     // occ_cap
+      {4, 8, 16},    // items_per_wg
+      {128, 256},    // tj
+  };
+  const int order[6] = {3, 1, 0, 4, 5, 2};  // knob index in pack() order
+  for (int d = 0; d < 6 && !rc; ++d) {
+    const int q = order[d];
+    for (int32_t v : choices[d]) {
+      std::array<int32_t, 6> kp = best.pack();
+      if (kp[q] == v) continue;
+      kp[q] = v;
+      const Knobs cand = Knobs::unpack(kp);
+      float ms = 0.f;
+      rc = time_of(cand, &ms);
+      if (rc) break;
+      if (ms < best_ms * 0.99f) {
+        best = cand;
+        best_ms = ms;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  ctx->tune_cache[key] = best.pack();
+  return save_tune_cache(ctx);
 }
 
 std::mutex g_default_mu;
@@ -533,69 +784,54 @@ int dh_histo_async(dh_ctx *ctx, dh_stream stream, const double *d_coords, const 
   hipStream_t st = static_cast<hipStream_t>(stream);
   DH_HIP(ctx, hipSetDevice(ctx->device));
 
-  FrameParams fp;
-  int kind = frame_consts(box_type, box, r_max, n_bins, fp);
-  if (precision == DH_FP32 && kind == kBoxOrtho && fp.L[0] == fp.L[1] && fp.L[1] == fp.L[2])
-    fp.box = kind = kBoxCube;
-  const int32_t n_hist = n_species * (n_species + 1) / 2;
-  uint64_t total = 0;
+  FrameJob job;
+  job.d_coords = d_coords;
+  job.offsets = offsets;
+  job.n_species = n_species;
+  job.precision = precision;
+  job.d_out = d_out;
+  job.d_oor = d_out_of_range;
+  job.kind = frame_consts(box_type, box, r_max, n_bins, job.fp);
+  if (precision == DH_FP32 && job.kind == kBoxOrtho && job.fp.L[0] == job.fp.L[1] &&
+      job.fp.L[1] == job.fp.L[2])
+    job.fp.box = job.kind = kBoxCube;
   for (int s = 0; s < n_species; ++s) {
     const uint64_t a = static_cast<uint64_t>(offsets[s + 1] - offsets[s]);
-    total += a * (a > 0 ? a - 1 : 0) / 2;
+    job.total += a * (a > 0 ? a - 1 : 0) / 2;
     for (int t = s + 1; t < n_species; ++t)
-      total += a * static_cast<uint64_t>(offsets[t + 1] - offsets[t]);
+      job.total += a * static_cast<uint64_t>(offsets[t + 1] - offsets[t]);
   }
-  Launch L = choose_launch(ctx, precision, fp, total);
-  fp.win = L.win;
-  fp.n_sweeps = L.n_sweeps;
-  fp.noclamp = L.noclamp ? 1 : 0;
-  std::vector<WorkItem> items;
-  std::vector<uint64_t> pairs;
-  plan_frame(0, offsets, n_species, L, items, pairs);
-
   rc = ensure_device(ctx, &ctx->d_staged, &ctx->staged_cap,
                      std::max<size_t>(1, static_cast<size_t>(n)) * coord_bytes(precision));
   if (rc) return rc;
-  fp.coords = ctx->d_staged;
-  fp.out = d_out;
-  const BlobLayout lay = blob_layout(1, items.size(), pairs.size());
-  std::vector<FrameParams> frames(1, fp);
-  rc = upload_blob(ctx, st, lay, frames, items, pairs);
-  if (rc) return rc;
-  char *db = static_cast<char *>(ctx->d_blob);
-  DH_HIP(ctx, launch_stage(precision, kind, d_coords, ctx->d_staged, n, fp, st));
-  DH_HIP(ctx, launch_zero(d_out, static_cast<int64_t>(n_hist) * n_bins,
-                          reinterpret_cast<int32_t *>(db + lay.counter), st));
-  if (!items.empty()) {
-    PairKernelArgs a;
-    a.frames = reinterpret_cast<const FrameParams *>(db + lay.frames);
-    a.items = reinterpret_cast<const WorkItem *>(db + lay.items);
-    a.counter = reinterpret_cast<int32_t *>(db + lay.counter);
-    a.n_items = static_cast<int32_t>(items.size());
-    a.copies = L.cfg.copies;
-    a.stride = L.stride;
-    a.tj = L.cfg.tj;
-    const int grid = std::max(1, std::min<int>(L.grid, static_cast<int>(items.size())));
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (ctx->profile) {
-      if (ctx->prof_used == ctx->prof_events.size()) {
-        hipEvent_t x, y;
-        DH_HIP(ctx, hipEventCreate(&x));
-        DH_HIP(ctx, hipEventCreate(&y));
-        ctx->prof_events.emplace_back(x, y);
-      }
-      e0 = ctx->prof_events[ctx->prof_used].first;
-      e1 = ctx->prof_events[ctx->prof_used].second;
-      ++ctx->prof_used;
-      DH_HIP(ctx, hipEventRecord(e0, st));
+
+  Knobs k = default_knobs(precision);
+  const std::string key = tune_key(ctx, job);
+  if (ctx->forced) {
+    k = Knobs::unpack(ctx->forced_knobs);
+  } else if (ctx->tune_mode != DH_TUNE_OFF) {
+    auto it = ctx->tune_cache.find(key);
+    if (it != ctx->tune_cache.end()) {
+      k = Knobs::unpack(it->second);
+    } else if (ctx->tune_mode == DH_TUNE_ON && job.total > 0) {
+      rc = tune_frame(ctx, st, job, key, k);
+      if (rc) return rc;
     }
-    DH_HIP(ctx, launch_pairs(precision, kind, L.n_sweeps > 1, L.cfg, a, grid, L.lds, st));
-    if (e1) DH_HIP(ctx, hipEventRecord(e1, st));
   }
-  if (d_out_of_range)
-    DH_HIP(ctx, launch_oor(d_out, n_hist, n_bins,
-                           reinterpret_cast<const uint64_t *>(db + lay.pairs), d_out_of_range, st));
-  return DH_OK;
+
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ctx->profile) {
+    if (ctx->prof_used == ctx->prof_events.size()) {
+      hipEvent_t x, y;
+      DH_HIP(ctx, hipEventCreate(&x));
+      DH_HIP(ctx, hipEventCreate(&y));
+      ctx->prof_events.emplace_back(x, y);
+    }
+    e0 = ctx->prof_events[ctx->prof_used].first;
+    e1 = ctx->prof_events[ctx->prof_used].second;
+    ++ctx->prof_used;
+  }
+  return run_frame(ctx, st, job, k, true, e0, e1);
 }
 
 int dh_histo(const double *coords, const int64_t *offsets, int32_t n_species, int32_t box_type,
@@ -690,7 +926,8 @@ int dh_batch_create(dh_ctx *ctx, const dh_frame_desc *frames, int32_t n_frames, 
     std::vector<uint64_t> hist_pairs;
   };
   std::vector<FrameInfo> info(n_frames);
-  const BaseConfig base = base_config(ctx, precision);
+  const Knobs bk = ctx->forced ? Knobs::unpack(ctx->forced_knobs) : default_knobs(precision);
+  const BaseConfig base = base_config(ctx, precision, bk);
   for (int32_t f = 0; f < n_frames; ++f) {
     const dh_frame_desc &d = frames[f];
     int rc = check(nullptr, d.offsets, d.n_species, d.box_type, d.box, d.r_max, d.n_bins,
@@ -713,8 +950,7 @@ int dh_batch_create(dh_ctx *ctx, const dh_frame_desc *frames, int32_t n_frames, 
       fi.sweep = true;
     }
     const double tb = t_bound(fi.fp);
-    const char *env = std::getenv("DH_NOCLAMP");
-    if (!(env && env[0] == '0') && !fi.sweep && tb > 0) {
+    if (base.noclamp && !fi.sweep && tb > 0) {
       fi.slots = static_cast<int64_t>(tb * (1.0 + 1e-4)) + 2;
       fi.noclamp_ok = fi.slots <= base.win_max + kDump;
     }
@@ -768,8 +1004,8 @@ int dh_batch_create(dh_ctx *ctx, const dh_frame_desc *frames, int32_t n_frames, 
     for (int32_t f : fs) info[f].fp.noclamp = (info[f].noclamp_ok && info[f].slots <= stride) ? 1 : 0;
     g.stride = static_cast<int>(stride);
     g.lds = base.tile_bytes + static_cast<size_t>(g.cfg.copies) * g.stride * 4;
-    g.grid = ctx->n_cu * pairs_occupancy(precision, g.kind, g.sweep, g.cfg, g.lds);
-    g.cfg.jchunk = jchunk_for(g.cfg, g.grid, work);
+    g.grid = grid_for_config(ctx, precision, g.kind, g.sweep, base, g.lds);
+    g.cfg.jchunk = jchunk_for(g.cfg, g.grid, work, base.items_per_wg);
     // large frames first: the tail of the work list is made of small items
     std::stable_sort(fs.begin(), fs.end(),
                      [&](int32_t x, int32_t y) { return info[x].pairs > info[y].pairs; });
@@ -885,6 +1121,36 @@ void dh_batch_destroy(dh_batch *b) {
   }
   (void)hipGetLastError();
   delete b;
+}
+
+int dh_ctx_set_tuning(dh_ctx *ctx, int32_t mode, const char *cache_path) {
+  if (!ctx || mode < DH_TUNE_OFF || mode > DH_TUNE_ON) return DH_EINVAL;
+  ctx->tune_mode = mode;
+  if (cache_path) {
+    ctx->tune_path = cache_path;
+    return load_tune_cache(ctx);
+  }
+  return DH_OK;
+}
+
+int dh_ctx_set_config(dh_ctx *ctx, const int32_t *knobs) {
+  if (!ctx) return DH_EINVAL;
+  if (!knobs) {
+    ctx->forced = false;
+    return DH_OK;
+  }
+  std::array<int32_t, 6> v;
+  for (int q = 0; q < 6; ++q) v[q] = knobs[q];
+  if (!Knobs::unpack(v).valid()) return fail(ctx, DH_EINVAL, "invalid launch knobs");
+  ctx->forced = true;
+  ctx->forced_knobs = v;
+  return DH_OK;
+}
+
+int dh_ctx_last_config(const dh_ctx *ctx, int32_t *out) {
+  if (!ctx || !out) return DH_EINVAL;
+  for (int q = 0; q < 10; ++q) out[q] = ctx->last_config[q];
+  return DH_OK;
 }
 
 int dh_ctx_profile(dh_ctx *ctx, int32_t enable) {

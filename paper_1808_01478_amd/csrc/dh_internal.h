@@ -73,8 +73,8 @@ struct PairKernelArgs {
   const WorkItem *items;
   int32_t *counter;  // dynamic work counter, zero before launch
   int32_t n_items;
-  int32_t copies;    // LDS sub-histogram copies per workgroup
-  int32_t stride;    // words per copy (>= win + kDump of every frame)
+  int32_t copies;    // interleaved LDS sub-histogram copies (1, 2 or 4)
+  int32_t stride;    // slots per copy (>= win + kDump of every frame)
   int32_t tj;        // j-tile length staged through LDS
 };
 
@@ -82,7 +82,7 @@ struct PairKernelArgs {
 struct KernelConfig {
   int32_t threads;   // workgroup size (multiple of 64, <= 256)
   int32_t r;         // i-particles per lane (4 or 8)
-  int32_t copies;    // sub-histogram copies per workgroup (1, 2, 4)
+  int32_t copies;    // interleaved sub-histogram copies (1, 2, 4)
   int32_t tj;        // j-tile length (<= threads)
   int32_t jchunk;    // j-range of one work item (multiple of tj)
   int32_t wg_per_cu; // 0 = as many as fit

@@ -285,6 +285,7 @@ __global__ void oor_batch_kernel(const FrameParams *__restrict__ frames) {
 // --------------------------------------------------------------------------
 
 // Adds the LDS copies of bins [0, count) into out[] and clears every slot.
+// Copies are interleaved bin-major: slot b of copy c is word b * copies + c.
 __device__ __forceinline__ void flush_hist(uint32_t *hist, const PairKernelArgs &a,
                                            const FrameParams *F, int hist_idx, int sweep) {
   const int n_bins = uni(F->n_bins);
@@ -297,10 +298,10 @@ __device__ __forceinline__ void flush_hist(uint32_t *hist, const PairKernelArgs 
   const int clear = a.stride;
   for (int b = threadIdx.x; b < clear; b += blockDim.x) {
     uint64_t v = 0;
+    uint32_t *p = hist + b * a.copies;
     for (int c = 0; c < a.copies; ++c) {
-      uint32_t *p = hist + c * a.stride + b;
-      v += *p;
-      *p = 0u;
+      v += p[c];
+      p[c] = 0u;
     }
     if (b < count && v != 0)
       atomicAdd(reinterpret_cast<unsigned long long *>(out + b),
@@ -324,6 +325,7 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
   const int tj = a.tj;
   const int win = uni(F->win);
   const int b_lo = w.sweep * win;
+  const int log_copies = a.copies == 4 ? 2 : (a.copies == 2 ? 1 : 0);
 
   // i-particles: wave w holds [wbase, wbase + 64R), lane l the R values
   // wbase + r*64 + l
@@ -387,7 +389,7 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
             if constexpr (SWEEP) idx -= static_cast<uint32_t>(b_lo);
             idx = max(min(idx, hi), l);
           }
-          atomicAdd(my + idx, 1u);
+          atomicAdd(my + (idx << log_copies), 1u);
         }
       };
       // Ping-pong over two j registers: the read of the next j is issued
@@ -420,8 +422,9 @@ __global__ __launch_bounds__(256) void pairs_kernel(PairKernelArgs a) {
   V *tile = reinterpret_cast<V *>(smem);
   uint32_t *hist = reinterpret_cast<uint32_t *>(smem + 2 * a.tj * sizeof(V));
   const int tid = threadIdx.x;
-  const int wave = tid >> 6;
-  uint32_t *my = hist + (wave % a.copies) * a.stride;
+  // lane-interleaved sub-histogram copies: lanes of one instruction that
+  // hit the same bin use different words (and banks) when copies > 1
+  uint32_t *my = hist + (tid & 63) % a.copies;
 
   for (int k = tid; k < a.copies * a.stride; k += blockDim.x) hist[k] = 0u;
 

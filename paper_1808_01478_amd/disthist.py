@@ -38,6 +38,9 @@ SIGNATURES = {
     "dh_batch_info": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32), ctypes.POINTER(_f64)],
                       ctypes.c_int),
     "dh_batch_destroy": ([_vp], None),
+    "dh_ctx_set_tuning": ([_vp, _i32, ctypes.c_char_p], ctypes.c_int),
+    "dh_ctx_set_config": ([_vp, _vp], ctypes.c_int),
+    "dh_ctx_last_config": ([_vp, _vp], ctypes.c_int),
     "dh_ctx_profile": ([_vp, _i32], ctypes.c_int),
     "dh_ctx_profile_read": ([_vp, ctypes.POINTER(_f64), ctypes.POINTER(_i64)], ctypes.c_int),
 }
@@ -51,6 +54,8 @@ class FrameDesc(ctypes.Structure):
 
 
 BATCH_GRAPH = 1
+TUNE_OFF, TUNE_CACHED, TUNE_ON = 0, 1, 2
+KNOB_NAMES = ("r", "copies", "tj", "noclamp", "occ_cap", "items_per_wg")
 
 
 def _load() -> ctypes.CDLL:
@@ -185,6 +190,30 @@ class Context:
                                   None if d_out_of_range is None
                                   else ctypes.c_void_p(d_out_of_range.data_ptr())),
                self.handle)
+
+    def set_tuning(self, mode: int, cache_path: Optional[str] = None) -> None:
+        """dh_ctx_set_tuning: TUNE_OFF, TUNE_CACHED or TUNE_ON, optional JSON cache."""
+        _check(LIB.dh_ctx_set_tuning(self.handle, int(mode),
+                                     None if cache_path is None else cache_path.encode()),
+               self.handle)
+
+    def set_config(self, knobs=None) -> None:
+        """dh_ctx_set_config: force a launch shape (dict or 6 ints) or None."""
+        if knobs is None:
+            _check(LIB.dh_ctx_set_config(self.handle, None), self.handle)
+            return
+        if isinstance(knobs, dict):
+            knobs = [knobs[k] for k in KNOB_NAMES]
+        arr = np.ascontiguousarray(np.asarray(knobs, np.int32))
+        _check(LIB.dh_ctx_set_config(self.handle, _np_ptr(arr)), self.handle)
+
+    def last_config(self) -> dict:
+        """dh_ctx_last_config: the shape of the last single-frame launch."""
+        out = np.zeros(10, np.int32)
+        _check(LIB.dh_ctx_last_config(self.handle, _np_ptr(out)), self.handle)
+        d = {k: int(v) for k, v in zip(KNOB_NAMES, out[:6])}
+        d.update(grid=int(out[6]), lds_bytes=int(out[7]), sweeps=int(out[8]), items=int(out[9]))
+        return d
 
     def profile(self, enable: bool = True) -> None:
         """dh_ctx_profile: time the pair kernel of every launch with HIP events."""
