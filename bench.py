@@ -173,6 +173,64 @@ def bench_trajectory(ctx, n_frames: int, steps: int):
     }
 
 
+def run_trace(server_args, frames, gaps):
+    """Submits frames at the given inter-arrival gaps (seconds) to a new
+    server; returns per-job latencies and the makespan."""
+    import threading
+    import paper_1808_01478_amd as dh
+    with dh.Server(0, **server_args) as srv:
+        ids, t_sub = [None] * len(frames), [0.0] * len(frames)
+        t0 = time.perf_counter()
+
+        def client():
+            t_next = t0
+            for k, (f, g) in enumerate(zip(frames, gaps)):
+                t_next += g
+                delay = t_next - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                t_sub[k] = time.perf_counter() - t0
+                ids[k] = srv.submit(f.coords, f.offsets, f.box_type, f.box, f.r_max, f.n_bins,
+                                    dh.FP32)
+        th = threading.Thread(target=client)
+        th.start()
+        th.join()
+        lat = []
+        for k in range(len(frames)):
+            _, _, times = srv.wait(ids[k])
+            lat.append(times[2])
+        st = srv.stats()
+    end = max(t + l for t, l in zip(t_sub, lat))
+    return np.array(lat), end, st
+
+
+def bench_serving(n_jobs: int, seed: int = 5):
+    """Histogram jobs with N log-uniform in [1e3, 2e6], box none/orthorhombic/
+    triclinic, 1-3 species, 1k/10k/50k bins, binary32, Poisson arrivals at
+    0.75 of the saturated job rate: continuous batching (4 slots, 8 GiB HBM
+    budget) against one job at a time on the same arrivals."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    frames = [workloads.serving_job(rng, j, 0.0).frame for j in range(n_jobs)]
+    pairs = sum(f.total_pairs() for f in frames)
+    cont = {"hbm_budget_bytes": 8 << 30, "max_inflight": 4}
+    fifo = {"hbm_budget_bytes": 8 << 30, "max_inflight": 1}
+    # saturated capacity: everything submitted at once, one at a time
+    _, sat_end, _ = run_trace(fifo, frames, [0.0] * n_jobs)
+    capacity = n_jobs / sat_end
+    lam = 0.75 * capacity
+    gaps = rng.exponential(1.0 / lam, size=n_jobs)
+    out = {"workload": f"serving: {n_jobs} jobs, N log-uniform [1e3, 2e6], box none/ortho/"
+                       "triclinic, 1-3 species, bins 1k/10k/50k, binary32, Poisson arrivals",
+           "pairs": pairs, "saturated_jobs_per_s": capacity, "arrival_rate_per_s": lam}
+    for name, args in (("continuous_batching", cont), ("fifo_one_at_a_time", fifo)):
+        lat, end, st = run_trace(args, frames, gaps)
+        out[name] = {"p50_ms": float(np.percentile(lat, 50) * 1e3),
+                     "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                     "throughput_pairs_per_s": pairs / end, "jobs_per_s": n_jobs / end,
+                     "max_running": st["max_running"], "peak_bytes": st["peak_bytes"]}
+    return out
+
+
 def cpu_baseline(frame, target_s: float = 12.0):
     """The oracle (plain FP64 double loop, OpenMP) on the first M points of
     every species of the same frame, M sized for about target_s seconds."""
@@ -217,6 +275,8 @@ def main():
     ap.add_argument("--workload", default="ortho100k")
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving-jobs", type=int, default=40,
+                    help="jobs of the serving comparison (0 = skip)")
     ap.add_argument("--no-tune", action="store_true",
                     help="built-in launch shape instead of tuning on the first warm-up call")
     ap.add_argument("--trajectory-frames", type=int, default=512,
@@ -235,7 +295,10 @@ def main():
     pairs = frame.total_pairs()
     ctx = dh.Context(0)
     if not args.no_tune:
-        ctx.set_tuning(dh.TUNE_ON)     # the first warm-up call of each precision tunes
+        # shapes from the committed cache; a bucket missing from it is tuned
+        # on the first warm-up call
+        from paper_1808_01478_amd.tune import DEFAULT_CACHE
+        ctx.set_tuning(dh.TUNE_ON, DEFAULT_CACHE if os.path.exists(DEFAULT_CACHE) else None)
     r32 = time_path(ctx, frame, dh.FP32, args.steps, max(1, args.warmup))
     shape32 = ctx.last_config()
     fp64_steps = args.fp64_steps if args.fp64_steps is not None else max(1, args.steps // 2)
@@ -294,6 +357,10 @@ def main():
         },
         "cpu_baseline": None,
     }
+    if args.serving_jobs > 0:
+        line["serving"] = bench_serving(args.serving_jobs)
+        line["latency_ms"]["serving_p50"] = line["serving"]["continuous_batching"]["p50_ms"]
+        line["latency_ms"]["serving_p99"] = line["serving"]["continuous_batching"]["p99_ms"]
     if args.trajectory_frames > 0:
         line["trajectory"] = bench_trajectory(ctx, args.trajectory_frames, max(1, args.steps // 5))
     if not args.no_cpu_baseline:

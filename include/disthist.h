@@ -227,9 +227,78 @@ int dh_batch_info(const dh_batch *batch, int64_t *n_items, int32_t *n_launches,
 void dh_batch_destroy(dh_batch *batch);
 
 /* ---------------------------------------------------------------------------
+ * Serving: a request loop that runs histogram jobs of mixed sizes, boxes and
+ * bin counts concurrently on one GPU (continuous batching). A scheduler
+ * thread admits queued jobs while a slot (a context with its own stream) is
+ * free and the job's device footprint fits the HBM budget, in arrival order
+ * with backfill: a later job that fits may start while an earlier one waits
+ * for memory, unless the earliest job has waited longer than the head-wait
+ * limit, which then reserves the memory it needs. Admitted jobs keep their
+ * frame resident on the device, run on their slot's stream and overlap with
+ * the other running jobs; completion is detected with events. The paper's
+ * counterpart is its producer/consumer engine that feeds frames to GPU
+ * workers through queues (Sec. 3.3).
+ */
+typedef struct dh_server dh_server;
+
+#define DH_JOB_DONE 0
+#define DH_JOB_QUEUED 1
+#define DH_JOB_RUNNING 2
+
+/*
+ * Creates a server on `device` with `max_inflight` (1..16) slots and an HBM
+ * budget in bytes for the footprints of running jobs (coordinates, staged
+ * copy, histograms, work list). head_wait_limit_s < 0 selects 1 second.
+ */
+int dh_server_create(int32_t device, int64_t hbm_budget_bytes, int32_t max_inflight,
+                     double head_wait_limit_s, dh_server **server);
+
+/*
+ * Queues one job (arguments as dh_histo, host memory, copied before return)
+ * and returns its id. DH_EINVAL for invalid arguments, DH_EBUDGET when the
+ * job's footprint alone exceeds the budget; neither queues anything.
+ */
+int dh_server_submit(dh_server *server, const double *coords, const int64_t *offsets,
+                     int32_t n_species, int32_t box_type, const double *box, double r_max,
+                     int32_t n_bins, int32_t precision, int64_t *job_id);
+
+/* DH_JOB_QUEUED, DH_JOB_RUNNING, DH_JOB_DONE, or the job's negative error;
+ * DH_EINVAL for an unknown id. */
+int dh_server_status(dh_server *server, int64_t job_id);
+
+/*
+ * Waits for a job, copies its histograms (uint64 [H][n_bins]) and
+ * out-of-range counts ([H]) to host memory (either may be NULL) and releases
+ * it. times[3] (may be NULL) = seconds queued, seconds running, and the
+ * latency from submission to completion. Returns the job's status.
+ */
+int dh_server_wait(dh_server *server, int64_t job_id, uint64_t *out, uint64_t *out_of_range,
+                   double *times);
+
+/*
+ * stats[6] = jobs submitted, completed, failed, the largest number of jobs
+ * running at once, the largest sum of admitted footprints (bytes), and the
+ * budget (bytes).
+ */
+int dh_server_stats(const dh_server *server, int64_t *stats);
+
+/* Finishes running jobs, drops queued ones, releases the server. */
+void dh_server_destroy(dh_server *server);
+
+/*
+ * The admission policy of the server as a pure host function (no device):
+ * given the queued jobs in arrival order (footprints and seconds waited),
+ * the free budget and the free slots, writes the queue positions to start
+ * now into admit[] (ascending) and returns how many.
+ */
+int32_t dh_sched_select(const int64_t *need_bytes, const double *waited_s, int32_t n_queued,
+                        int64_t free_bytes, int32_t free_slots, double head_wait_limit_s,
+                        int32_t *admit);
+
+/* ---------------------------------------------------------------------------
  * Launch tuning. The launch shape of a frame (i-particles per lane, LDS
  * sub-histogram copies, j-tile length, unclamped interior blocks, workgroups
- * per CU, work items per workgroup) changes speed only: every shape gives
+ * per CU, work items per workgroup, workgroup size) changes speed only: every shape gives
  * the same counts (the paper picks its block size and kernel by fixed
  * heuristics, Sec. 3.2.4 and Sec. 4.2).
  *
@@ -249,15 +318,17 @@ int dh_ctx_set_tuning(dh_ctx *ctx, int32_t mode, const char *cache_path);
 
 /*
  * Forces a launch shape for every later call on ctx (NULL restores tuning):
- * knobs[6] = {r (4|8), copies (1|2|4), tj (128|256), noclamp (0|1),
- * occ_cap (0..16, 0 = as many as fit), items_per_wg (1..64)}.
+ * knobs[7] = {r (4|8), copies (1|2|4), tj (128|256), noclamp (0|1),
+ * occ_cap (0..16, 0 = as many as fit), items_per_wg (1..64),
+ * threads (256|512|1024; the 27-image search always runs 256)}.
  * Invalid knob values give DH_EINVAL.
  */
 int dh_ctx_set_config(dh_ctx *ctx, const int32_t *knobs);
 
 /*
- * The shape of the last single-frame launch on ctx: out[10] = the six knobs,
- * then grid size, LDS bytes per workgroup, bin-window sweeps, work items.
+ * The shape of the last single-frame launch on ctx: out[11] = the first six
+ * knobs, the workgroup size launched, the grid size, LDS bytes per
+ * workgroup, bin-window sweeps, work items.
  */
 int dh_ctx_last_config(const dh_ctx *ctx, int32_t *out);
 

@@ -42,10 +42,10 @@ struct dh_ctx {
   // launch tuning (see dh_ctx_set_tuning)
   int tune_mode = 0;
   std::string tune_path;
-  std::map<std::string, std::array<int32_t, 6>> tune_cache;
+  std::map<std::string, std::array<int32_t, 7>> tune_cache;   // launch knobs per bucket
   bool forced = false;
-  std::array<int32_t, 6> forced_knobs{};
-  std::array<int32_t, 10> last_config{};
+  std::array<int32_t, 7> forced_knobs{};
+  std::array<int32_t, 11> last_config{};
   // kernel timing: event pairs recorded around pair-kernel launches
   bool profile = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
@@ -219,6 +219,8 @@ size_t coord_bytes(int precision) { return precision == DH_FP64 ? 32 : 16; }
 
 // Launch shape for one frame (heuristic defaults).
 // Launch knobs. Every choice yields identical counts; they only change speed.
+constexpr int kNumKnobs = 7;
+
 struct Knobs {
   int32_t r = 8;             // i-particles per lane: 4 or 8
   int32_t copies = 1;        // interleaved LDS copies: 1, 2 or 4
@@ -226,17 +228,21 @@ struct Knobs {
   int32_t noclamp = 1;       // allow unclamped interior blocks
   int32_t occ_cap = 0;       // workgroups per CU at most (0: as many as fit)
   int32_t items_per_wg = 8;  // work items per workgroup (sets the j-chunk)
-  std::array<int32_t, 6> pack() const { return {r, copies, tj, noclamp, occ_cap, items_per_wg}; }
-  static Knobs unpack(const std::array<int32_t, 6> &v) {
+  int32_t threads = 256;     // workgroup size: 256, 512 or 1024
+  std::array<int32_t, kNumKnobs> pack() const {
+    return {r, copies, tj, noclamp, occ_cap, items_per_wg, threads};
+  }
+  static Knobs unpack(const std::array<int32_t, kNumKnobs> &v) {
     Knobs k;
     k.r = v[0]; k.copies = v[1]; k.tj = v[2]; k.noclamp = v[3]; k.occ_cap = v[4];
-    k.items_per_wg = v[5];
+    k.items_per_wg = v[5]; k.threads = v[6];
     return k;
   }
   bool valid() const {
     return (r == 4 || r == 8) && (copies == 1 || copies == 2 || copies == 4) &&
            (tj == 128 || tj == 256) && (noclamp == 0 || noclamp == 1) && occ_cap >= 0 &&
-           occ_cap <= 16 && items_per_wg >= 1 && items_per_wg <= 64;
+           occ_cap <= 16 && items_per_wg >= 1 && items_per_wg <= 64 &&
+           (threads == 256 || threads == 512 || threads == 1024);
   }
 };
 
@@ -259,10 +265,11 @@ struct BaseConfig {
   bool noclamp;
 };
 
-BaseConfig base_config(const dh_ctx *ctx, int precision, const Knobs &k) {
+BaseConfig base_config(const dh_ctx *ctx, int precision, const Knobs &k, int kind) {
   BaseConfig b;
   KernelConfig &c = b.cfg;
-  c.threads = 256;
+  // the image-search kernels are built for at most 256 threads
+  c.threads = kind == kBoxTricSearch ? 256 : k.threads;
   c.r = k.r;
   c.copies = k.copies;
   c.tj = k.tj;
@@ -298,7 +305,7 @@ int grid_for_config(const dh_ctx *ctx, int precision, int kind, bool sweep, cons
 Launch choose_launch(const dh_ctx *ctx, int precision, const FrameParams &fp,
                      uint64_t total_pairs, const Knobs &k) {
   Launch L;
-  const BaseConfig b = base_config(ctx, precision, k);
+  const BaseConfig b = base_config(ctx, precision, k, fp.box);
   L.cfg = b.cfg;
   const int32_t n_bins = fp.n_bins;
   if (n_bins <= b.win_max) {
@@ -534,12 +541,13 @@ int run_frame(dh_ctx *ctx, hipStream_t st, const FrameJob &job, const Knobs &k, 
   if (job.d_oor)
     DH_HIP(ctx, launch_oor(job.d_out, n_hist, fp.n_bins,
                            reinterpret_cast<const uint64_t *>(db + lay.pairs), job.d_oor, st));
-  const std::array<int32_t, 6> kp = k.pack();
-  for (int q = 0; q < 6; ++q) ctx->last_config[q] = kp[q];
-  ctx->last_config[6] = items.empty() ? 0 : grid;
-  ctx->last_config[7] = static_cast<int32_t>(L.lds);
-  ctx->last_config[8] = L.n_sweeps;
-  ctx->last_config[9] = static_cast<int32_t>(items.size());
+  const std::array<int32_t, kNumKnobs> kp = k.pack();
+  for (int q = 0; q < kNumKnobs; ++q) ctx->last_config[q] = kp[q];
+  ctx->last_config[6] = L.cfg.threads;  // the workgroup size actually launched
+  ctx->last_config[7] = items.empty() ? 0 : grid;
+  ctx->last_config[8] = static_cast<int32_t>(L.lds);
+  ctx->last_config[9] = L.n_sweeps;
+  ctx->last_config[10] = static_cast<int32_t>(items.size());
   return DH_OK;
 }
 
@@ -563,12 +571,12 @@ std::string tune_key(const dh_ctx *ctx, const FrameJob &job) {
 int save_tune_cache(dh_ctx *ctx) {
   if (ctx->tune_path.empty()) return DH_OK;
   std::ostringstream o;
-  o << "{\"version\": 1, \"knobs\": [\"r\", \"copies\", \"tj\", \"noclamp\", \"occ_cap\", "
-       "\"items_per_wg\"], \"entries\": {";
+  o << "{\"version\": 2, \"knobs\": [\"r\", \"copies\", \"tj\", \"noclamp\", \"occ_cap\", "
+       "\"items_per_wg\", \"threads\"], \"entries\": {";
   bool first = true;
   for (const auto &kv : ctx->tune_cache) {
     o << (first ? "\n  " : ",\n  ") << '"' << kv.first << "\": [";
-    for (int q = 0; q < 6; ++q) o << (q ? ", " : "") << kv.second[q];
+    for (int q = 0; q < kNumKnobs; ++q) o << (q ? ", " : "") << kv.second[q];
     o << ']';
     first = false;
   }
@@ -604,16 +612,17 @@ int load_tune_cache(dh_ctx *ctx) {
     const size_t rb = t.find(']', lb);
     if (rb == std::string::npos) break;
     const std::string key = t.substr(q0 + 1, q1 - q0 - 1);
-    std::array<int32_t, 6> v{};
+    std::array<int32_t, kNumKnobs> v{};
     std::istringstream in(t.substr(lb + 1, rb - lb - 1));
     int q = 0;
     std::string tok;
     try {
-      while (q < 6 && std::getline(in, tok, ',')) v[q++] = static_cast<int32_t>(std::stol(tok));
+      while (q < kNumKnobs && std::getline(in, tok, ','))
+      v[q++] = static_cast<int32_t>(std::stol(tok));
     } catch (...) {
       return fail(ctx, DH_EINVAL, "malformed tuning cache entry %s", key.c_str());
     }
-    if (q == 6 && Knobs::unpack(v).valid()) ctx->tune_cache[key] = v;
+    if (q == kNumKnobs && Knobs::unpack(v).valid()) ctx->tune_cache[key] = v;
     pos = rb;
   }
   return DH_OK;
@@ -648,18 +657,19 @@ int tune_frame(dh_ctx *ctx, hipStream_t st, const FrameJob &job, const std::stri
   float best_ms = 0.f;
   int rc = time_of(best, &best_ms);
   const std::vector<std::vector<int32_t>> choices = {
-      {0, 1},        // noclamp
-      {1, 2, 4},     // copies
-      {4, 8},        // r
-      {0, 1, 2},     // occ_cap
-      {4, 8, 16},    // items_per_wg
-      {128, 256},    // tj
+      {256, 512, 1024},  // threads
+      {0, 1},            // noclamp
+      {1, 2, 4},         // copies
+      {4, 8},            // r
+      {0, 1, 2},         // occ_cap
+      {4, 8, 16},        // items_per_wg
+      {128, 256},        // tj
   };
-  const int order[6] = {3, 1, 0, 4, 5, 2};  // knob index in pack() order
-  for (int d = 0; d < 6 && !rc; ++d) {
+  const int order[kNumKnobs] = {6, 3, 1, 0, 4, 5, 2};  // knob index in pack() order
+  for (int d = 0; d < kNumKnobs && !rc; ++d) {
     const int q = order[d];
     for (int32_t v : choices[d]) {
-      std::array<int32_t, 6> kp = best.pack();
+      std::array<int32_t, kNumKnobs> kp = best.pack();
       if (kp[q] == v) continue;
       kp[q] = v;
       const Knobs cand = Knobs::unpack(kp);
@@ -683,6 +693,34 @@ std::mutex g_default_mu;
 std::map<int, dh_ctx *> g_default;
 
 }  // namespace
+
+namespace dh {
+
+size_t ctx_device_bytes(const dh_ctx *ctx) {
+  return ctx->staged_cap + ctx->blob_cap + ctx->in_cap + ctx->out_cap;
+}
+
+void ctx_release_scratch(dh_ctx *ctx) {
+  if (hipSetDevice(ctx->device) != hipSuccess) return;
+  void **bufs[4] = {&ctx->d_staged, &ctx->d_blob, reinterpret_cast<void **>(&ctx->d_in),
+                    reinterpret_cast<void **>(&ctx->d_out)};
+  size_t *caps[4] = {&ctx->staged_cap, &ctx->blob_cap, &ctx->in_cap, &ctx->out_cap};
+  for (int k = 0; k < 4; ++k) {
+    if (*bufs[k]) (void)hipFree(*bufs[k]);
+    *bufs[k] = nullptr;
+    *caps[k] = 0;
+  }
+  (void)hipGetLastError();
+}
+
+size_t job_scratch_bytes(int64_t n_points, int32_t n_hist, int32_t precision) {
+  // staged coordinates plus the work blob (frame constants, work items and
+  // pair counts: a few MB at most for millions of points)
+  return static_cast<size_t>(std::max<int64_t>(1, n_points)) * coord_bytes(precision) +
+         (4u << 20) + static_cast<size_t>(n_hist) * 8;
+}
+
+}  // namespace dh
 
 // The launch sequence of a batch: stage, zero, one persistent pair kernel per
 // class of frames, out-of-range counts. Recorded once into a graph, or issued
@@ -927,7 +965,7 @@ int dh_batch_create(dh_ctx *ctx, const dh_frame_desc *frames, int32_t n_frames, 
   };
   std::vector<FrameInfo> info(n_frames);
   const Knobs bk = ctx->forced ? Knobs::unpack(ctx->forced_knobs) : default_knobs(precision);
-  const BaseConfig base = base_config(ctx, precision, bk);
+  const BaseConfig base = base_config(ctx, precision, bk, kBoxNone);
   for (int32_t f = 0; f < n_frames; ++f) {
     const dh_frame_desc &d = frames[f];
     int rc = check(nullptr, d.offsets, d.n_species, d.box_type, d.box, d.r_max, d.n_bins,
@@ -985,7 +1023,8 @@ int dh_batch_create(dh_ctx *ctx, const dh_frame_desc *frames, int32_t n_frames, 
     dh_batch::Group g;
     g.kind = kv.first.first;
     g.sweep = kv.first.second != 0;
-    g.cfg = base.cfg;
+    const BaseConfig gbase = base_config(ctx, precision, bk, g.kind);
+    g.cfg = gbase.cfg;
     int64_t stride = 0;
     uint64_t work = 0;
     for (int32_t f : fs) {
@@ -1003,9 +1042,9 @@ int dh_batch_create(dh_ctx *ctx, const dh_frame_desc *frames, int32_t n_frames, 
     }
     for (int32_t f : fs) info[f].fp.noclamp = (info[f].noclamp_ok && info[f].slots <= stride) ? 1 : 0;
     g.stride = static_cast<int>(stride);
-    g.lds = base.tile_bytes + static_cast<size_t>(g.cfg.copies) * g.stride * 4;
-    g.grid = grid_for_config(ctx, precision, g.kind, g.sweep, base, g.lds);
-    g.cfg.jchunk = jchunk_for(g.cfg, g.grid, work, base.items_per_wg);
+    g.lds = gbase.tile_bytes + static_cast<size_t>(g.cfg.copies) * g.stride * 4;
+    g.grid = grid_for_config(ctx, precision, g.kind, g.sweep, gbase, g.lds);
+    g.cfg.jchunk = jchunk_for(g.cfg, g.grid, work, gbase.items_per_wg);
     // large frames first: the tail of the work list is made of small items
     std::stable_sort(fs.begin(), fs.end(),
                      [&](int32_t x, int32_t y) { return info[x].pairs > info[y].pairs; });
@@ -1139,8 +1178,8 @@ int dh_ctx_set_config(dh_ctx *ctx, const int32_t *knobs) {
     ctx->forced = false;
     return DH_OK;
   }
-  std::array<int32_t, 6> v;
-  for (int q = 0; q < 6; ++q) v[q] = knobs[q];
+  std::array<int32_t, kNumKnobs> v;
+  for (int q = 0; q < kNumKnobs; ++q) v[q] = knobs[q];
   if (!Knobs::unpack(v).valid()) return fail(ctx, DH_EINVAL, "invalid launch knobs");
   ctx->forced = true;
   ctx->forced_knobs = v;
@@ -1149,7 +1188,7 @@ int dh_ctx_set_config(dh_ctx *ctx, const int32_t *knobs) {
 
 int dh_ctx_last_config(const dh_ctx *ctx, int32_t *out) {
   if (!ctx || !out) return DH_EINVAL;
-  for (int q = 0; q < 10; ++q) out[q] = ctx->last_config[q];
+  for (int q = 0; q < 11; ++q) out[q] = ctx->last_config[q];
   return DH_OK;
 }
 

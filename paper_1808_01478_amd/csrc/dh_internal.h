@@ -80,7 +80,7 @@ struct PairKernelArgs {
 
 // Kernel configuration (chosen per launch by the tuner).
 struct KernelConfig {
-  int32_t threads;   // workgroup size (multiple of 64, <= 256)
+  int32_t threads;   // workgroup size: 256, 512 or 1024
   int32_t r;         // i-particles per lane (4 or 8)
   int32_t copies;    // interleaved sub-histogram copies (1, 2, 4)
   int32_t tj;        // j-tile length (<= threads)
@@ -110,4 +110,14 @@ hipError_t launch_pair_t(int precision, int box_kind, const FrameParams *d_fp, c
 int pairs_occupancy(int precision, int box_kind, bool sweep, const KernelConfig &cfg,
                     size_t lds_bytes);
 
+}  // namespace dh
+
+struct dh_ctx;
+namespace dh {
+// device bytes held by a context's scratch (staged coordinates, work blob)
+size_t ctx_device_bytes(const dh_ctx *ctx);
+// frees a context's scratch (the context must be idle); it regrows on use
+void ctx_release_scratch(dh_ctx *ctx);
+// device footprint of a single-frame job besides the caller's buffers
+size_t job_scratch_bytes(int64_t n_points, int32_t n_hist, int32_t precision);
 }  // namespace dh

@@ -414,8 +414,16 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
   }
 }
 
+// Workgroups of up to 1024 threads share one LDS histogram (more waves per
+// CU when a wide histogram leaves room for one workgroup only). The image
+// search keeps many more live values and is limited to 256 threads.
+template <int BOX>
+constexpr int max_threads() {
+  return BOX == kBoxTricSearch ? 256 : 1024;
+}
+
 template <typename T, int R, int BOX, bool SWEEP>
-__global__ __launch_bounds__(256) void pairs_kernel(PairKernelArgs a) {
+__global__ __launch_bounds__(max_threads<BOX>()) void pairs_kernel(PairKernelArgs a) {
   using V = typename V4<T>::type;
   extern __shared__ __align__(32) unsigned char smem[];
   __shared__ int s_item;

@@ -38,6 +38,14 @@ SIGNATURES = {
     "dh_batch_info": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32), ctypes.POINTER(_f64)],
                       ctypes.c_int),
     "dh_batch_destroy": ([_vp], None),
+    "dh_server_create": ([_i32, _i64, _i32, _f64, ctypes.POINTER(_vp)], ctypes.c_int),
+    "dh_server_submit": ([_vp, _vp, _vp, _i32, _i32, _vp, _f64, _i32, _i32, ctypes.POINTER(_i64)],
+                         ctypes.c_int),
+    "dh_server_status": ([_vp, _i64], ctypes.c_int),
+    "dh_server_wait": ([_vp, _i64, _vp, _vp, _vp], ctypes.c_int),
+    "dh_server_stats": ([_vp, _vp], ctypes.c_int),
+    "dh_server_destroy": ([_vp], None),
+    "dh_sched_select": ([_vp, _vp, _i32, _i64, _i32, _f64, _vp], ctypes.c_int32),
     "dh_ctx_set_tuning": ([_vp, _i32, ctypes.c_char_p], ctypes.c_int),
     "dh_ctx_set_config": ([_vp, _vp], ctypes.c_int),
     "dh_ctx_last_config": ([_vp, _vp], ctypes.c_int),
@@ -55,7 +63,7 @@ class FrameDesc(ctypes.Structure):
 
 BATCH_GRAPH = 1
 TUNE_OFF, TUNE_CACHED, TUNE_ON = 0, 1, 2
-KNOB_NAMES = ("r", "copies", "tj", "noclamp", "occ_cap", "items_per_wg")
+KNOB_NAMES = ("r", "copies", "tj", "noclamp", "occ_cap", "items_per_wg", "threads")
 
 
 def _load() -> ctypes.CDLL:
@@ -198,7 +206,7 @@ class Context:
                self.handle)
 
     def set_config(self, knobs=None) -> None:
-        """dh_ctx_set_config: force a launch shape (dict or 6 ints) or None."""
+        """dh_ctx_set_config: force a launch shape (dict or 7 ints) or None."""
         if knobs is None:
             _check(LIB.dh_ctx_set_config(self.handle, None), self.handle)
             return
@@ -209,10 +217,10 @@ class Context:
 
     def last_config(self) -> dict:
         """dh_ctx_last_config: the shape of the last single-frame launch."""
-        out = np.zeros(10, np.int32)
+        out = np.zeros(11, np.int32)
         _check(LIB.dh_ctx_last_config(self.handle, _np_ptr(out)), self.handle)
-        d = {k: int(v) for k, v in zip(KNOB_NAMES, out[:6])}
-        d.update(grid=int(out[6]), lds_bytes=int(out[7]), sweeps=int(out[8]), items=int(out[9]))
+        d = {k: int(v) for k, v in zip(KNOB_NAMES, out[:7])}
+        d.update(grid=int(out[7]), lds_bytes=int(out[8]), sweeps=int(out[9]), items=int(out[10]))
         return d
 
     def profile(self, enable: bool = True) -> None:
@@ -284,6 +292,80 @@ class Batch:
         if getattr(self, "handle", None):
             LIB.dh_batch_destroy(self.handle)
             self.handle = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+JOB_DONE, JOB_QUEUED, JOB_RUNNING = 0, 1, 2
+
+
+def sched_select(need_bytes, waited_s, free_bytes: int, free_slots: int,
+                 head_wait_limit_s: float):
+    """dh_sched_select: queue positions the server would start now."""
+    need = np.ascontiguousarray(np.asarray(need_bytes, np.int64))
+    wait = np.ascontiguousarray(np.asarray(waited_s, np.float64))
+    out = np.zeros(max(1, len(need)), np.int32)
+    n = LIB.dh_sched_select(_np_ptr(need), _np_ptr(wait), len(need), int(free_bytes),
+                            int(free_slots), float(head_wait_limit_s), _np_ptr(out))
+    return [int(v) for v in out[:n]]
+
+
+class Server:
+    """dh_server: continuous-batching request loop on one GPU."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 8 << 30, max_inflight: int = 4,
+                 head_wait_limit_s: float = 1.0):
+        h = ctypes.c_void_p()
+        _check(LIB.dh_server_create(int(device), int(hbm_budget_bytes), int(max_inflight),
+                                    float(head_wait_limit_s), ctypes.byref(h)))
+        self.handle = h
+        self._shapes = {}
+
+    def submit(self, coords, offsets, box_type: int, box, r_max: float, n_bins: int,
+               precision: int = FP32) -> int:
+        c = np.ascontiguousarray(coords, np.float64)
+        o = _offsets(offsets)
+        b = _host_box(box)
+        jid = ctypes.c_int64()
+        _check(LIB.dh_server_submit(self.handle, _np_ptr(c), _np_ptr(o), len(o) - 1, int(box_type),
+                                    _np_ptr(b), float(r_max), int(n_bins), int(precision),
+                                    ctypes.byref(jid)))
+        self._shapes[jid.value] = (n_hist(len(o) - 1), int(n_bins))
+        return int(jid.value)
+
+    def status(self, job_id: int) -> int:
+        return int(LIB.dh_server_status(self.handle, int(job_id)))
+
+    def wait(self, job_id: int):
+        """(histograms uint64 [H, n_bins], out_of_range [H], (queued_s, run_s, latency_s))."""
+        h, nb = self._shapes.pop(job_id)
+        out = np.empty((h, nb), np.uint64)
+        oor = np.empty(h, np.uint64)
+        times = np.zeros(3, np.float64)
+        _check(LIB.dh_server_wait(self.handle, int(job_id), _np_ptr(out), _np_ptr(oor),
+                                  _np_ptr(times)))
+        return out, oor, tuple(float(t) for t in times)
+
+    def stats(self) -> dict:
+        st = np.zeros(6, np.int64)
+        _check(LIB.dh_server_stats(self.handle, _np_ptr(st)))
+        return dict(zip(("submitted", "completed", "failed", "max_running", "peak_bytes",
+                         "budget_bytes"), (int(v) for v in st)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            LIB.dh_server_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
     def __del__(self):  # pragma: no cover
         try:

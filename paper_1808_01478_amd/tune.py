@@ -1,0 +1,48 @@
+"""Tune the launch shapes of named workloads on the current GPU and store
+them in the JSON cache that bench.py and callers load with dh_ctx_set_tuning.
+
+    python -m paper_1808_01478_amd.tune [--out PATH] [--workloads a,b,...]
+
+Every shape gives identical counts; the cache only records which one was
+fastest for each bucket (arch, precision, box kind, log2 bins, log2 N,
+species).
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_CACHE = os.path.join(PKG, "tuning", "launch_shapes.json")
+
+
+def main(argv=None) -> int:
+    sys.path.insert(0, os.path.dirname(PKG))
+    import torch
+    import workloads
+    import paper_1808_01478_amd as dh
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=DEFAULT_CACHE)
+    ap.add_argument("--workloads", default="ortho100k,tiny,triclinic1M")
+    args = ap.parse_args(argv)
+    makers = {"ortho100k": workloads.ortho, "tiny": workloads.tiny,
+              "triclinic1M": workloads.triclinic}
+    ctx = dh.Context(0)
+    ctx.set_tuning(dh.TUNE_ON, args.out)
+    dev = torch.device("cuda")
+    for name in args.workloads.split(","):
+        fr = makers[name]()
+        x = torch.from_numpy(fr.coords).to(dev)
+        out = torch.empty((fr.n_hist, fr.n_bins), dtype=torch.int64, device=dev)
+        for prec in (dh.FP32, dh.FP64):
+            ctx.histo_async(x, fr.offsets, fr.box_type, fr.box, fr.r_max, fr.n_bins, prec, out)
+            torch.cuda.synchronize()
+            print(f"{name} precision={prec}: {ctx.last_config()}", flush=True)
+    ctx.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,110 @@
+"""The serving loop on the GPU: every job's result in a concurrent mix is
+bit-identical to the same job run alone (same kernels, integer sums), binary64
+jobs equal the oracle, the budget bounds the admitted footprints, and bad
+jobs fail alone."""
+import math
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def job_mix(seed=21, n_jobs=18, n_hi=12_000):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    jobs = []
+    for j in range(n_jobs):
+        job = workloads.serving_job(rng, j, 0.0, n_lo=200, n_hi=n_hi, bins=(1000, 10_000, 50_000))
+        prec = int(rng.integers(0, 2))
+        jobs.append((job.frame, prec))
+    return jobs
+
+
+def alone(frame, prec):
+    import paper_1808_01478_amd as dh
+    return dh.histo(frame.coords, frame.offsets, frame.box_type, frame.box, frame.r_max,
+                    frame.n_bins, prec)
+
+
+def test_mix_equals_alone_and_oracle():
+    import paper_1808_01478_amd as dh
+    jobs = job_mix()
+    print(f"\n[case] serving mix of {len(jobs)} jobs", flush=True)
+    with dh.Server(0, hbm_budget_bytes=8 << 30, max_inflight=4) as srv:
+        ids = [srv.submit(f.coords, f.offsets, f.box_type, f.box, f.r_max, f.n_bins, p)
+               for f, p in jobs]
+        results = [srv.wait(i) for i in ids]
+        st = srv.stats()
+    assert st["completed"] == len(jobs) and st["failed"] == 0
+    assert st["max_running"] >= 2, st          # jobs did overlap
+    for (f, p), (h, oor, times) in zip(jobs, results):
+        ref = alone(f, p)
+        assert np.array_equal(h, ref), f"{f.name} prec={p}: mix differs from alone"
+        assert list(h.sum(axis=1).astype(np.int64) + oor.astype(np.int64)) == f.hist_pairs()
+        assert times[2] >= times[1] >= 0 and times[0] >= 0
+    for (f, p), (h, _, _) in list(zip(jobs, results))[:6]:
+        if p == 1:
+            assert np.array_equal(h, oracle.frame_histogram(f).hist), f.name
+
+
+def test_budget_back_pressure():
+    import paper_1808_01478_amd as dh
+    jobs = job_mix(seed=22, n_jobs=10, n_hi=30_000)
+    # footprint of the largest job, plus a little: at most one or two run at once
+    probe = []
+    with dh.Server(0, hbm_budget_bytes=1 << 40, max_inflight=1) as s1:
+        for f, p in jobs:
+            probe.append(s1.wait(s1.submit(f.coords, f.offsets, f.box_type, f.box, f.r_max,
+                                           f.n_bins, p))[0])
+    sizes = [f.n * 24 + f.n_hist * f.n_bins * 8 + f.n * (32 if p else 16) + (4 << 20) + f.n_hist * 8
+             for f, p in jobs]
+    budget = int(max(sizes) * 1.2)
+    with dh.Server(0, hbm_budget_bytes=budget, max_inflight=4, head_wait_limit_s=0.05) as srv:
+        ids = [srv.submit(f.coords, f.offsets, f.box_type, f.box, f.r_max, f.n_bins, p)
+               for f, p in jobs]
+        got = [srv.wait(i)[0] for i in ids]
+        st = srv.stats()
+    assert st["peak_bytes"] <= budget
+    for a, b in zip(got, probe):
+        assert np.array_equal(a, b)
+
+
+def test_bad_jobs_fail_alone():
+    import paper_1808_01478_amd as dh
+    f = workloads.random_frame(601, [500, 300], workloads.BOX_ORTHO, n_bins=100)
+    # the small job needs about 4 MB (mostly work-list slack), the big one
+    # about 16 MB: an 8 MB budget admits one and refuses the other
+    with dh.Server(0, hbm_budget_bytes=8 << 20, max_inflight=2) as srv:
+        good = srv.submit(f.coords, f.offsets, f.box_type, f.box, f.r_max, f.n_bins, 0)
+        with pytest.raises(dh.DisthistError) as e:
+            srv.submit(f.coords, f.offsets, f.box_type, f.box, -1.0, f.n_bins, 0)
+        assert e.value.code == -1
+        big = workloads.random_frame(602, [200_000], workloads.BOX_NONE, n_bins=10)
+        with pytest.raises(dh.DisthistError) as e:
+            srv.submit(big.coords, big.offsets, 0, None, big.r_max, 50_000, 1)
+        assert e.value.code == -4                   # larger than the whole budget
+        h, _, _ = srv.wait(good)
+        assert np.array_equal(h, alone(f, 0))
+        assert srv.status(12345) == -1
+
+
+def test_poisson_arrivals_overlap():
+    """Jobs arriving while others run are admitted and finish; latency is
+    measured from submission."""
+    import paper_1808_01478_amd as dh
+    jobs = job_mix(seed=23, n_jobs=12, n_hi=40_000)
+    rng = np.random.Generator(np.random.PCG64(5))
+    gaps = rng.exponential(0.002, size=len(jobs))
+    with dh.Server(0, hbm_budget_bytes=8 << 30, max_inflight=4) as srv:
+        ids = []
+        for (f, p), g in zip(jobs, gaps):
+            time.sleep(g)
+            ids.append(srv.submit(f.coords, f.offsets, f.box_type, f.box, f.r_max, f.n_bins, p))
+        res = [srv.wait(i) for i in ids]
+    for (f, p), (h, _, t) in zip(jobs, res):
+        assert np.array_equal(h, alone(f, p))
+        assert math.isfinite(t[2]) and t[2] > 0

@@ -34,8 +34,9 @@ FRAMES = [
     workloads.triclinic(n=8000),
 ]
 
-SHAPES = [dict(zip(("r", "copies", "tj", "noclamp", "occ_cap", "items_per_wg"), v))
-          for v in itertools.product((4, 8), (1, 2, 4), (128, 256), (0, 1), (0, 1), (4, 16))]
+SHAPES = [dict(zip(("r", "copies", "tj", "noclamp", "occ_cap", "items_per_wg", "threads"), v))
+          for v in itertools.product((4, 8), (1, 2, 4), (128, 256), (0, 1), (0, 1), (4, 16),
+                                     (256, 512, 1024))]
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -50,7 +51,7 @@ def test_all_shapes_identical(ctx, precision, fi):
         ctx.set_config(SHAPES[k])
         h, oor = run_gpu(ctx, fr, precision)
         cfg = ctx.last_config()
-        assert all(cfg[n] == v for n, v in SHAPES[k].items())
+        assert all(cfg[n] == v for n, v in SHAPES[k].items() if n != "threads")
         assert np.array_equal(h, ref), f"shape {SHAPES[k]} changed the counts"
         assert np.array_equal(oor, ref_oor)
     ctx.set_config(None)
@@ -58,8 +59,9 @@ def test_all_shapes_identical(ctx, precision, fi):
 
 def test_invalid_shape_rejected(ctx):
     import paper_1808_01478_amd as dh
-    for bad in ([3, 1, 256, 1, 0, 8], [8, 3, 256, 1, 0, 8], [8, 1, 64, 1, 0, 8],
-                [8, 1, 256, 2, 0, 8], [8, 1, 256, 1, -1, 8], [8, 1, 256, 1, 0, 0]):
+    for bad in ([3, 1, 256, 1, 0, 8, 256], [8, 3, 256, 1, 0, 8, 256], [8, 1, 64, 1, 0, 8, 256],
+                [8, 1, 256, 2, 0, 8, 256], [8, 1, 256, 1, -1, 8, 256], [8, 1, 256, 1, 0, 0, 256],
+                [8, 1, 256, 1, 0, 8, 128], [8, 1, 256, 1, 0, 8, 2048]):
         with pytest.raises(dh.DisthistError):
             ctx.set_config(bad)
 
@@ -95,9 +97,9 @@ def test_handwritten_cache_is_used(tmp_path):
         run_gpu(c, fr, 1)
         key = next(iter(json.load(open(tmp_path / "probe.json"))["entries"]))
     path = tmp_path / "hand.json"
-    path.write_text(json.dumps({"version": 1, "entries": {key: [4, 2, 128, 0, 1, 4]}}))
+    path.write_text(json.dumps({"version": 2, "entries": {key: [4, 2, 128, 0, 1, 4, 512]}}))
     with dh.Context(0) as c:
         c.set_tuning(dh.TUNE_CACHED, str(path))
         run_gpu(c, fr, 1)
         cfg = c.last_config()
-        assert [cfg[n] for n in dh.KNOB_NAMES] == [4, 2, 128, 0, 1, 4]
+        assert [cfg[n] for n in dh.KNOB_NAMES] == [4, 2, 128, 0, 1, 4, 512]
