@@ -19,6 +19,7 @@
 #include "dh_internal.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace dh {
 namespace {
@@ -71,6 +72,27 @@ __device__ __forceinline__ Geo64 load_geo64(const FrameParams *F) {
   return g;
 }
 
+// Correctly rounded binary64 square root. Fast path: Goldschmidt's coupled
+// iteration for sqrt(q) and 1/(2 sqrt(q)) started from v_rsq_f64, then two
+// Newton corrections of the root with fused residuals (the Markstein-style
+// final step that yields the correctly rounded result). It needs q to be
+// normal and not tiny (no range scaling), so a wave in which any lane has
+// q < 2^-767, q = 0 or a NaN takes the library sqrt instead (which applies
+// the same iteration to a scaled input). Identical results either way.
+__device__ __forceinline__ double sqrt_rn(double q) {
+  if (__builtin_amdgcn_ballot_w64(!(q >= 0x1p-767)) != 0) return sqrt(q);
+  const double y = __builtin_amdgcn_rsq(q);
+  double g = q * y;
+  double h = 0.5 * y;
+  const double r = fma(-h, g, 0.5);
+  h = fma(h, r, h);
+  g = fma(g, r, g);
+  double d = fma(-g, g, q);
+  g = fma(d, h, g);
+  d = fma(-g, g, q);
+  return fma(d, h, g);
+}
+
 template <int BOX>
 __device__ __forceinline__ double t64(double xi, double yi, double zi, double xj, double yj,
                                       double zj, const Geo64 &g) {
@@ -99,7 +121,7 @@ __device__ __forceinline__ double t64(double xi, double yi, double zi, double xj
       q = v < q ? v : q;
     }
   }
-  return sqrt(q) * g.s;  // correctly rounded sqrt (default HIP lowering)
+  return sqrt_rn(q) * g.s;
 }
 
 // binary32. Without a box the staged coordinates are x * s, so the
@@ -129,13 +151,34 @@ __device__ __forceinline__ float frac_diff(float ui, float uj) {
 }
 
 template <int BOX>
+__device__ __forceinline__ float t32_packed(uint64_t ab_j, uint64_t neg_ab_i, float zi, float zj,
+                                            const Geo32 &g);
+
+template <int BOX>
 __device__ __forceinline__ float t32(float xi, float yi, float zi, float xj, float yj, float zj,
                                      const Geo32 &g) {
   if constexpr (BOX == kBoxNone) {
     const float dx = xj - xi, dy = yj - yi, dz = zj - zi;
     return __builtin_amdgcn_sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));  // v_sqrt_f32
   } else {
-    const float fa = frac_diff(xi, xj), fb = frac_diff(yi, yj), fc = frac_diff(zi, zj);
+    const uint64_t ai = (static_cast<uint64_t>(__float_as_uint(yi)) << 32) | __float_as_uint(xi);
+    const uint64_t aj = (static_cast<uint64_t>(__float_as_uint(yj)) << 32) | __float_as_uint(xj);
+    return t32_packed<BOX>(aj, 0ull - ai, zi, zj, g);
+  }
+}
+
+// Periodic binary32 distance from packed fractional words: ab = (b << 32) | a
+// of particle j and -(b << 32 | a) of particle i. One 64-bit addition gives
+// both differences: the low word exactly, the high word lowered by one unit
+// (2^-32 of a cell vector, far below binary32 rounding) when a borrows.
+template <int BOX>
+__device__ __forceinline__ float t32_packed(uint64_t ab_j, uint64_t neg_ab_i, float zi, float zj,
+                                            const Geo32 &g) {
+  {
+    const uint64_t dab = ab_j + neg_ab_i;
+    const float fa = static_cast<float>(static_cast<int32_t>(static_cast<uint32_t>(dab)));
+    const float fb = static_cast<float>(static_cast<int32_t>(static_cast<uint32_t>(dab >> 32)));
+    const float fc = frac_diff(zi, zj);
     if constexpr (BOX == kBoxCube) {
       return __builtin_amdgcn_sqrtf(fmaf(fc, fc, fmaf(fb, fb, fa * fa))) * g.kx;
     } else if constexpr (BOX == kBoxOrtho) {
@@ -326,6 +369,10 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
   const int win = uni(F->win);
   const int b_lo = w.sweep * win;
   const int log_copies = a.copies == 4 ? 2 : (a.copies == 2 ? 1 : 0);
+  const uint32_t shift_bytes = static_cast<uint32_t>(log_copies + 2);
+  char *const my_bytes = reinterpret_cast<char *>(my);
+  // canonical once here, so fmin below needs no per-pair canonicalisation
+  const double cap64 = __builtin_canonicalize(static_cast<double>(a.stride - 1));
 
   // i-particles: wave w holds [wbase, wbase + 64R), lane l the R values
   // wbase + r*64 + l
@@ -341,6 +388,16 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
     const V p = X[ok ? i : w.i0];
     xi[r] = p.x; yi[r] = p.y; zi[r] = p.z;
     lo[r] = ok ? 0u : hi;
+  }
+  // -(b:a) of each i-particle for the packed periodic binary32 difference
+  uint64_t nab[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if constexpr (sizeof(T) == 4)
+      nab[r] = 0ull - ((static_cast<uint64_t>(__float_as_uint(yi[r])) << 32) |
+                       __float_as_uint(xi[r]));
+    else
+      nab[r] = 0ull;
   }
   float lof[R];
   const float hif = static_cast<float>(hi);
@@ -366,14 +423,40 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
     if constexpr (DIAG) js = max(0, min(jcount, wbase + 1 - jt));
     if (wave_active && js < jcount) {
       const V *__restrict__ tb = tile + buf * tj;
+      // periodic binary32: j as its packed (b:a) word plus c (see t32_packed)
+      constexpr bool kPacked = sizeof(T) == 4 && BOX != kBoxNone;
+      struct JPacked {
+        uint64_t ab;
+        float z;
+      };
+      using J = typename std::conditional<kPacked, JPacked, V>::type;
+      const uint64_t *__restrict__ tb64 = reinterpret_cast<const uint64_t *>(tb);
+      const float *__restrict__ tbf = reinterpret_cast<const float *>(tb);
+      auto load_j = [&](int k) -> J {
+        if constexpr (kPacked)
+          return JPacked{tb64[2 * k], tbf[4 * k + 2]};
+        else
+          return tb[k];
+      };
       // R pairs of one j: distance, bin, one LDS atomic each
-      auto pairs_of = [&](const V &pj, int j) {
+      auto pairs_of = [&](const J &pj, int j) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const T t = pair_t<T, BOX>(xi[r], yi[r], zi[r], pj.x, pj.y, pj.z, g);
+          T t;
+          if constexpr (kPacked)
+            t = t32_packed<BOX>(pj.ab, nab[r], zi[r], pj.z, g);
+          else
+            t = pair_t<T, BOX>(xi[r], yi[r], zi[r], pj.x, pj.y, pj.z, g);
           uint32_t idx;
           if constexpr (!CLAMP) {
-            idx = static_cast<uint32_t>(t);
+            if constexpr (sizeof(T) == 4) {
+              // fixed-point staging bounds every binary32 t below the stride
+              idx = static_cast<uint32_t>(t);
+            } else {
+              // binary64 reads raw device coordinates: cap t so that even
+              // non-finite or absurd input stays inside the LDS histogram
+              idx = static_cast<uint32_t>(fmin(t, cap64));
+            }
           } else if constexpr (sizeof(T) == 4 && !SWEEP) {
             float l = lof[r];
             if constexpr (DIAG) l = (j > wbase + r * 64 + lane) ? l : hif;
@@ -389,23 +472,25 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
             if constexpr (SWEEP) idx -= static_cast<uint32_t>(b_lo);
             idx = max(min(idx, hi), l);
           }
-          atomicAdd(my + (idx << log_copies), 1u);
+          // byte offset with one shift (copies interleaved bin-major), so the
+          // address is a single v_lshl_add_u32
+          atomicAdd(reinterpret_cast<uint32_t *>(my_bytes + (idx << shift_bytes)), 1u);
         }
       };
       // Ping-pong over two j registers: the read of the next j is issued
       // before the current j's atomics. LDS operations complete in order, so
       // a read issued after the atomics would wait for all of them
       // (bank-conflicted) before the arithmetic could start.
-      V pa = tb[js];
+      J pa = load_j(js);
       __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
       int jj = js;
       for (; jj + 1 < jcount; jj += 2) {
-        const V pb = tb[jj + 1];
+        const J pb = load_j(jj + 1);
         // binary32: pin the read ahead of the atomics (measured faster);
         // binary64 has enough arithmetic per j to hide it unpinned
         if constexpr (sizeof(T) == 4) __builtin_amdgcn_sched_barrier(0);
         pairs_of(pa, jt + jj);
-        pa = tb[min(jj + 2, jcount - 1)];
+        pa = load_j(min(jj + 2, jcount - 1));
         if constexpr (sizeof(T) == 4) __builtin_amdgcn_sched_barrier(0);
         pairs_of(pb, jt + jj + 1);
       }

@@ -183,3 +183,30 @@ def test_sqrt_exact_on_perfect_squares(ctx):
     sq = np.array([math.isqrt(int(v)) for v in q])
     perfect = sq * sq == q
     assert np.array_equal(got[perfect], sq[perfect].astype(np.float64))
+
+
+def test_sqrt_wide_range_and_mixed_waves(ctx):
+    """binary64 per-pair t against the oracle for squared distances from
+    1e-300 to 1e300: waves mix lanes that take the fast square root with
+    lanes that need the library path (tiny, zero), and every result must be
+    bit-identical to the correctly rounded oracle."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(17))
+    m = 1 << 16
+    mant = rng.uniform(1.0, 2.0, size=(m, 3))
+    expo = rng.integers(-500, 500, size=(m, 1))
+    pts = np.ldexp(mant * rng.choice([-1.0, 1.0], size=(m, 3)), expo)
+    pts[rng.random(m) < 0.05] = 0.0                      # exact zeros: q = 0
+    coords = np.concatenate([np.zeros((1, 3)), pts])
+    pi = np.zeros(m, np.int64)
+    pj = np.arange(1, m + 1, dtype=np.int64)
+    r_max, n_bins = 1.0, 1 << 20
+    ref = oracle.pair_t(coords, 0, None, r_max, n_bins, pi, pj)
+    dev = torch.device("cuda")
+    t = torch.empty(m, dtype=torch.float64, device=dev)
+    ctx.pair_t_async(torch.from_numpy(coords).to(dev), 0, None, r_max, n_bins, 1,
+                     torch.from_numpy(pi.astype(np.int32)).to(dev),
+                     torch.from_numpy(pj.astype(np.int32)).to(dev), t)
+    torch.cuda.synchronize()
+    got = t.cpu().numpy()
+    assert np.array_equal(got, ref, equal_nan=True), f"{int((got != ref).sum())} differ"
