@@ -122,6 +122,22 @@ def time_path(ctx, frame, precision, steps, warmup):
     }
 
 
+def time_host_buffers(frame, precision, steps):
+    """Synchronous dh_histo from host memory: the host-to-device copy of the
+    coordinates, the whole path and the copy of the histograms back."""
+    import paper_1808_01478_amd as dh
+    args = (frame.coords, frame.offsets, frame.box_type, frame.box, frame.r_max, frame.n_bins,
+            precision)
+    dh.histo(*args)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        h = dh.histo(*args)
+    t1 = time.perf_counter()
+    assert int(h.sum()) <= frame.total_pairs()
+    return {"value": frame.total_pairs() * steps / (t1 - t0), "unit": "pairs/s",
+            "steps": steps, "ms_per_step": (t1 - t0) * 1e3 / steps}
+
+
 def bench_trajectory(ctx, n_frames: int, steps: int):
     """The trajectory workload (512 orthorhombic frames, N log-uniform in
     [1e4, 2e5], 1-4 species, 4,096 bins) in binary32: one batched graph
@@ -299,6 +315,11 @@ def main():
         # on the first warm-up call
         from paper_1808_01478_amd.tune import DEFAULT_CACHE
         ctx.set_tuning(dh.TUNE_ON, DEFAULT_CACHE if os.path.exists(DEFAULT_CACHE) else None)
+        # the library-owned context of the synchronous entry point reads its
+        # tuning mode from the environment when it is created
+        if os.path.exists(DEFAULT_CACHE):
+            os.environ.setdefault("DH_TUNE", str(dh.TUNE_CACHED))
+            os.environ.setdefault("DH_TUNE_CACHE", DEFAULT_CACHE)
     r32 = time_path(ctx, frame, dh.FP32, args.steps, max(1, args.warmup))
     shape32 = ctx.last_config()
     fp64_steps = args.fp64_steps if args.fp64_steps is not None else max(1, args.steps // 2)
@@ -357,6 +378,8 @@ def main():
         },
         "cpu_baseline": None,
     }
+    # PCIe-inclusive rate of the synchronous host-buffer entry point
+    line["host_buffers"] = time_host_buffers(frame, dh.FP32, max(1, args.steps // 4))
     if args.serving_jobs > 0:
         line["serving"] = bench_serving(args.serving_jobs)
         line["latency_ms"]["serving_p50"] = line["serving"]["continuous_batching"]["p50_ms"]
