@@ -138,6 +138,41 @@ def time_host_buffers(frame, precision, steps):
             "steps": steps, "ms_per_step": (t1 - t0) * 1e3 / steps}
 
 
+def bench_wide(frame, bins=(250_000, 1_000_000, 4_000_000), steps=3):
+    """Histograms wider than LDS on the bench frame, binary32: LDS bin windows
+    against uint64 global atomics, and which one the default shape takes."""
+    import torch
+    import paper_1808_01478_amd as dh
+    dev = torch.device("cuda")
+    x = torch.from_numpy(frame.coords).to(dev)
+    rows = []
+    with dh.Context(0) as c:
+        for nb in bins:
+            out = torch.empty((frame.n_hist, nb), dtype=torch.int64, device=dev)
+            row = {"n_bins": nb}
+            for label, knobs in (("default", None), ("lds_windows", 0), ("global_atomics", 1)):
+                if knobs is None:
+                    c.set_config(None)
+                else:
+                    c.set_config(dict(r=8, copies=1, tj=256, noclamp=1, occ_cap=0,
+                                      items_per_wg=8, threads=0, wide=knobs))
+                args = (x, frame.offsets, frame.box_type, frame.box, frame.r_max, nb, dh.FP32, out)
+                c.histo_async(*args)
+                torch.cuda.synchronize()
+                c.profile(True)
+                for _ in range(steps):
+                    c.histo_async(*args)
+                ms, n = c.profile_read()
+                c.profile(False)
+                cfg = c.last_config()
+                row[label] = {"kernel_ms": ms / n, "pairs_per_s": frame.total_pairs() / (ms / n * 1e-3),
+                              "mode": ["lds", "lds_windows", "global_atomics"][cfg["mode"]],
+                              "windows": cfg["sweeps"], "threads": cfg["threads"]}
+            rows.append(row)
+        c.set_config(None)
+    return {"workload": "ortho100k frame with wider histograms, binary32", "rows": rows}
+
+
 def bench_trajectory(ctx, n_frames: int, steps: int):
     """The trajectory workload (512 orthorhombic frames, N log-uniform in
     [1e4, 2e5], 1-4 species, 4,096 bins) in binary32: one batched graph
@@ -297,6 +332,8 @@ def main():
                     help="built-in launch shape instead of tuning on the first warm-up call")
     ap.add_argument("--trajectory-frames", type=int, default=512,
                     help="frames of the batched trajectory comparison (0 = skip)")
+    ap.add_argument("--no-wide", dest="wide", action="store_false",
+                    help="skip the wide-histogram comparison")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the histogram of a frame runs on a single "
@@ -384,6 +421,8 @@ def main():
         line["serving"] = bench_serving(args.serving_jobs)
         line["latency_ms"]["serving_p50"] = line["serving"]["continuous_batching"]["p50_ms"]
         line["latency_ms"]["serving_p99"] = line["serving"]["continuous_batching"]["p99_ms"]
+    if args.wide:
+        line["wide"] = bench_wide(frame)
     if args.trajectory_frames > 0:
         line["trajectory"] = bench_trajectory(ctx, args.trajectory_frames, max(1, args.steps // 5))
     if not args.no_cpu_baseline:

@@ -298,9 +298,11 @@ int32_t dh_sched_select(const int64_t *need_bytes, const double *waited_s, int32
 /* ---------------------------------------------------------------------------
  * Launch tuning. The launch shape of a frame (i-particles per lane, LDS
  * sub-histogram copies, j-tile length, unclamped interior blocks, workgroups
- * per CU, work items per workgroup, workgroup size) changes speed only: every shape gives
- * the same counts (the paper picks its block size and kernel by fixed
- * heuristics, Sec. 3.2.4 and Sec. 4.2).
+ * per CU, work items per workgroup, workgroup size, and for histograms wider
+ * than LDS the choice between LDS bin windows and uint64 global atomics)
+ * changes speed only: every shape gives the same counts (the paper picks its
+ * block size by fixed heuristics, Sec. 3.2.4, and its shared- or
+ * global-memory kernel by the number of bins, Sec. 4.2).
  *
  *   DH_TUNE_OFF     built-in defaults
  *   DH_TUNE_CACHED  use cached shapes, never measure
@@ -317,18 +319,24 @@ int32_t dh_sched_select(const int64_t *need_bytes, const double *waited_s, int32
 int dh_ctx_set_tuning(dh_ctx *ctx, int32_t mode, const char *cache_path);
 
 /*
- * Forces a launch shape for every later call on ctx (NULL restores tuning):
- * knobs[7] = {r (4|8), copies (1|2|4), tj (128|256), noclamp (0|1),
+ * Forces a launch shape for every later call on ctx and for batches created
+ * on it (NULL restores tuning):
+ * knobs[8] = {r (4|8), copies (1|2|4), tj (128|256), noclamp (0|1),
  * occ_cap (0..16, 0 = as many as fit), items_per_wg (1..64),
- * threads (256|512|1024; the 27-image search always runs 256)}.
+ * threads (256|512|1024, or 0 = 1024 when one 256-thread workgroup fills a
+ * CU's LDS and 256 otherwise; the 27-image search always runs 256),
+ * wide (0..65536: count with uint64 global atomics instead of LDS
+ * sub-histograms when the histogram would need at least this many LDS bin
+ * windows; 0 = never, 1 = always)}.
  * Invalid knob values give DH_EINVAL.
  */
 int dh_ctx_set_config(dh_ctx *ctx, const int32_t *knobs);
 
 /*
- * The shape of the last single-frame launch on ctx: out[11] = the first six
- * knobs, the workgroup size launched, the grid size, LDS bytes per
- * workgroup, bin-window sweeps, work items.
+ * The shape of the last single-frame launch on ctx: out[13] = the first six
+ * knobs, the workgroup size launched, the wide knob, the grid size, LDS
+ * bytes per workgroup, bin-window sweeps, work items, and the accumulation
+ * mode (0 LDS histogram, 1 LDS bin windows, 2 global atomics).
  */
 int dh_ctx_last_config(const dh_ctx *ctx, int32_t *out);
 

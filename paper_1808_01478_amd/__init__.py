@@ -9,7 +9,7 @@ no CPU fallback).
 _EXPORTS = (
     "BOX_NONE", "BOX_ORTHO", "BOX_TRICLINIC", "FP32", "FP64", "Batch", "Context", "DisthistError",
     "LIB_PATH", "KNOB_NAMES", "Server", "sched_select", "TUNE_CACHED", "TUNE_OFF", "TUNE_ON", "check_args",
-    "exported_symbols", "histo", "n_hist", "version",
+    "exported_symbols", "histo", "n_hist", "version", "MODE_LDS", "MODE_SWEEP", "MODE_GLOBAL",
 )
 __all__ = list(_EXPORTS)
 

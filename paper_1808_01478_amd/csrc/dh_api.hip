@@ -42,10 +42,10 @@ struct dh_ctx {
   // launch tuning (see dh_ctx_set_tuning)
   int tune_mode = 0;
   std::string tune_path;
-  std::map<std::string, std::array<int32_t, 7>> tune_cache;   // launch knobs per bucket
+  std::map<std::string, std::array<int32_t, 8>> tune_cache;   // launch knobs per bucket
   bool forced = false;
-  std::array<int32_t, 7> forced_knobs{};
-  std::array<int32_t, 11> last_config{};
+  std::array<int32_t, 8> forced_knobs{};
+  std::array<int32_t, 13> last_config{};
   // kernel timing: event pairs recorded around pair-kernel launches
   bool profile = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
@@ -55,7 +55,7 @@ struct dh_ctx {
 struct dh_batch {
   struct Group {
     int kind = 0;
-    bool sweep = false;
+    int mode = kModeLds;
     KernelConfig cfg{};
     int stride = 0, grid = 0;
     size_t lds = 0;
@@ -210,6 +210,7 @@ double t_bound(const FrameParams &fp) {
 
 struct Launch {
   KernelConfig cfg;
+  int mode = kModeLds;
   int win = 0, n_sweeps = 1, stride = 0, grid = 0;
   bool noclamp = false;
   size_t lds = 0;
@@ -219,7 +220,16 @@ size_t coord_bytes(int precision) { return precision == DH_FP64 ? 32 : 16; }
 
 // Launch shape for one frame (heuristic defaults).
 // Launch knobs. Every choice yields identical counts; they only change speed.
-constexpr int kNumKnobs = 7;
+constexpr int kNumKnobs = 8;
+
+// Bin windows from which the global-atomic kernel replaces LDS windows when
+// no tuned shape says otherwise. Measured on MI355X (100k points, periodic
+// cube, half the pairs in range): a binary32 window pass costs about 2.2 ms
+// and a binary64 one about 5.5 ms, while uint64 global atomics run at about
+// 2.4e10 per second whatever the bin count, so global atomics pay off from
+// about 50 windows (binary32) and 20 windows (binary64).
+constexpr int32_t kWideDefault32 = 48;
+constexpr int32_t kWideDefault64 = 20;
 
 struct Knobs {
   int32_t r = 8;             // i-particles per lane: 4 or 8
@@ -228,21 +238,27 @@ struct Knobs {
   int32_t noclamp = 1;       // allow unclamped interior blocks
   int32_t occ_cap = 0;       // workgroups per CU at most (0: as many as fit)
   int32_t items_per_wg = 8;  // work items per workgroup (sets the j-chunk)
-  int32_t threads = 256;     // workgroup size: 256, 512 or 1024
+  // workgroup size: 256, 512 or 1024; 0 = 1024 when only one workgroup of
+  // 256 fits per CU (a wide LDS histogram), else 256
+  int32_t threads = 0;
+  // global-atomic kernel when the LDS plan needs at least this many bin
+  // windows (0: never, 1: always)
+  int32_t wide = kWideDefault32;
   std::array<int32_t, kNumKnobs> pack() const {
-    return {r, copies, tj, noclamp, occ_cap, items_per_wg, threads};
+    return {r, copies, tj, noclamp, occ_cap, items_per_wg, threads, wide};
   }
   static Knobs unpack(const std::array<int32_t, kNumKnobs> &v) {
     Knobs k;
     k.r = v[0]; k.copies = v[1]; k.tj = v[2]; k.noclamp = v[3]; k.occ_cap = v[4];
-    k.items_per_wg = v[5]; k.threads = v[6];
+    k.items_per_wg = v[5]; k.threads = v[6]; k.wide = v[7];
     return k;
   }
   bool valid() const {
     return (r == 4 || r == 8) && (copies == 1 || copies == 2 || copies == 4) &&
            (tj == 128 || tj == 256) && (noclamp == 0 || noclamp == 1) && occ_cap >= 0 &&
            occ_cap <= 16 && items_per_wg >= 1 && items_per_wg <= 64 &&
-           (threads == 256 || threads == 512 || threads == 1024);
+           (threads == 0 || threads == 256 || threads == 512 || threads == 1024) && wide >= 0 &&
+           wide <= 65536;
   }
 };
 
@@ -251,6 +267,7 @@ Knobs default_knobs(int precision) {
   if (precision == DH_FP64) {
     k.r = 4;
     k.tj = 128;
+    k.wide = kWideDefault64;
   }
   return k;
 }
@@ -268,8 +285,9 @@ struct BaseConfig {
 BaseConfig base_config(const dh_ctx *ctx, int precision, const Knobs &k, int kind) {
   BaseConfig b;
   KernelConfig &c = b.cfg;
-  // the image-search kernels are built for at most 256 threads
-  c.threads = kind == kBoxTricSearch ? 256 : k.threads;
+  // the image-search kernels are built for at most 256 threads; "auto" is
+  // resolved by resolve_threads once the LDS size is known
+  c.threads = kind == kBoxTricSearch ? 256 : (k.threads ? k.threads : 256);
   c.r = k.r;
   c.copies = k.copies;
   c.tj = k.tj;
@@ -294,9 +312,20 @@ int32_t jchunk_for(const KernelConfig &c, int grid, uint64_t work, int items_per
   return static_cast<int32_t>(jc);
 }
 
-int grid_for_config(const dh_ctx *ctx, int precision, int kind, bool sweep, const BaseConfig &b,
-                    size_t lds) {
-  int occ = pairs_occupancy(precision, kind, sweep, b.cfg, lds);
+// Workgroup size "auto": one workgroup of 256 threads per CU leaves each
+// SIMD a single wave, so take 1024 threads when the LDS histogram admits no
+// second workgroup.
+void resolve_threads(int precision, int kind, int mode, const Knobs &k, size_t lds,
+                     KernelConfig &cfg) {
+  if (k.threads != 0 || kind == kBoxTricSearch) return;
+  KernelConfig c256 = cfg;
+  c256.threads = 256;
+  cfg.threads = pairs_occupancy(precision, kind, mode, c256, lds) <= 1 ? 1024 : 256;
+}
+
+int grid_for_config(const dh_ctx *ctx, int precision, int kind, int mode, const BaseConfig &b,
+                    size_t lds, const KernelConfig &cfg) {
+  int occ = pairs_occupancy(precision, kind, mode, cfg, lds);
   if (b.occ_cap > 0) occ = std::min(occ, b.occ_cap);
   return ctx->n_cu * std::max(1, occ);
 }
@@ -315,6 +344,19 @@ Launch choose_launch(const dh_ctx *ctx, int precision, const FrameParams &fp,
     L.n_sweeps = static_cast<int>((n_bins + b.win_max - 1) / b.win_max);
     L.win = (n_bins + L.n_sweeps - 1) / L.n_sweeps;
   }
+  if (k.wide > 0 && L.n_sweeps >= k.wide) {
+    // one pass, uint64 atomics into the output; LDS holds the j-tiles only
+    L.mode = kModeGlobal;
+    L.n_sweeps = 1;
+    L.win = n_bins;
+    L.stride = 0;
+    L.lds = b.tile_bytes;
+    resolve_threads(precision, fp.box, L.mode, k, L.lds, L.cfg);
+    L.grid = grid_for_config(ctx, precision, fp.box, L.mode, b, L.lds, L.cfg);
+    L.cfg.jchunk = jchunk_for(L.cfg, L.grid, total_pairs, b.items_per_wg);
+    return L;
+  }
+  L.mode = L.n_sweeps > 1 ? kModeSweep : kModeLds;
   L.stride = L.win + kDump;
   // Without clamping, every t of a periodic frame must index a slot below the
   // stride: slots = floor(bound * (1 + 1e-4)) + 2 covers the rounding of the
@@ -329,7 +371,8 @@ Launch choose_launch(const dh_ctx *ctx, int precision, const FrameParams &fp,
     }
   }
   L.lds = b.tile_bytes + static_cast<size_t>(L.cfg.copies) * L.stride * 4;
-  L.grid = grid_for_config(ctx, precision, fp.box, L.n_sweeps > 1, b, L.lds);
+  resolve_threads(precision, fp.box, L.mode, k, L.lds, L.cfg);
+  L.grid = grid_for_config(ctx, precision, fp.box, L.mode, b, L.lds, L.cfg);
   L.cfg.jchunk = jchunk_for(L.cfg, L.grid, total_pairs * static_cast<uint64_t>(L.n_sweeps),
                             b.items_per_wg);
   return L;
@@ -535,7 +578,7 @@ int run_frame(dh_ctx *ctx, hipStream_t st, const FrameJob &job, const Knobs &k, 
     a.copies = L.cfg.copies;
     a.stride = L.stride;
     a.tj = L.cfg.tj;
-    DH_HIP(ctx, launch_pairs(job.precision, job.kind, L.n_sweeps > 1, L.cfg, a, grid, L.lds, st));
+    DH_HIP(ctx, launch_pairs(job.precision, job.kind, L.mode, L.cfg, a, grid, L.lds, st));
   }
   if (e1) DH_HIP(ctx, hipEventRecord(e1, st));
   if (job.d_oor)
@@ -544,10 +587,11 @@ int run_frame(dh_ctx *ctx, hipStream_t st, const FrameJob &job, const Knobs &k, 
   const std::array<int32_t, kNumKnobs> kp = k.pack();
   for (int q = 0; q < kNumKnobs; ++q) ctx->last_config[q] = kp[q];
   ctx->last_config[6] = L.cfg.threads;  // the workgroup size actually launched
-  ctx->last_config[7] = items.empty() ? 0 : grid;
-  ctx->last_config[8] = static_cast<int32_t>(L.lds);
-  ctx->last_config[9] = L.n_sweeps;
-  ctx->last_config[10] = static_cast<int32_t>(items.size());
+  ctx->last_config[8] = items.empty() ? 0 : grid;
+  ctx->last_config[9] = static_cast<int32_t>(L.lds);
+  ctx->last_config[10] = L.n_sweeps;
+  ctx->last_config[11] = static_cast<int32_t>(items.size());
+  ctx->last_config[12] = L.mode;
   return DH_OK;
 }
 
@@ -571,8 +615,8 @@ std::string tune_key(const dh_ctx *ctx, const FrameJob &job) {
 int save_tune_cache(dh_ctx *ctx) {
   if (ctx->tune_path.empty()) return DH_OK;
   std::ostringstream o;
-  o << "{\"version\": 2, \"knobs\": [\"r\", \"copies\", \"tj\", \"noclamp\", \"occ_cap\", "
-       "\"items_per_wg\", \"threads\"], \"entries\": {";
+  o << "{\"version\": 3, \"knobs\": [\"r\", \"copies\", \"tj\", \"noclamp\", \"occ_cap\", "
+       "\"items_per_wg\", \"threads\", \"wide\"], \"entries\": {";
   bool first = true;
   for (const auto &kv : ctx->tune_cache) {
     o << (first ? "\n  " : ",\n  ") << '"' << kv.first << "\": [";
@@ -592,7 +636,8 @@ int save_tune_cache(dh_ctx *ctx) {
   return DH_OK;
 }
 
-// Reads entries written by save_tune_cache ("key": [6 integers]).
+// Reads entries written by save_tune_cache ("key": [kNumKnobs integers]);
+// entries of another length or with invalid knobs are skipped.
 int load_tune_cache(dh_ctx *ctx) {
   std::ifstream f(ctx->tune_path);
   if (!f) return DH_OK;  // no cache yet
@@ -654,9 +699,21 @@ int tune_frame(dh_ctx *ctx, hipStream_t st, const FrameJob &job, const std::stri
     return DH_OK;
   };
   best = default_knobs(job.precision);
+  // LDS bin windows against global atomics, only where the histogram needs
+  // more than one window: 0 keeps the windows, 1 always takes global atomics
+  std::vector<int32_t> wide_choices;
+  {
+    Knobs k0 = best;
+    k0.wide = 0;
+    if (choose_launch(ctx, job.precision, job.fp, job.total, k0).n_sweeps > 1) {
+      best.wide = 0;
+      wide_choices = {1};
+    }
+  }
   float best_ms = 0.f;
   int rc = time_of(best, &best_ms);
   const std::vector<std::vector<int32_t>> choices = {
+      wide_choices,      // wide
       {256, 512, 1024},  // threads
       {0, 1},            // noclamp
       {1, 2, 4},         // copies
@@ -665,7 +722,7 @@ int tune_frame(dh_ctx *ctx, hipStream_t st, const FrameJob &job, const std::stri
       {4, 8, 16},        // items_per_wg
       {128, 256},        // tj
   };
-  const int order[kNumKnobs] = {6, 3, 1, 0, 4, 5, 2};  // knob index in pack() order
+  const int order[kNumKnobs] = {7, 6, 3, 1, 0, 4, 5, 2};  // knob index in pack() order
   for (int d = 0; d < kNumKnobs && !rc; ++d) {
     const int q = order[d];
     for (int32_t v : choices[d]) {
@@ -745,7 +802,7 @@ static int dh_batch_launch_direct(dh_batch *b, hipStream_t st) {
     a.stride = g.stride;
     a.tj = g.cfg.tj;
     const int grid = std::max(1, std::min<int>(g.grid, a.n_items));
-    DH_HIP(ctx, launch_pairs(b->precision, g.kind, g.sweep, g.cfg, a, grid, g.lds, st));
+    DH_HIP(ctx, launch_pairs(b->precision, g.kind, g.mode, g.cfg, a, grid, g.lds, st));
   }
   if (b->any_oor) DH_HIP(ctx, launch_oor_batch(d_frames, b->n_frames, b->max_hist, st));
   return DH_OK;
@@ -957,7 +1014,8 @@ int dh_batch_create(dh_ctx *ctx, const dh_frame_desc *frames, int32_t n_frames, 
   if (precision != DH_FP32 && precision != DH_FP64) return fail(ctx, DH_EINVAL, "precision");
   struct FrameInfo {
     FrameParams fp;
-    bool sweep = false, noclamp_ok = false;
+    int mode = kModeLds;
+    bool noclamp_ok = false;
     int64_t slots = 0;
     uint64_t pairs = 0;
     std::vector<int64_t> offsets;
@@ -985,10 +1043,15 @@ int dh_batch_create(dh_ctx *ctx, const dh_frame_desc *frames, int32_t n_frames, 
     } else {
       fi.fp.n_sweeps = static_cast<int32_t>((d.n_bins + base.win_max - 1) / base.win_max);
       fi.fp.win = (d.n_bins + fi.fp.n_sweeps - 1) / fi.fp.n_sweeps;
-      fi.sweep = true;
+      fi.mode = kModeSweep;
+    }
+    if (bk.wide > 0 && fi.fp.n_sweeps >= bk.wide) {
+      fi.mode = kModeGlobal;
+      fi.fp.win = d.n_bins;
+      fi.fp.n_sweeps = 1;
     }
     const double tb = t_bound(fi.fp);
-    if (base.noclamp && !fi.sweep && tb > 0) {
+    if (base.noclamp && fi.mode == kModeLds && tb > 0) {
       fi.slots = static_cast<int64_t>(tb * (1.0 + 1e-4)) + 2;
       fi.noclamp_ok = fi.slots <= base.win_max + kDump;
     }
@@ -1013,7 +1076,7 @@ int dh_batch_create(dh_ctx *ctx, const dh_frame_desc *frames, int32_t n_frames, 
   // classes of frames that share one persistent launch
   std::map<std::pair<int, int>, std::vector<int32_t>> classes;
   for (int32_t f = 0; f < n_frames; ++f)
-    classes[{info[f].fp.box, info[f].sweep ? 1 : 0}].push_back(f);
+    classes[{info[f].fp.box, info[f].mode}].push_back(f);
 
   std::vector<WorkItem> items;
   std::vector<uint64_t> pairs;
@@ -1022,16 +1085,18 @@ int dh_batch_create(dh_ctx *ctx, const dh_frame_desc *frames, int32_t n_frames, 
     std::vector<int32_t> &fs = kv.second;
     dh_batch::Group g;
     g.kind = kv.first.first;
-    g.sweep = kv.first.second != 0;
+    g.mode = kv.first.second;
     const BaseConfig gbase = base_config(ctx, precision, bk, g.kind);
     g.cfg = gbase.cfg;
     int64_t stride = 0;
     uint64_t work = 0;
     for (int32_t f : fs) {
       FrameInfo &fi = info[f];
-      int64_t need = fi.fp.win + kDump;
-      if (fi.noclamp_ok) need = std::max<int64_t>(need, fi.slots);
-      stride = std::max(stride, need);
+      if (g.mode != kModeGlobal) {
+        int64_t need = fi.fp.win + kDump;
+        if (fi.noclamp_ok) need = std::max<int64_t>(need, fi.slots);
+        stride = std::max(stride, need);
+      }
       for (int s = 0; s < frames[f].n_species; ++s) {
         const uint64_t a = static_cast<uint64_t>(fi.offsets[s + 1] - fi.offsets[s]);
         fi.pairs += a * (a > 0 ? a - 1 : 0) / 2;
@@ -1043,7 +1108,8 @@ int dh_batch_create(dh_ctx *ctx, const dh_frame_desc *frames, int32_t n_frames, 
     for (int32_t f : fs) info[f].fp.noclamp = (info[f].noclamp_ok && info[f].slots <= stride) ? 1 : 0;
     g.stride = static_cast<int>(stride);
     g.lds = gbase.tile_bytes + static_cast<size_t>(g.cfg.copies) * g.stride * 4;
-    g.grid = grid_for_config(ctx, precision, g.kind, g.sweep, gbase, g.lds);
+    resolve_threads(precision, g.kind, g.mode, bk, g.lds, g.cfg);
+    g.grid = grid_for_config(ctx, precision, g.kind, g.mode, gbase, g.lds, g.cfg);
     g.cfg.jchunk = jchunk_for(g.cfg, g.grid, work, gbase.items_per_wg);
     // large frames first: the tail of the work list is made of small items
     std::stable_sort(fs.begin(), fs.end(),
@@ -1188,7 +1254,7 @@ int dh_ctx_set_config(dh_ctx *ctx, const int32_t *knobs) {
 
 int dh_ctx_last_config(const dh_ctx *ctx, int32_t *out) {
   if (!ctx || !out) return DH_EINVAL;
-  for (int q = 0; q < 11; ++q) out[q] = ctx->last_config[q];
+  for (int q = 0; q < 13; ++q) out[q] = ctx->last_config[q];
   return DH_OK;
 }
 

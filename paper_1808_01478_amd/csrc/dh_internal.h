@@ -15,6 +15,13 @@ enum BoxKind : int32_t {
   kBoxCube = 4,        // binary32 only: orthorhombic cell with equal edges
 };
 
+// How a pair kernel accumulates its counts.
+enum HistMode : int32_t {
+  kModeLds = 0,     // the whole histogram in LDS sub-histograms
+  kModeSweep = 1,   // LDS sub-histograms of one bin window per item
+  kModeGlobal = 2,  // uint64 atomics straight into the output (wide histograms)
+};
+
 // WorkItem::flags
 constexpr int32_t kItemDiag = 1;  // i- and j-range are the same block: count j > i only
 constexpr int32_t kItemFull = 2;  // every lane holds a valid i-particle
@@ -74,7 +81,7 @@ struct PairKernelArgs {
   int32_t *counter;  // dynamic work counter, zero before launch
   int32_t n_items;
   int32_t copies;    // interleaved LDS sub-histogram copies (1, 2 or 4)
-  int32_t stride;    // slots per copy (>= win + kDump of every frame)
+  int32_t stride;    // slots per copy (>= win + kDump of every frame); 0 in kModeGlobal
   int32_t tj;        // j-tile length staged through LDS
 };
 
@@ -92,7 +99,7 @@ struct KernelConfig {
 hipError_t launch_stage(int precision, int box_kind, const double *in, void *out, int64_t n,
                         const FrameParams &fp, hipStream_t st);
 hipError_t launch_zero(uint64_t *out, int64_t n_words, int32_t *counter, hipStream_t st);
-hipError_t launch_pairs(int precision, int box_kind, bool sweep, const KernelConfig &cfg,
+hipError_t launch_pairs(int precision, int box_kind, int mode, const KernelConfig &cfg,
                         const PairKernelArgs &args, int grid, size_t lds_bytes, hipStream_t st);
 hipError_t launch_oor(const uint64_t *hist, int32_t n_hist, int32_t n_bins, const uint64_t *pairs,
                       uint64_t *oor, hipStream_t st);
@@ -107,7 +114,7 @@ hipError_t launch_pair_t(int precision, int box_kind, const FrameParams *d_fp, c
                          const int32_t *pj, int64_t n_pairs, int32_t n, double *t,
                          hipStream_t st);
 // Occupancy of the pair kernel (workgroups per CU) for a config and LDS size.
-int pairs_occupancy(int precision, int box_kind, bool sweep, const KernelConfig &cfg,
+int pairs_occupancy(int precision, int box_kind, int mode, const KernelConfig &cfg,
                     size_t lds_bytes);
 
 }  // namespace dh

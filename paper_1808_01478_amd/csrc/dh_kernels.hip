@@ -16,6 +16,11 @@
 // window or frame changes, or before any u32 slot could wrap, the workgroup
 // sums its copies and adds them to the uint64 output with global atomics
 // (Sec. 3.1: u32 private histograms flushed into a u64 global one).
+//
+// Histograms too wide for LDS either run as bin windows (one LDS window per
+// item, the shared-memory kernel's sweeps of Sec. 3.2.3) or, in the global
+// mode, count every in-range pair with one uint64 atomic straight into the
+// output (the global-memory kernel of Sec. 3.2.2); the host picks the mode.
 #include "dh_internal.h"
 
 #include <algorithm>
@@ -355,13 +360,15 @@ __device__ __forceinline__ void flush_hist(uint32_t *hist, const PairKernelArgs 
 // CLAMP = false: the host proved that every t of this frame is below the LDS
 // stride and the block has no invalid lanes, so the bin index needs no clamp
 // (out-of-range pairs land in slots [n_bins, stride) that are never flushed).
-template <typename T, int R, int BOX, bool SWEEP, bool DIAG, bool CLAMP>
+template <typename T, int R, int BOX, int MODE, bool DIAG, bool CLAMP>
 __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem &w,
                                          const FrameParams *F,
                                          typename V4<T>::type *__restrict__ tile,
                                          uint32_t *__restrict__ my) {
   using V = typename V4<T>::type;
   using G = typename Geo<T>::type;
+  constexpr bool SWEEP = MODE == kModeSweep;
+  constexpr bool GLOBAL = MODE == kModeGlobal;
   const V *__restrict__ X = static_cast<const V *>(F->coords);
   const G g = Geo<T>::load(F);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -403,6 +410,18 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
   const float hif = static_cast<float>(hi);
 #pragma unroll
   for (int r = 0; r < R; ++r) lof[r] = static_cast<float>(lo[r]);
+  // global mode: a pair counts iff t < n_bins (in the working precision);
+  // ragged lanes get a limit no t reaches
+  T glim[R];
+  const int n_bins = uni(F->n_bins);
+#pragma unroll
+  for (int r = 0; r < R; ++r) glim[r] = lo[r] == 0u ? static_cast<T>(n_bins) : T(-1);
+  // the output is global memory: say so, so the atomics are global_atomic_*
+  // (a generic pointer would give flat atomics, which also count as LDS
+  // operations in lgkmcnt)
+  using GlobalU64 = __attribute__((address_space(1))) unsigned long long;
+  GlobalU64 *const gout =
+      (GlobalU64 *)(F->out + static_cast<size_t>(w.hist) * static_cast<size_t>(n_bins));
   // The i-particles are complete before the tile loop, so the only global
   // load in flight inside it is the next tile's prefetch, which the j-loop
   // never reads.
@@ -438,7 +457,7 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
         else
           return tb[k];
       };
-      // R pairs of one j: distance, bin, one LDS atomic each
+      // R pairs of one j: distance, bin, one atomic each
       auto pairs_of = [&](const J &pj, int j) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -447,34 +466,42 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
             t = t32_packed<BOX>(pj.ab, nab[r], zi[r], pj.z, g);
           else
             t = pair_t<T, BOX>(xi[r], yi[r], zi[r], pj.x, pj.y, pj.z, g);
-          uint32_t idx;
-          if constexpr (!CLAMP) {
-            if constexpr (sizeof(T) == 4) {
-              // fixed-point staging bounds every binary32 t below the stride
-              idx = static_cast<uint32_t>(t);
-            } else {
-              // binary64 reads raw device coordinates: cap t so that even
-              // non-finite or absurd input stays inside the LDS histogram
-              idx = static_cast<uint32_t>(fmin(t, cap64));
-            }
-          } else if constexpr (sizeof(T) == 4 && !SWEEP) {
-            float l = lof[r];
-            if constexpr (DIAG) l = (j > wbase + r * 64 + lane) ? l : hif;
-            idx = static_cast<uint32_t>(__builtin_amdgcn_fmed3f(t, l, hif));
+          if constexpr (GLOBAL) {
+            bool ok = t < glim[r];
+            if constexpr (DIAG) ok = ok && (j > wbase + r * 64 + lane);
+            if (ok)
+              __hip_atomic_fetch_add(gout + static_cast<uint32_t>(t), 1ull, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
           } else {
-            uint32_t l = lo[r];
-            if constexpr (DIAG) l = (j > wbase + r * 64 + lane) ? l : hi;
-            // floor(t), saturated; t >= 0 always
-            if constexpr (sizeof(T) == 4)
-              idx = static_cast<uint32_t>(fminf(t, 4294967040.0f));
-            else
-              idx = static_cast<uint32_t>(fmin(t, 4294967295.0));
-            if constexpr (SWEEP) idx -= static_cast<uint32_t>(b_lo);
-            idx = max(min(idx, hi), l);
+            uint32_t idx;
+            if constexpr (!CLAMP) {
+              if constexpr (sizeof(T) == 4) {
+                // fixed-point staging bounds every binary32 t below the stride
+                idx = static_cast<uint32_t>(t);
+              } else {
+                // binary64 reads raw device coordinates: cap t so that even
+                // non-finite or absurd input stays inside the LDS histogram
+                idx = static_cast<uint32_t>(fmin(t, cap64));
+              }
+            } else if constexpr (sizeof(T) == 4 && !SWEEP) {
+              float l = lof[r];
+              if constexpr (DIAG) l = (j > wbase + r * 64 + lane) ? l : hif;
+              idx = static_cast<uint32_t>(__builtin_amdgcn_fmed3f(t, l, hif));
+            } else {
+              uint32_t l = lo[r];
+              if constexpr (DIAG) l = (j > wbase + r * 64 + lane) ? l : hi;
+              // floor(t), saturated; t >= 0 always
+              if constexpr (sizeof(T) == 4)
+                idx = static_cast<uint32_t>(fminf(t, 4294967040.0f));
+              else
+                idx = static_cast<uint32_t>(fmin(t, 4294967295.0));
+              if constexpr (SWEEP) idx -= static_cast<uint32_t>(b_lo);
+              idx = max(min(idx, hi), l);
+            }
+            // byte offset with one shift (copies interleaved bin-major), so the
+            // address is a single v_lshl_add_u32
+            atomicAdd(reinterpret_cast<uint32_t *>(my_bytes + (idx << shift_bytes)), 1u);
           }
-          // byte offset with one shift (copies interleaved bin-major), so the
-          // address is a single v_lshl_add_u32
-          atomicAdd(reinterpret_cast<uint32_t *>(my_bytes + (idx << shift_bytes)), 1u);
         }
       };
       // Ping-pong over two j registers: the read of the next j is issued
@@ -507,7 +534,7 @@ constexpr int max_threads() {
   return BOX == kBoxTricSearch ? 256 : 1024;
 }
 
-template <typename T, int R, int BOX, bool SWEEP>
+template <typename T, int R, int BOX, int MODE>
 __global__ __launch_bounds__(max_threads<BOX>()) void pairs_kernel(PairKernelArgs a) {
   using V = typename V4<T>::type;
   extern __shared__ __align__(32) unsigned char smem[];
@@ -519,7 +546,9 @@ __global__ __launch_bounds__(max_threads<BOX>()) void pairs_kernel(PairKernelArg
   // hit the same bin use different words (and banks) when copies > 1
   uint32_t *my = hist + (tid & 63) % a.copies;
 
-  for (int k = tid; k < a.copies * a.stride; k += blockDim.x) hist[k] = 0u;
+  constexpr bool GLOBAL = MODE == kModeGlobal;
+  if constexpr (!GLOBAL)
+    for (int k = tid; k < a.copies * a.stride; k += blockDim.x) hist[k] = 0u;
 
   int cur_frame = -1, cur_hist = -1, cur_sweep = -1;
   uint64_t acc = 0;
@@ -536,31 +565,34 @@ __global__ __launch_bounds__(max_threads<BOX>()) void pairs_kernel(PairKernelArg
       w.flags = uni(p->flags); w.i0 = uni(p->i0); w.i1 = uni(p->i1);
       w.j0 = uni(p->j0); w.j1 = uni(p->j1);
     }
-    const uint64_t npairs =
-        static_cast<uint64_t>(w.i1 - w.i0) * static_cast<uint64_t>(w.j1 - w.j0);
-    if (w.frame != cur_frame || w.hist != cur_hist || w.sweep != cur_sweep ||
-        acc + npairs > 0xffffffffull) {
-      if (cur_frame >= 0) {
-        flush_hist(hist, a, a.frames + cur_frame, cur_hist, cur_sweep);
-        __syncthreads();
+    if constexpr (!GLOBAL) {
+      const uint64_t npairs =
+          static_cast<uint64_t>(w.i1 - w.i0) * static_cast<uint64_t>(w.j1 - w.j0);
+      if (w.frame != cur_frame || w.hist != cur_hist || w.sweep != cur_sweep ||
+          acc + npairs > 0xffffffffull) {
+        if (cur_frame >= 0) {
+          flush_hist(hist, a, a.frames + cur_frame, cur_hist, cur_sweep);
+          __syncthreads();
+        }
+        cur_frame = w.frame; cur_hist = w.hist; cur_sweep = w.sweep;
+        acc = 0;
       }
-      cur_frame = w.frame; cur_hist = w.hist; cur_sweep = w.sweep;
-      acc = 0;
+      acc += npairs;
     }
-    acc += npairs;
     const FrameParams *F = a.frames + w.frame;
     if (w.flags & kItemDiag) {
-      run_item<T, R, BOX, SWEEP, true, true>(a, w, F, tile, my);
+      run_item<T, R, BOX, MODE, true, true>(a, w, F, tile, my);
     } else {
       bool clamp = true;
-      if constexpr (!SWEEP) clamp = !((w.flags & kItemFull) && uni(F->noclamp));
+      if constexpr (MODE == kModeLds) clamp = !((w.flags & kItemFull) && uni(F->noclamp));
       if (clamp)
-        run_item<T, R, BOX, SWEEP, false, true>(a, w, F, tile, my);
-      else if constexpr (!SWEEP)
-        run_item<T, R, BOX, false, false, false>(a, w, F, tile, my);
+        run_item<T, R, BOX, MODE, false, true>(a, w, F, tile, my);
+      else if constexpr (MODE == kModeLds)
+        run_item<T, R, BOX, kModeLds, false, false>(a, w, F, tile, my);
     }
   }
-  if (cur_frame >= 0) flush_hist(hist, a, a.frames + cur_frame, cur_hist, cur_sweep);
+  if constexpr (!GLOBAL)
+    if (cur_frame >= 0) flush_hist(hist, a, a.frames + cur_frame, cur_hist, cur_sweep);
 }
 
 // --------------------------------------------------------------------------
@@ -608,7 +640,7 @@ __global__ void pair_t_kernel(const FrameParams *F, const int32_t *__restrict__ 
 
 using PairFn = void (*)(PairKernelArgs);
 
-template <typename T, int R, bool SW>
+template <typename T, int R, int SW>
 PairFn pick_box(int box) {
   switch (box) {
     case kBoxNone: return pairs_kernel<T, R, kBoxNone, SW>;
@@ -621,14 +653,22 @@ PairFn pick_box(int box) {
   }
 }
 
-template <typename T>
-PairFn pick_r(int r, int box, bool sweep) {
-  if (r == 8) return sweep ? pick_box<T, 8, true>(box) : pick_box<T, 8, false>(box);
-  return sweep ? pick_box<T, 4, true>(box) : pick_box<T, 4, false>(box);
+template <typename T, int R>
+PairFn pick_mode(int box, int mode) {
+  switch (mode) {
+    case kModeSweep: return pick_box<T, R, kModeSweep>(box);
+    case kModeGlobal: return pick_box<T, R, kModeGlobal>(box);
+    default: return pick_box<T, R, kModeLds>(box);
+  }
 }
 
-PairFn pick(int precision, int r, int box, bool sweep) {
-  return precision == 1 ? pick_r<double>(r, box, sweep) : pick_r<float>(r, box, sweep);
+template <typename T>
+PairFn pick_r(int r, int box, int mode) {
+  return r == 8 ? pick_mode<T, 8>(box, mode) : pick_mode<T, 4>(box, mode);
+}
+
+PairFn pick(int precision, int r, int box, int mode) {
+  return precision == 1 ? pick_r<double>(r, box, mode) : pick_r<float>(r, box, mode);
 }
 
 int grid_for(int64_t n, int threads) {
@@ -666,9 +706,9 @@ hipError_t launch_zero(uint64_t *out, int64_t n_words, int32_t *counter, hipStre
   return hipGetLastError();
 }
 
-hipError_t launch_pairs(int precision, int box_kind, bool sweep, const KernelConfig &cfg,
+hipError_t launch_pairs(int precision, int box_kind, int mode, const KernelConfig &cfg,
                         const PairKernelArgs &args, int grid, size_t lds_bytes, hipStream_t st) {
-  PairFn fn = pick(precision, cfg.r, box_kind, sweep);
+  PairFn fn = pick(precision, cfg.r, box_kind, mode);
   hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes));
   (void)hipGetLastError();
@@ -676,9 +716,9 @@ hipError_t launch_pairs(int precision, int box_kind, bool sweep, const KernelCon
   return hipGetLastError();
 }
 
-int pairs_occupancy(int precision, int box_kind, bool sweep, const KernelConfig &cfg,
+int pairs_occupancy(int precision, int box_kind, int mode, const KernelConfig &cfg,
                     size_t lds_bytes) {
-  PairFn fn = pick(precision, cfg.r, box_kind, sweep);
+  PairFn fn = pick(precision, cfg.r, box_kind, mode);
   hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes));
   (void)hipGetLastError();

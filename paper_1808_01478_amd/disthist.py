@@ -63,7 +63,9 @@ class FrameDesc(ctypes.Structure):
 
 BATCH_GRAPH = 1
 TUNE_OFF, TUNE_CACHED, TUNE_ON = 0, 1, 2
-KNOB_NAMES = ("r", "copies", "tj", "noclamp", "occ_cap", "items_per_wg", "threads")
+KNOB_NAMES = ("r", "copies", "tj", "noclamp", "occ_cap", "items_per_wg", "threads", "wide")
+# accumulation modes reported by dh_ctx_last_config
+MODE_LDS, MODE_SWEEP, MODE_GLOBAL = 0, 1, 2
 
 
 def _load() -> ctypes.CDLL:
@@ -206,21 +208,24 @@ class Context:
                self.handle)
 
     def set_config(self, knobs=None) -> None:
-        """dh_ctx_set_config: force a launch shape (dict or 7 ints) or None."""
+        """dh_ctx_set_config: force a launch shape (dict or 8 ints, KNOB_NAMES order) or None."""
         if knobs is None:
             _check(LIB.dh_ctx_set_config(self.handle, None), self.handle)
             return
         if isinstance(knobs, dict):
             knobs = [knobs[k] for k in KNOB_NAMES]
         arr = np.ascontiguousarray(np.asarray(knobs, np.int32))
+        if arr.shape != (len(KNOB_NAMES),):
+            raise ValueError(f"expected {len(KNOB_NAMES)} knobs {KNOB_NAMES}, got {arr.shape}")
         _check(LIB.dh_ctx_set_config(self.handle, _np_ptr(arr)), self.handle)
 
     def last_config(self) -> dict:
         """dh_ctx_last_config: the shape of the last single-frame launch."""
-        out = np.zeros(11, np.int32)
+        out = np.zeros(13, np.int32)
         _check(LIB.dh_ctx_last_config(self.handle, _np_ptr(out)), self.handle)
-        d = {k: int(v) for k, v in zip(KNOB_NAMES, out[:7])}
-        d.update(grid=int(out[7]), lds_bytes=int(out[8]), sweeps=int(out[9]), items=int(out[10]))
+        d = {k: int(v) for k, v in zip(KNOB_NAMES, out[:8])}
+        d.update(grid=int(out[8]), lds_bytes=int(out[9]), sweeps=int(out[10]), items=int(out[11]),
+                 mode=int(out[12]))
         return d
 
     def profile(self, enable: bool = True) -> None:

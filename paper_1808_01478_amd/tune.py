@@ -10,6 +10,7 @@ species).
 from __future__ import annotations
 
 import argparse
+import json
 import os
 import sys
 
@@ -29,8 +30,13 @@ def main(argv=None) -> int:
     args = ap.parse_args(argv)
     makers = {"ortho100k": workloads.ortho, "tiny": workloads.tiny,
               "triclinic1M": workloads.triclinic}
+    # tune into a fresh file so that every listed workload is measured again,
+    # then merge its entries over the existing cache
+    fresh = args.out + ".new"
+    if os.path.exists(fresh):
+        os.remove(fresh)
     ctx = dh.Context(0)
-    ctx.set_tuning(dh.TUNE_ON, args.out)
+    ctx.set_tuning(dh.TUNE_ON, fresh)
     dev = torch.device("cuda")
     for name in args.workloads.split(","):
         fr = makers[name]()
@@ -41,7 +47,29 @@ def main(argv=None) -> int:
             torch.cuda.synchronize()
             print(f"{name} precision={prec}: {ctx.last_config()}", flush=True)
     ctx.close()
+    merge(args.out, fresh)
+    os.remove(fresh)
     return 0
+
+
+def merge(out: str, fresh: str) -> None:
+    """Entries of `fresh` replace those of `out` with the same key; entries
+    of an older cache format are dropped."""
+    with open(fresh) as fh:
+        new = json.load(fh)
+    entries = {}
+    if os.path.exists(out):
+        with open(out) as fh:
+            old = json.load(fh)
+        if old.get("version") == new["version"]:
+            entries.update(old["entries"])
+    entries.update(new["entries"])
+    with open(out + ".tmp", "w") as fh:
+        fh.write(f'{{"version": {new["version"]}, "knobs": {json.dumps(new["knobs"])}, '
+                 '"entries": {')
+        fh.write(",".join(f'\n  "{k}": {json.dumps(v)}' for k, v in sorted(entries.items())))
+        fh.write("\n}}\n")
+    os.replace(out + ".tmp", out)
 
 
 if __name__ == "__main__":

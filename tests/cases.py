@@ -1,0 +1,60 @@
+"""Seeded frames shared by the GPU parity tests: every box kind, ragged and
+empty species, unwrapped coordinates, r_max beyond half the cell, image
+search, clustered points, bin windows, coincident points, all pairs out of
+range, a single bin, and a trajectory frame."""
+import numpy as np
+
+import workloads
+
+SKEW = np.array([[10.0, 0, 0], [3.0, 9.5, 0], [-2.0, 3.5, 9.0]])
+
+
+def _frame(coords, sizes, box_type, box, r_max, n_bins, name):
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    return workloads.Frame(np.ascontiguousarray(coords, np.float64), offs, box_type,
+                           None if box is None else np.asarray(box, np.float64), float(r_max),
+                           int(n_bins), name)
+
+
+def parity_cases():
+    rng = np.random.Generator(np.random.PCG64(2024))
+    out = [workloads.tiny()]
+    out.append(workloads.random_frame(11, [2500, 1, 0, 1337], workloads.BOX_NONE, r_max=12.0,
+                                      n_bins=97))
+    out[-1].name = "none-4species-ragged"
+    out.append(workloads.random_frame(12, [3001, 2047], workloads.BOX_ORTHO, n_bins=1000))
+    out[-1].name = "ortho-2species"
+    box = workloads.ortho_box(10.0, 11.0, 12.0)
+    out.append(_frame(rng.uniform(-30, 50, size=(2900, 3)), [1900, 1000], workloads.BOX_ORTHO,
+                      box, 5.9, 500, "ortho-unwrapped"))
+    out.append(_frame(rng.uniform(0, 10, size=(2100, 3)), [2100], workloads.BOX_ORTHO,
+                      workloads.ortho_box(10.0, 10.0, 10.0), 8.0, 333, "ortho-beyond-half"))
+    out.append(workloads.random_frame(13, [2600, 900], workloads.BOX_TRICLINIC, n_bins=777))
+    out[-1].name = "tric-2species"
+    w = workloads.min_width(SKEW)
+    out.append(workloads.random_frame(14, [1500, 700], workloads.BOX_TRICLINIC, box=SKEW,
+                                      r_max=0.8 * w, n_bins=300))
+    out[-1].name = "tric-search"
+    x = rng.uniform(-1.5, 2.5, size=(1800, 3)) @ SKEW
+    out.append(_frame(x, [1000, 800], workloads.BOX_TRICLINIC, SKEW, 0.45 * w, 256,
+                      "tric-unwrapped"))
+    c3 = workloads.triclinic(n=6000)
+    c3.name = "tric-clustered-6k"
+    out.append(c3)
+    out.append(workloads.random_frame(15, [2000, 1000], workloads.BOX_ORTHO, n_bins=50_000))
+    out[-1].name = "ortho-50k-bins-sweeps"
+    out.append(workloads.random_frame(16, [1700], workloads.BOX_NONE, r_max=17.3,
+                                      n_bins=90_001))
+    out[-1].name = "none-90001-bins-sweeps"
+    out.append(_frame(np.tile([[1.5, 2.5, 3.5]], (3000, 1)), [3000], workloads.BOX_NONE, None,
+                      1.0, 64, "coincident"))
+    out.append(workloads.random_frame(17, [1200, 800], workloads.BOX_NONE, r_max=1e-3,
+                                      n_bins=10))
+    out[-1].name = "all-out-of-range"
+    out.append(workloads.random_frame(18, [900, 1100], workloads.BOX_ORTHO, n_bins=1))
+    out[-1].name = "one-bin"
+    tr = workloads.trajectory_frame(7)
+    out.append(tr.subset([4000] * tr.n_species))
+    return out
+
+

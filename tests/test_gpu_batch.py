@@ -28,6 +28,7 @@ def mixed_frames():
                                r_max=0.8 * w, n_bins=300),
         workloads.random_frame(405, [2200, 5], workloads.BOX_NONE, r_max=9.0, n_bins=777),
         workloads.random_frame(406, [1800, 1000], workloads.BOX_ORTHO, n_bins=60_000),
+        workloads.random_frame(409, [1600, 900], workloads.BOX_ORTHO, n_bins=200_000),
         workloads.random_frame(407, [1], workloads.BOX_NONE, n_bins=16),
         workloads.random_frame(408, [0, 700], workloads.BOX_ORTHO, n_bins=128),
         workloads.trajectory_frame(3).subset([3000] * 4),
