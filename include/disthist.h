@@ -341,6 +341,16 @@ int dh_ctx_set_config(dh_ctx *ctx, const int32_t *knobs);
 int dh_ctx_last_config(const dh_ctx *ctx, int32_t *out);
 
 /*
+ * Splits every later histogram on ctx into pair-kernel launches of at most
+ * max_pairs pairs (0 = one launch per frame, the default; otherwise at least
+ * 2^24). Counts are unchanged. A persistent launch holds every CU until its
+ * work list is drained; bounded launches let work queued on other streams
+ * start between them (the serving loop runs its jobs this way). DH_EINVAL
+ * for a negative or too small limit.
+ */
+int dh_ctx_set_launch_pairs(dh_ctx *ctx, int64_t max_pairs);
+
+/*
  * Kernel timing. When enabled, every histogram launch on ctx records a pair
  * of HIP events on its stream around the pair kernel (the dominant kernel of
  * the path); batches are not timed this way. dh_ctx_profile_read() waits for the recorded launches, returns

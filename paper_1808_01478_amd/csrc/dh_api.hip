@@ -46,6 +46,8 @@ struct dh_ctx {
   bool forced = false;
   std::array<int32_t, 8> forced_knobs{};
   std::array<int32_t, 13> last_config{};
+  // pairs per pair-kernel launch at most (0: one launch per frame)
+  uint64_t launch_pairs = 0;
   // kernel timing: event pairs recorded around pair-kernel launches
   bool profile = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
@@ -217,6 +219,9 @@ struct Launch {
 };
 
 size_t coord_bytes(int precision) { return precision == DH_FP64 ? 32 : 16; }
+
+// Smallest work item (pairs) when a frame is split into bounded launches.
+constexpr int64_t kMinItemPairs = int64_t{1} << 21;
 
 // Launch shape for one frame (heuristic defaults).
 // Launch knobs. Every choice yields identical counts; they only change speed.
@@ -472,13 +477,13 @@ struct BlobLayout {
   size_t frames = 0, items = 0, pairs = 0, counter = 0, total = 0;
 };
 
-BlobLayout blob_layout(size_t n_frames, size_t n_items, size_t n_pairs) {
+BlobLayout blob_layout(size_t n_frames, size_t n_items, size_t n_pairs, size_t n_counters = 1) {
   BlobLayout b;
   b.frames = 0;
   b.items = align_up(b.frames + n_frames * sizeof(FrameParams), 256);
   b.pairs = align_up(b.items + n_items * sizeof(WorkItem), 256);
   b.counter = align_up(b.pairs + n_pairs * sizeof(uint64_t), 256);
-  b.total = b.counter + 256;
+  b.total = b.counter + align_up(std::max<size_t>(1, n_counters) * sizeof(int32_t), 256);
   return b;
 }
 
@@ -497,7 +502,7 @@ int upload_blob(dh_ctx *ctx, hipStream_t st, const BlobLayout &lay,
   if (!frames.empty()) std::memcpy(h + lay.frames, frames.data(), frames.size() * sizeof(FrameParams));
   if (!items.empty()) std::memcpy(h + lay.items, items.data(), items.size() * sizeof(WorkItem));
   if (!pairs.empty()) std::memcpy(h + lay.pairs, pairs.data(), pairs.size() * sizeof(uint64_t));
-  std::memset(h + lay.counter, 0, 256);
+  std::memset(h + lay.counter, 0, lay.total - lay.counter);
   DH_HIP(ctx, hipMemcpyAsync(ctx->d_blob, h, lay.total, hipMemcpyHostToDevice, st));
   DH_HIP(ctx, hipEventRecord(ctx->blob_evt, st));
   ctx->blob_pending = true;
@@ -554,12 +559,37 @@ int run_frame(dh_ctx *ctx, hipStream_t st, const FrameJob &job, const Knobs &k, 
   fp.win = L.win;
   fp.n_sweeps = L.n_sweeps;
   fp.noclamp = L.noclamp ? 1 : 0;
+  // bounded launches: size the items for one launch's share of the work,
+  // then cut the list wherever the running pair count reaches the limit
+  const uint64_t work = job.total * static_cast<uint64_t>(L.n_sweeps);
+  const uint64_t limit = ctx->launch_pairs;
+  if (limit > 0 && work > limit) {
+    // items of at least kMinItemPairs keep the work list of a huge frame small
+    const int64_t bi = static_cast<int64_t>(L.cfg.threads) * L.cfg.r;
+    const int64_t min_jc = (kMinItemPairs / bi + L.cfg.tj - 1) / L.cfg.tj * L.cfg.tj;
+    L.cfg.jchunk = std::max<int32_t>(jchunk_for(L.cfg, L.grid, limit, k.items_per_wg),
+                                     static_cast<int32_t>(std::min<int64_t>(min_jc, 64 * L.cfg.tj)));
+  }
   std::vector<WorkItem> items;
   std::vector<uint64_t> pairs;
   plan_frame(0, job.offsets, job.n_species, L, items, pairs);
+  std::vector<size_t> cuts(1, 0);
+  if (limit > 0 && work > limit) {
+    uint64_t acc = 0;
+    for (size_t q = 0; q < items.size(); ++q) {
+      acc += static_cast<uint64_t>(items[q].i1 - items[q].i0) *
+             static_cast<uint64_t>(items[q].j1 - items[q].j0);
+      if (acc >= limit && q + 1 < items.size()) {
+        cuts.push_back(q + 1);
+        acc = 0;
+      }
+    }
+  }
+  cuts.push_back(items.size());
+  const size_t n_launches = cuts.size() - 1;
   fp.coords = ctx->d_staged;
   fp.out = job.d_out;
-  const BlobLayout lay = blob_layout(1, items.size(), pairs.size());
+  const BlobLayout lay = blob_layout(1, items.size(), pairs.size(), n_launches);
   std::vector<FrameParams> frames(1, fp);
   int rc = upload_blob(ctx, st, lay, frames, items, pairs);
   if (rc) return rc;
@@ -569,16 +599,18 @@ int run_frame(dh_ctx *ctx, hipStream_t st, const FrameJob &job, const Knobs &k, 
                           reinterpret_cast<int32_t *>(db + lay.counter), st));
   const int grid = std::max(1, std::min<int>(L.grid, static_cast<int>(items.size())));
   if (e0) DH_HIP(ctx, hipEventRecord(e0, st));
-  if (!items.empty()) {
+  for (size_t c = 0; c < n_launches && !items.empty(); ++c) {
+    // every launch has its own work counter (zeroed with the blob upload)
     PairKernelArgs a;
     a.frames = reinterpret_cast<const FrameParams *>(db + lay.frames);
-    a.items = reinterpret_cast<const WorkItem *>(db + lay.items);
-    a.counter = reinterpret_cast<int32_t *>(db + lay.counter);
-    a.n_items = static_cast<int32_t>(items.size());
+    a.items = reinterpret_cast<const WorkItem *>(db + lay.items) + cuts[c];
+    a.counter = reinterpret_cast<int32_t *>(db + lay.counter) + c;
+    a.n_items = static_cast<int32_t>(cuts[c + 1] - cuts[c]);
     a.copies = L.cfg.copies;
     a.stride = L.stride;
     a.tj = L.cfg.tj;
-    DH_HIP(ctx, launch_pairs(job.precision, job.kind, L.mode, L.cfg, a, grid, L.lds, st));
+    const int g = std::max(1, std::min(grid, a.n_items));
+    DH_HIP(ctx, launch_pairs(job.precision, job.kind, L.mode, L.cfg, a, g, L.lds, st));
   }
   if (e1) DH_HIP(ctx, hipEventRecord(e1, st));
   if (job.d_oor)
@@ -770,11 +802,17 @@ void ctx_release_scratch(dh_ctx *ctx) {
   (void)hipGetLastError();
 }
 
-size_t job_scratch_bytes(int64_t n_points, int32_t n_hist, int32_t precision) {
-  // staged coordinates plus the work blob (frame constants, work items and
-  // pair counts: a few MB at most for millions of points)
-  return static_cast<size_t>(std::max<int64_t>(1, n_points)) * coord_bytes(precision) +
-         (4u << 20) + static_cast<size_t>(n_hist) * 8;
+size_t job_scratch_bytes(int64_t n_points, int32_t n_hist, int32_t n_bins, int32_t precision) {
+  // staged coordinates plus the work blob (frame constants, pair counts and
+  // work items: a few MB, plus one item per kMinItemPairs pairs of every bin
+  // window when the frame runs as bounded launches; at least 9,000 bins fit
+  // one window, and beyond 64 windows the global-atomic mode needs one pass)
+  const uint64_t n = static_cast<uint64_t>(std::max<int64_t>(1, n_points));
+  const uint64_t windows = std::min<uint64_t>(64, (static_cast<uint64_t>(n_bins) + 8999) / 9000);
+  const uint64_t work = n * (n - 1) / 2 * windows;
+  return static_cast<size_t>(n) * coord_bytes(precision) + (4u << 20) +
+         static_cast<size_t>(n_hist) * 8 +
+         static_cast<size_t>(work / kMinItemPairs) * sizeof(WorkItem);
 }
 
 }  // namespace dh
@@ -1255,6 +1293,14 @@ int dh_ctx_set_config(dh_ctx *ctx, const int32_t *knobs) {
 int dh_ctx_last_config(const dh_ctx *ctx, int32_t *out) {
   if (!ctx || !out) return DH_EINVAL;
   for (int q = 0; q < 13; ++q) out[q] = ctx->last_config[q];
+  return DH_OK;
+}
+
+int dh_ctx_set_launch_pairs(dh_ctx *ctx, int64_t max_pairs) {
+  if (!ctx || max_pairs < 0) return DH_EINVAL;
+  if (max_pairs > 0 && max_pairs < (int64_t{1} << 24))
+    return fail(ctx, DH_EINVAL, "max_pairs must be 0 or at least 2^24");
+  ctx->launch_pairs = static_cast<uint64_t>(max_pairs);
   return DH_OK;
 }
 

@@ -126,5 +126,5 @@ size_t ctx_device_bytes(const dh_ctx *ctx);
 // frees a context's scratch (the context must be idle); it regrows on use
 void ctx_release_scratch(dh_ctx *ctx);
 // device footprint of a single-frame job besides the caller's buffers
-size_t job_scratch_bytes(int64_t n_points, int32_t n_hist, int32_t precision);
+size_t job_scratch_bytes(int64_t n_points, int32_t n_hist, int32_t n_bins, int32_t precision);
 }  // namespace dh

@@ -21,6 +21,10 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+// pairs per pair-kernel launch of a served job (about 10 ms of binary32
+// orthorhombic work on MI355X)
+constexpr int64_t kServeLaunchPairs = int64_t{3} << 33;
+
 double seconds_since(Clock::time_point t0, Clock::time_point t1) {
   return std::chrono::duration<double>(t1 - t0).count();
 }
@@ -292,6 +296,9 @@ int dh_server_create(int32_t device, int64_t hbm_budget_bytes, int32_t max_infli
   s->slots.resize(max_inflight);
   for (Slot &sl : s->slots) {
     int rc = dh_ctx_create(device, &sl.ctx);
+    // bounded launches: a job that arrives while a huge one runs waits for
+    // one launch of the huge job (about 10 ms), not for all of it
+    if (!rc) rc = dh_ctx_set_launch_pairs(sl.ctx, kServeLaunchPairs);
     if (!rc && (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
                 hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess))
       rc = DH_EDEVICE;
@@ -319,7 +326,7 @@ int dh_server_submit(dh_server *s, const double *coords, const int64_t *offsets,
   j->n_hist = n_species * (n_species + 1) / 2;
   j->need = static_cast<int64_t>(std::max<int64_t>(1, n) * 3 * sizeof(double) +
                                  static_cast<size_t>(j->n_hist) * n_bins * sizeof(uint64_t) +
-                                 dh::job_scratch_bytes(n, j->n_hist, precision));
+                                 dh::job_scratch_bytes(n, j->n_hist, n_bins, precision));
   if (j->need > s->budget) return DH_EBUDGET;
   j->coords.assign(coords, coords + 3 * n);
   j->offsets.assign(offsets, offsets + n_species + 1);

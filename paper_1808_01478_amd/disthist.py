@@ -49,6 +49,7 @@ SIGNATURES = {
     "dh_ctx_set_tuning": ([_vp, _i32, ctypes.c_char_p], ctypes.c_int),
     "dh_ctx_set_config": ([_vp, _vp], ctypes.c_int),
     "dh_ctx_last_config": ([_vp, _vp], ctypes.c_int),
+    "dh_ctx_set_launch_pairs": ([_vp, _i64], ctypes.c_int),
     "dh_ctx_profile": ([_vp, _i32], ctypes.c_int),
     "dh_ctx_profile_read": ([_vp, ctypes.POINTER(_f64), ctypes.POINTER(_i64)], ctypes.c_int),
 }
@@ -227,6 +228,11 @@ class Context:
         d.update(grid=int(out[8]), lds_bytes=int(out[9]), sweeps=int(out[10]), items=int(out[11]),
                  mode=int(out[12]))
         return d
+
+    def set_launch_pairs(self, max_pairs: int) -> None:
+        """dh_ctx_set_launch_pairs: split histograms into launches of at most
+        max_pairs pairs (0 = one launch per frame)."""
+        _check(LIB.dh_ctx_set_launch_pairs(self.handle, int(max_pairs)), self.handle)
 
     def profile(self, enable: bool = True) -> None:
         """dh_ctx_profile: time the pair kernel of every launch with HIP events."""

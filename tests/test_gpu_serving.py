@@ -60,8 +60,12 @@ def test_budget_back_pressure():
         for f, p in jobs:
             probe.append(s1.wait(s1.submit(f.coords, f.offsets, f.box_type, f.box, f.r_max,
                                            f.n_bins, p))[0])
-    sizes = [f.n * 24 + f.n_hist * f.n_bins * 8 + f.n * (32 if p else 16) + (4 << 20) + f.n_hist * 8
-             for f, p in jobs]
+    def footprint(f, p):
+        windows = min(64, (f.n_bins + 8999) // 9000)
+        work = f.n * (f.n - 1) // 2 * windows
+        return (f.n * 24 + f.n_hist * f.n_bins * 8 + f.n * (32 if p else 16) + (4 << 20)
+                + f.n_hist * 8 + (work >> 21) * 32)
+    sizes = [footprint(f, p) for f, p in jobs]
     budget = int(max(sizes) * 1.2)
     with dh.Server(0, hbm_budget_bytes=budget, max_inflight=4, head_wait_limit_s=0.05) as srv:
         ids = [srv.submit(f.coords, f.offsets, f.box_type, f.box, f.r_max, f.n_bins, p)
@@ -108,3 +112,31 @@ def test_poisson_arrivals_overlap():
     for (f, p), (h, _, t) in zip(jobs, res):
         assert np.array_equal(h, alone(f, p))
         assert math.isfinite(t[2]) and t[2] > 0
+
+
+def test_small_job_overtakes_huge_job():
+    """A job submitted while a huge one runs starts at the huge job's next
+    launch boundary and finishes long before it (bounded launches)."""
+    import paper_1808_01478_amd as dh
+    huge = workloads.random_frame(611, [1_000_000], workloads.BOX_NONE, n_bins=1000)
+    small = workloads.random_frame(612, [3000, 1000], workloads.BOX_ORTHO, n_bins=1000)
+    with dh.Server(0, hbm_budget_bytes=8 << 30, max_inflight=4) as srv:
+        warm = srv.submit(small.coords, small.offsets, small.box_type, small.box, small.r_max,
+                          small.n_bins, 0)
+        srv.wait(warm)
+        big = srv.submit(huge.coords, huge.offsets, huge.box_type, huge.box, huge.r_max,
+                         huge.n_bins, 0)
+        t0 = time.perf_counter()
+        while srv.status(big) == dh.JOB_QUEUED and time.perf_counter() - t0 < 5.0:
+            time.sleep(0.001)
+        time.sleep(0.02)
+        sid = srv.submit(small.coords, small.offsets, small.box_type, small.box, small.r_max,
+                         small.n_bins, 0)
+        h, _, t_small = srv.wait(sid)
+        still_running = srv.status(big) == dh.JOB_RUNNING
+        hb, _, t_big = srv.wait(big)
+    assert np.array_equal(h, alone(small, 0))
+    assert int(hb.sum()) <= huge.total_pairs()
+    print(f"\nsmall job {t_small[2] * 1e3:.1f} ms, huge job {t_big[2] * 1e3:.1f} ms", flush=True)
+    assert still_running, "the small job waited for the whole huge job"
+    assert t_small[2] < 0.25 * t_big[2]

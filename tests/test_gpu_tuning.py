@@ -114,3 +114,45 @@ def test_handwritten_cache_is_used(tmp_path):
         run_gpu(c, fr, 1)
         cfg = c.last_config()
         assert [cfg[n] for n in dh.KNOB_NAMES] == [4, 2, 128, 0, 1, 4, 512, 2]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_bounded_launches_identical(ctx, precision):
+    """Splitting a frame into many bounded launches (each with its own work
+    counter and flushes) leaves every count unchanged, in all three
+    accumulation modes."""
+    import paper_1808_01478_amd as dh
+    frames = FRAMES + [
+        workloads.random_frame(504, [6000, 2500], workloads.BOX_ORTHO, n_bins=300_000),
+    ]
+    ctx.set_config(None)
+    try:
+        for fi, fr in enumerate(frames):
+            print(f"\n[case] bounded launches frame={fi} prec={precision}", flush=True)
+            ctx.set_launch_pairs(0)
+            ref, ref_oor = run_gpu(ctx, fr, precision)
+            for limit in (1 << 24, 1 << 26):
+                ctx.set_launch_pairs(limit)
+                h, oor = run_gpu(ctx, fr, precision)
+                assert np.array_equal(h, ref), f"frame {fi}: limit {limit} changed the counts"
+                assert np.array_equal(oor, ref_oor)
+        with pytest.raises(dh.DisthistError):
+            ctx.set_launch_pairs(-1)
+        with pytest.raises(dh.DisthistError):
+            ctx.set_launch_pairs(1000)
+    finally:
+        ctx.set_launch_pairs(0)
+
+
+def test_bounded_launches_full_size(ctx):
+    fr = workloads.ortho()
+    ctx.set_config(None)
+    ctx.set_launch_pairs(0)
+    ref, _ = run_gpu(ctx, fr, 0)
+    try:
+        for limit in (3 << 33, 1 << 30):
+            ctx.set_launch_pairs(limit)
+            h, _ = run_gpu(ctx, fr, 0)
+            assert np.array_equal(h, ref), f"limit {limit}"
+    finally:
+        ctx.set_launch_pairs(0)
