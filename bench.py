@@ -173,6 +173,42 @@ def bench_wide(frame, bins=(250_000, 1_000_000, 4_000_000), steps=3):
     return {"workload": "ortho100k frame with wider histograms, binary32", "rows": rows}
 
 
+def bench_image_search(steps=3):
+    """A triclinic frame whose cut-off exceeds half the smallest cell width,
+    so the 27-image search runs: 200,000 uniform points (density of the bench
+    frame), species 120,000/80,000, r_max = 0.8 of the smallest width,
+    4,000 bins."""
+    import torch
+    import paper_1808_01478_amd as dh
+    rng = np.random.Generator(np.random.PCG64(31))
+    shape = np.array([[10.0, 0, 0], [3.0, 9.5, 0], [-2.0, 3.5, 9.0]])
+    n = 200_000
+    box = shape * (n / workloads.DENSITY / abs(np.linalg.det(shape))) ** (1.0 / 3.0)
+    x = rng.uniform(0.0, 1.0, size=(n, 3)) @ box
+    offs = [0, 120_000, n]
+    r_max = 0.8 * workloads.min_width(box)
+    pairs = n * (n - 1) // 2
+    out = {"workload": "image search: 200,000 uniform points in a skewed triclinic cell, "
+                       "species 120,000/80,000, r_max = 0.8 of the smallest width, 4,000 bins",
+           "flops_per_pair": FLOPS_PER_PAIR[3]}
+    xt = torch.from_numpy(x).cuda()
+    h = torch.empty((3, 4000), dtype=torch.int64, device="cuda")
+    with dh.Context(0) as c:
+        for prec, name in ((dh.FP32, "fp32"), (dh.FP64, "fp64")):
+            c.histo_async(xt, offs, dh.BOX_TRICLINIC, box, r_max, 4000, prec, h)
+            torch.cuda.synchronize()
+            c.profile(True)
+            for _ in range(steps):
+                c.histo_async(xt, offs, dh.BOX_TRICLINIC, box, r_max, 4000, prec, h)
+            ms, k = c.profile_read()
+            c.profile(False)
+            ms /= k
+            ach = pairs * FLOPS_PER_PAIR[3] / (ms * 1e-3) / 1e12
+            out[name] = {"kernel_ms": ms, "pairs_per_s": pairs / (ms * 1e-3),
+                         "achieved_tflops": ach, "roofline_frac": ach / PEAK_TFLOPS[prec]}
+    return out
+
+
 def bench_trajectory(ctx, n_frames: int, steps: int):
     """The trajectory workload (512 orthorhombic frames, N log-uniform in
     [1e4, 2e5], 1-4 species, 4,096 bins) in binary32: one batched graph
@@ -432,6 +468,7 @@ def main():
         line["latency_ms"]["serving_p99"] = line["serving"]["continuous_batching"]["p99_ms"]
     if args.wide:
         line["wide"] = bench_wide(frame)
+        line["image_search"] = bench_image_search()
     if args.trajectory_frames > 0:
         line["trajectory"] = bench_trajectory(ctx, args.trajectory_frames, max(1, args.steps // 5))
     if not args.no_cpu_baseline:

@@ -189,6 +189,17 @@ int frame_consts(int32_t box_type, const double *box, double r_max, int32_t n_bi
     for (int c = 0; c < 6; ++c) fp.Bk[c] = static_cast<float>(B[c] * fp.s / kTwo32);
     for (int q = 0; q < kShifts; ++q)
       for (int c = 0; c < 3; ++c) fp.shift32[q][c] = static_cast<float>(fp.shift64[q][c] * fp.s);
+    // A reduced vector shorter than half the shortest lattice vector lambda
+    // is the nearest image: every other image is at least lambda - |d| away.
+    // The margin 1e-6 puts the decision far above the rounding of q.
+    double lambda2 = 0.0;
+    for (int q = 0; q < kShifts; ++q) {
+      const double *v = fp.shift64[q];
+      const double l2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+      if (l2 > 0.0 && (lambda2 == 0.0 || l2 < lambda2)) lambda2 = l2;
+    }
+    fp.qskip64 = 0.25 * lambda2 * (1.0 - 1e-6);
+    fp.qskip32 = static_cast<float>(0.25 * lambda2 * fp.s * fp.s * (1.0 - 4e-6));
   }
   fp.box = kind;
   return kind;
@@ -219,6 +230,12 @@ struct Launch {
 };
 
 size_t coord_bytes(int precision) { return precision == DH_FP64 ? 32 : 16; }
+
+// LDS of the image-search rings (one per wave), the table of the 27 shift
+// vectors and the padding before them.
+size_t search_queue_bytes(int precision, int threads, int r) {
+  return 32 + (static_cast<size_t>(threads / 64) * queue_cap(r) + kShifts) * coord_bytes(precision);
+}
 
 // Smallest work item (pairs) when a frame is split into bounded launches.
 constexpr int64_t kMinItemPairs = int64_t{1} << 21;
@@ -299,6 +316,9 @@ BaseConfig base_config(const dh_ctx *ctx, int precision, const Knobs &k, int kin
   c.wg_per_cu = k.occ_cap;
   c.jchunk = c.tj;
   b.tile_bytes = 2 * static_cast<size_t>(c.tj) * coord_bytes(precision);
+  // the search kernels keep their queues after the histogram; counting them
+  // with the tiles leaves the histogram budget below them
+  if (kind == kBoxTricSearch) b.tile_bytes += search_queue_bytes(precision, c.threads, c.r);
   const size_t budget = std::min<size_t>(ctx->lds_per_block, 160 * 1024) - b.tile_bytes - 256;
   b.win_max = static_cast<int64_t>(budget / 4 / c.copies) - kDump;
   b.occ_cap = k.occ_cap;

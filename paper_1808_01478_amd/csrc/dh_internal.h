@@ -28,6 +28,9 @@ constexpr int32_t kItemFull = 2;  // every lane holds a valid i-particle
 
 constexpr int kShifts = 27;
 constexpr int kDump = 64;  // per-lane discard slots after the bin window
+// Per-wave LDS ring of reduced vectors waiting for the 27-image search:
+// one j adds at most 64 per i-particle of a lane (R) on top of fewer than 64.
+constexpr int queue_cap(int r) { return 64 * (r + 1); }
 
 // Constants of one frame, computed once on the host.
 //
@@ -65,7 +68,8 @@ struct FrameParams {
   float Bk[6];         // ax bx by cx cy cz, times s / 2^32
   float shift32[kShifts][3];  // image shifts times s
   int32_t noclamp;     // 1: every t of a full block fits below `stride` slots
-  int32_t pad_;
+  float qskip32;       // binary32 q (t units) below which no image is nearer
+  double qskip64;      // binary64 q below which the reduced vector is nearest
 };
 
 // One unit of work: particles [i0, i1) of the frame against [j0, j1), for

@@ -57,6 +57,9 @@ __device__ __forceinline__ double uni(double v) {
 // Distance arithmetic
 // --------------------------------------------------------------------------
 
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return fma(a, b, c); }
+
 // binary64, canonical op sequence (Algorithm 1 with Eq. 5), no contraction.
 struct Geo64 {
   double s, L0, L1, L2, iL0, iL1, iL2;
@@ -98,10 +101,14 @@ __device__ __forceinline__ double sqrt_rn(double q) {
   return fma(d, h, g);
 }
 
+// d = x_j - x_i reduced by the minimum-image rule of the box kind.
 template <int BOX>
-__device__ __forceinline__ double t64(double xi, double yi, double zi, double xj, double yj,
-                                      double zj, const Geo64 &g) {
-  double dx = xj - xi, dy = yj - yi, dz = zj - zi;
+__device__ __forceinline__ void reduce64(double xi, double yi, double zi, double xj, double yj,
+                                         double zj, const Geo64 &g, double &dx, double &dy,
+                                         double &dz) {
+  dx = xj - xi;
+  dy = yj - yi;
+  dz = zj - zi;
   if constexpr (BOX == kBoxOrtho || BOX == kBoxCube) {
     const double n0 = rint(dx * g.iL0), n1 = rint(dy * g.iL1), n2 = rint(dz * g.iL2);
     dx = fma(-g.L0, n0, dx);
@@ -116,16 +123,40 @@ __device__ __forceinline__ double t64(double xi, double yi, double zi, double xj
     dy = fma(-g.cy, nc, fma(-g.by, nb, dy));
     dx = fma(-g.cx, nc, fma(-g.bx, nb, fma(-g.ax, na, dx)));
   }
-  double q = fma(dz, dz, fma(dy, dy, dx * dx));
-  if constexpr (BOX == kBoxTricSearch) {
-    for (int m = 0; m < kShifts; ++m) {
-      const double vx = dx + uni(g.shift[m][0]);
-      const double vy = dy + uni(g.shift[m][1]);
-      const double vz = dz + uni(g.shift[m][2]);
-      const double v = fma(vz, vz, fma(vy, vy, vx * vx));
-      q = v < q ? v : q;
+}
+
+// Minimum of q over the 27 images d + S (S = 0 gives q itself). Every q is
+// a sum of squares (never -0), so fmin equals the select v < q ? v : q,
+// NaN included (a NaN d makes every image NaN); the minimum of such values
+// does not depend on the order, so three running minima give the chain
+// more independent work.
+__device__ __forceinline__ double search_q64(double dx, double dy, double dz, double q,
+                                             const Geo64 &g) {
+  double qa = q, qb = q, qc = q;
+#pragma unroll
+  for (int m = 0; m < kShifts; m += 3) {
+    double v[3];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const double vx = dx + uni(g.shift[m + u][0]);
+      const double vy = dy + uni(g.shift[m + u][1]);
+      const double vz = dz + uni(g.shift[m + u][2]);
+      v[u] = fma(vz, vz, fma(vy, vy, vx * vx));
     }
+    qa = fmin(qa, v[0]);
+    qb = fmin(qb, v[1]);
+    qc = fmin(qc, v[2]);
   }
+  return fmin(qa, fmin(qb, qc));
+}
+
+template <int BOX>
+__device__ __forceinline__ double t64(double xi, double yi, double zi, double xj, double yj,
+                                      double zj, const Geo64 &g) {
+  double dx, dy, dz;
+  reduce64<BOX>(xi, yi, zi, xj, yj, zj, g, dx, dy, dz);
+  double q = fma(dz, dz, fma(dy, dy, dx * dx));
+  if constexpr (BOX == kBoxTricSearch) q = search_q64(dx, dy, dz, q, g);
   return sqrt_rn(q) * g.s;
 }
 
@@ -158,6 +189,39 @@ __device__ __forceinline__ float frac_diff(float ui, float uj) {
 template <int BOX>
 __device__ __forceinline__ float t32_packed(uint64_t ab_j, uint64_t neg_ab_i, float zi, float zj,
                                             const Geo32 &g);
+
+// Triclinic reduced vector (t units) from packed fractional words.
+__device__ __forceinline__ void tric_vec32(uint64_t ab_j, uint64_t neg_ab_i, float zi, float zj,
+                                           const Geo32 &g, float &dx, float &dy, float &dz) {
+  const uint64_t dab = ab_j + neg_ab_i;
+  const float fa = static_cast<float>(static_cast<int32_t>(static_cast<uint32_t>(dab)));
+  const float fb = static_cast<float>(static_cast<int32_t>(static_cast<uint32_t>(dab >> 32)));
+  const float fc = frac_diff(zi, zj);
+  dx = fmaf(g.cx, fc, fmaf(g.bx, fb, g.ax * fa));
+  dy = fmaf(g.cy, fc, g.by * fb);
+  dz = g.cz * fc;
+}
+
+// Minimum of q over the 27 images (binary32, t units), three running minima.
+__device__ __forceinline__ float search_q32(float dx, float dy, float dz, float q,
+                                            const Geo32 &g) {
+  float qa = q, qb = q, qc = q;
+#pragma unroll
+  for (int m = 0; m < kShifts; m += 3) {
+    float v[3];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const float vx = dx + uni(g.shift[m + u][0]);
+      const float vy = dy + uni(g.shift[m + u][1]);
+      const float vz = dz + uni(g.shift[m + u][2]);
+      v[u] = fmaf(vz, vz, fmaf(vy, vy, vx * vx));
+    }
+    qa = fminf(qa, v[0]);
+    qb = fminf(qb, v[1]);
+    qc = fminf(qc, v[2]);
+  }
+  return fminf(qa, fminf(qb, qc));
+}
 
 template <int BOX>
 __device__ __forceinline__ float t32(float xi, float yi, float zi, float xj, float yj, float zj,
@@ -194,17 +258,34 @@ __device__ __forceinline__ float t32_packed(uint64_t ab_j, uint64_t neg_ab_i, fl
       const float dy = fmaf(g.cy, fc, g.by * fb);
       const float dz = g.cz * fc;
       float q = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-      if constexpr (BOX == kBoxTricSearch) {
-        for (int m = 0; m < kShifts; ++m) {
-          const float vx = dx + uni(g.shift[m][0]);
-          const float vy = dy + uni(g.shift[m][1]);
-          const float vz = dz + uni(g.shift[m][2]);
-          q = fminf(q, fmaf(vz, vz, fmaf(vy, vy, vx * vx)));
-        }
-      }
+      if constexpr (BOX == kBoxTricSearch) q = search_q32(dx, dy, dz, q, g);
       return __builtin_amdgcn_sqrtf(q);
     }
   }
+}
+
+// Minimum of q over the 27 images, shifts read from an LDS table (broadcast
+// reads); the same operations as search_q64 / search_q32.
+template <typename T>
+__device__ __forceinline__ T search_lds(T dx, T dy, T dz, T q,
+                                        const typename V4<T>::type *__restrict__ sh) {
+  T qa = q, qb = q, qc = q;
+#pragma unroll
+  for (int m = 0; m < kShifts; m += 3) {
+    T v[3];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const typename V4<T>::type S = sh[m + u];
+      const T vx = dx + S.x;
+      const T vy = dy + S.y;
+      const T vz = dz + S.z;
+      v[u] = fmaT(vz, vz, fmaT(vy, vy, vx * vx));
+    }
+    qa = fmin(qa, v[0]);
+    qb = fmin(qb, v[1]);
+    qc = fmin(qc, v[2]);
+  }
+  return fmin(qa, fmin(qb, qc));
 }
 
 template <typename T>
@@ -360,15 +441,24 @@ __device__ __forceinline__ void flush_hist(uint32_t *hist, const PairKernelArgs 
 // CLAMP = false: the host proved that every t of this frame is below the LDS
 // stride and the block has no invalid lanes, so the bin index needs no clamp
 // (out-of-range pairs land in slots [n_bins, stride) that are never flushed).
+//
+// BOX = kBoxTricSearch: the 27-image search only runs for pairs whose reduced
+// vector is not provably the nearest image (q0 >= qskip: at least half the
+// shortest lattice vector long). Those pairs are queued per wave in LDS and
+// searched 64 at a time by the whole wave, so the search never runs for a
+// wave with only a few lanes needing it; the others are counted directly.
 template <typename T, int R, int BOX, int MODE, bool DIAG, bool CLAMP>
 __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem &w,
                                          const FrameParams *F,
                                          typename V4<T>::type *__restrict__ tile,
-                                         uint32_t *__restrict__ my) {
+                                         uint32_t *__restrict__ my,
+                                         typename V4<T>::type *__restrict__ queue,
+                                         typename V4<T>::type *__restrict__ sh) {
   using V = typename V4<T>::type;
   using G = typename Geo<T>::type;
   constexpr bool SWEEP = MODE == kModeSweep;
   constexpr bool GLOBAL = MODE == kModeGlobal;
+  constexpr bool SEARCH = BOX == kBoxTricSearch;
   const V *__restrict__ X = static_cast<const V *>(F->coords);
   const G g = Geo<T>::load(F);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -410,18 +500,95 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
   const float hif = static_cast<float>(hi);
 #pragma unroll
   for (int r = 0; r < R; ++r) lof[r] = static_cast<float>(lo[r]);
-  // global mode: a pair counts iff t < n_bins (in the working precision);
-  // ragged lanes get a limit no t reaches
-  T glim[R];
   const int n_bins = uni(F->n_bins);
-#pragma unroll
-  for (int r = 0; r < R; ++r) glim[r] = lo[r] == 0u ? static_cast<T>(n_bins) : T(-1);
   // the output is global memory: say so, so the atomics are global_atomic_*
   // (a generic pointer would give flat atomics, which also count as LDS
   // operations in lgkmcnt)
   using GlobalU64 = __attribute__((address_space(1))) unsigned long long;
   GlobalU64 *const gout =
       (GlobalU64 *)(F->out + static_cast<size_t>(w.hist) * static_cast<size_t>(n_bins));
+
+  // Counts one pair at scaled distance t. l / lf: lower clamp, 0 for a pair
+  // that counts, the lane's discard slot for one that must not.
+  auto count_t = [&](T t, uint32_t l, float lf) {
+    if constexpr (GLOBAL) {
+      // a pair counts iff t < n_bins (in the working precision)
+      if (l == 0u && t < static_cast<T>(n_bins))
+        __hip_atomic_fetch_add(gout + static_cast<uint32_t>(t), 1ull, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      uint32_t idx;
+      if constexpr (!CLAMP) {
+        if constexpr (sizeof(T) == 4) {
+          // fixed-point staging bounds every binary32 t below the stride
+          idx = static_cast<uint32_t>(t);
+        } else {
+          // binary64 reads raw device coordinates: cap t so that even
+          // non-finite or absurd input stays inside the LDS histogram
+          idx = static_cast<uint32_t>(fmin(t, cap64));
+        }
+      } else if constexpr (sizeof(T) == 4 && !SWEEP) {
+        idx = static_cast<uint32_t>(__builtin_amdgcn_fmed3f(t, lf, hif));
+      } else {
+        // floor(t), saturated; t >= 0 always
+        if constexpr (sizeof(T) == 4)
+          idx = static_cast<uint32_t>(fminf(t, 4294967040.0f));
+        else
+          idx = static_cast<uint32_t>(fmin(t, 4294967295.0));
+        if constexpr (SWEEP) idx -= static_cast<uint32_t>(b_lo);
+        idx = max(min(idx, hi), l);
+      }
+      // byte offset with one shift (copies interleaved bin-major), so the
+      // address is a single v_lshl_add_u32
+      atomicAdd(reinterpret_cast<uint32_t *>(my_bytes + (idx << shift_bytes)), 1u);
+    }
+  };
+
+  // image-search ring of this wave: qn entries from head (wave-uniform)
+  constexpr int cap = queue_cap(R);
+  V *const wq = queue + wave * cap;
+  int head = 0, qn = 0;
+  [[maybe_unused]] T qskip;
+  if constexpr (sizeof(T) == 4)
+    qskip = uni(F->qskip32);
+  else
+    qskip = uni(F->qskip64);
+  if constexpr (SEARCH) {
+    // this frame's shift table; read after the first tile barrier below
+    if (tid < kShifts) {
+      V S;
+      if constexpr (sizeof(T) == 4) {
+        S.x = F->shift32[tid][0]; S.y = F->shift32[tid][1]; S.z = F->shift32[tid][2];
+      } else {
+        S.x = F->shift64[tid][0]; S.y = F->shift64[tid][1]; S.z = F->shift64[tid][2];
+      }
+      S.w = T(0);
+      sh[tid] = S;
+    }
+  }
+  // searches and counts the `cnt` (<= 64) oldest queued vectors
+  auto drain = [&](int cnt) {
+    if constexpr (SEARCH) {
+      __builtin_amdgcn_wave_barrier();
+      const bool v = lane < cnt;
+      int idx = head + (v ? lane : 0);
+      if (idx >= cap) idx -= cap;
+      const V e = wq[idx];
+      T q = fmaT(e.z, e.z, fmaT(e.y, e.y, e.x * e.x));
+      q = search_lds<T>(e.x, e.y, e.z, q, sh);
+      T t;
+      if constexpr (sizeof(T) == 4)
+        t = __builtin_amdgcn_sqrtf(q);
+      else
+        t = sqrt_rn(q) * g.s;
+      count_t(t, v ? 0u : hi, v ? 0.f : hif);
+      head += cnt;
+      if (head >= cap) head -= cap;
+      qn -= cnt;
+      __builtin_amdgcn_wave_barrier();
+    }
+  };
+
   // The i-particles are complete before the tile loop, so the only global
   // load in flight inside it is the next tile's prefetch, which the j-loop
   // never reads.
@@ -461,69 +628,82 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
       auto pairs_of = [&](const J &pj, int j) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          T t;
-          if constexpr (kPacked)
-            t = t32_packed<BOX>(pj.ab, nab[r], zi[r], pj.z, g);
-          else
-            t = pair_t<T, BOX>(xi[r], yi[r], zi[r], pj.x, pj.y, pj.z, g);
-          if constexpr (GLOBAL) {
-            bool ok = t < glim[r];
-            if constexpr (DIAG) ok = ok && (j > wbase + r * 64 + lane);
-            if (ok)
-              __hip_atomic_fetch_add(gout + static_cast<uint32_t>(t), 1ull, __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_AGENT);
-          } else {
-            uint32_t idx;
-            if constexpr (!CLAMP) {
-              if constexpr (sizeof(T) == 4) {
-                // fixed-point staging bounds every binary32 t below the stride
-                idx = static_cast<uint32_t>(t);
-              } else {
-                // binary64 reads raw device coordinates: cap t so that even
-                // non-finite or absurd input stays inside the LDS histogram
-                idx = static_cast<uint32_t>(fmin(t, cap64));
+          uint32_t l = lo[r];
+          float lf = lof[r];
+          if constexpr (DIAG) {
+            const bool up = j > wbase + r * 64 + lane;
+            l = up ? l : hi;
+            lf = up ? lf : hif;
+          }
+          if constexpr (SEARCH) {
+            T dx, dy, dz;
+            if constexpr (kPacked)
+              tric_vec32(pj.ab, nab[r], zi[r], pj.z, g, dx, dy, dz);
+            else
+              reduce64<BOX>(xi[r], yi[r], zi[r], pj.x, pj.y, pj.z, g, dx, dy, dz);
+            const T q0 = fmaT(dz, dz, fmaT(dy, dy, dx * dx));
+            // valid pairs at least half the shortest lattice vector long
+            // are searched later; they must not count now
+            const bool need = l == 0u && q0 >= qskip;
+            T t;
+            if constexpr (sizeof(T) == 4)
+              t = __builtin_amdgcn_sqrtf(q0);
+            else
+              t = sqrt_rn(q0) * g.s;
+            count_t(t, need ? hi : l, need ? hif : lf);
+            const uint64_t m = __builtin_amdgcn_ballot_w64(need);
+            if (m != 0) {
+              const int below = __builtin_amdgcn_mbcnt_hi(
+                  static_cast<uint32_t>(m >> 32),
+                  __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
+              if (need) {
+                int pos = head + qn + below;  // < 2 cap: head < cap, qn + below < cap
+                if (pos >= cap) pos -= cap;
+                V e;
+                e.x = dx; e.y = dy; e.z = dz; e.w = T(0);
+                wq[pos] = e;
               }
-            } else if constexpr (sizeof(T) == 4 && !SWEEP) {
-              float l = lof[r];
-              if constexpr (DIAG) l = (j > wbase + r * 64 + lane) ? l : hif;
-              idx = static_cast<uint32_t>(__builtin_amdgcn_fmed3f(t, l, hif));
-            } else {
-              uint32_t l = lo[r];
-              if constexpr (DIAG) l = (j > wbase + r * 64 + lane) ? l : hi;
-              // floor(t), saturated; t >= 0 always
-              if constexpr (sizeof(T) == 4)
-                idx = static_cast<uint32_t>(fminf(t, 4294967040.0f));
-              else
-                idx = static_cast<uint32_t>(fmin(t, 4294967295.0));
-              if constexpr (SWEEP) idx -= static_cast<uint32_t>(b_lo);
-              idx = max(min(idx, hi), l);
+              qn += __builtin_popcountll(m);
             }
-            // byte offset with one shift (copies interleaved bin-major), so the
-            // address is a single v_lshl_add_u32
-            atomicAdd(reinterpret_cast<uint32_t *>(my_bytes + (idx << shift_bytes)), 1u);
+          } else {
+            T t;
+            if constexpr (kPacked)
+              t = t32_packed<BOX>(pj.ab, nab[r], zi[r], pj.z, g);
+            else
+              t = pair_t<T, BOX>(xi[r], yi[r], zi[r], pj.x, pj.y, pj.z, g);
+            count_t(t, l, lf);
           }
         }
+        if constexpr (SEARCH)
+          while (qn >= 64) drain(64);
       };
       // Ping-pong over two j registers: the read of the next j is issued
       // before the current j's atomics. LDS operations complete in order, so
       // a read issued after the atomics would wait for all of them
       // (bank-conflicted) before the arithmetic could start.
-      J pa = load_j(js);
-      __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
-      int jj = js;
-      for (; jj + 1 < jcount; jj += 2) {
-        const J pb = load_j(jj + 1);
-        // binary32: pin the read ahead of the atomics (measured faster);
-        // binary64 has enough arithmetic per j to hide it unpinned
-        if constexpr (sizeof(T) == 4) __builtin_amdgcn_sched_barrier(0);
-        pairs_of(pa, jt + jj);
-        pa = load_j(min(jj + 2, jcount - 1));
-        if constexpr (sizeof(T) == 4) __builtin_amdgcn_sched_barrier(0);
-        pairs_of(pb, jt + jj + 1);
+      if constexpr (SEARCH) {
+        // one copy of the search code: a plain j loop
+        for (int jj = js; jj < jcount; ++jj) pairs_of(load_j(jj), jt + jj);
+      } else {
+        J pa = load_j(js);
+        __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+        int jj = js;
+        for (; jj + 1 < jcount; jj += 2) {
+          const J pb = load_j(jj + 1);
+          // binary32: pin the read ahead of the atomics (measured faster);
+          // binary64 has enough arithmetic per j to hide it unpinned
+          if constexpr (sizeof(T) == 4) __builtin_amdgcn_sched_barrier(0);
+          pairs_of(pa, jt + jj);
+          pa = load_j(min(jj + 2, jcount - 1));
+          if constexpr (sizeof(T) == 4) __builtin_amdgcn_sched_barrier(0);
+          pairs_of(pb, jt + jj + 1);
+        }
+        if (jj < jcount) pairs_of(pa, jt + jj);
       }
-      if (jj < jcount) pairs_of(pa, jt + jj);
     }
   }
+  if constexpr (SEARCH)
+    if (qn > 0) drain(qn);
 }
 
 // Workgroups of up to 1024 threads share one LDS histogram (more waves per
@@ -545,6 +725,11 @@ __global__ __launch_bounds__(max_threads<BOX>()) void pairs_kernel(PairKernelArg
   // lane-interleaved sub-histogram copies: lanes of one instruction that
   // hit the same bin use different words (and banks) when copies > 1
   uint32_t *my = hist + (tid & 63) % a.copies;
+  // image-search queues after the histogram, 32-byte aligned
+  const size_t q_off = (2 * static_cast<size_t>(a.tj) * sizeof(V) +
+                        static_cast<size_t>(a.copies) * a.stride * 4 + 31) / 32 * 32;
+  V *queue = reinterpret_cast<V *>(smem + q_off);
+  V *shifts = queue + (blockDim.x / 64) * queue_cap(R);
 
   constexpr bool GLOBAL = MODE == kModeGlobal;
   if constexpr (!GLOBAL)
@@ -581,14 +766,16 @@ __global__ __launch_bounds__(max_threads<BOX>()) void pairs_kernel(PairKernelArg
     }
     const FrameParams *F = a.frames + w.frame;
     if (w.flags & kItemDiag) {
-      run_item<T, R, BOX, MODE, true, true>(a, w, F, tile, my);
+      run_item<T, R, BOX, MODE, true, true>(a, w, F, tile, my, queue, shifts);
     } else {
+      // the search needs the clamp to hold back queued pairs
       bool clamp = true;
-      if constexpr (MODE == kModeLds) clamp = !((w.flags & kItemFull) && uni(F->noclamp));
+      if constexpr (MODE == kModeLds && BOX != kBoxTricSearch)
+        clamp = !((w.flags & kItemFull) && uni(F->noclamp));
       if (clamp)
-        run_item<T, R, BOX, MODE, false, true>(a, w, F, tile, my);
-      else if constexpr (MODE == kModeLds)
-        run_item<T, R, BOX, kModeLds, false, false>(a, w, F, tile, my);
+        run_item<T, R, BOX, MODE, false, true>(a, w, F, tile, my, queue, shifts);
+      else if constexpr (MODE == kModeLds && BOX != kBoxTricSearch)
+        run_item<T, R, BOX, kModeLds, false, false>(a, w, F, tile, my, queue, shifts);
     }
   }
   if constexpr (!GLOBAL)

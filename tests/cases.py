@@ -55,6 +55,25 @@ def parity_cases():
     out[-1].name = "one-bin"
     tr = workloads.trajectory_frame(7)
     out.append(tr.subset([4000] * tr.n_species))
+    # image search: nearly every pair needs it (r_max close to the longest
+    # reduced vector of a strongly skewed cell)
+    sheared = np.array([[9.0, 0, 0], [4.4, 8.0, 0], [-4.3, 3.9, 7.5]])
+    out.append(workloads.random_frame(19, [1400, 900], workloads.BOX_TRICLINIC, box=sheared,
+                                      r_max=0.98 * workloads.min_width(sheared) * 1.2,
+                                      n_bins=400))
+    out[-1].name = "tric-search-sheared"
+    # an orthogonal cell given as triclinic, beyond half its width: every
+    # image lies on a tie boundary of the reduced cube
+    out.append(workloads.random_frame(20, [1600], workloads.BOX_TRICLINIC,
+                                      box=workloads.ortho_box(9.0, 10.0, 11.0), r_max=7.0,
+                                      n_bins=350))
+    out[-1].name = "tric-search-orthogonal"
+    # a dyadic lattice of points in a dyadic cell: many fractional
+    # differences are exactly +-1/2, and many distances repeat exactly
+    cell = np.array([[8.0, 0, 0], [2.0, 8.0, 0], [-2.0, 2.0, 8.0]])
+    grid = np.stack(np.meshgrid(*[np.arange(8) / 8.0] * 3, indexing="ij"), -1).reshape(-1, 3)
+    out.append(_frame(grid @ cell, [300, len(grid) - 300], workloads.BOX_TRICLINIC, cell,
+                      0.75 * workloads.min_width(cell), 97, "tric-search-lattice-ties"))
     return out
 
 
