@@ -296,6 +296,52 @@ int32_t dh_sched_select(const int64_t *need_bytes, const double *waited_s, int32
                         int32_t *admit);
 
 /* ---------------------------------------------------------------------------
+ * Trajectory engine (the paper's frame-parallel engine reads frames, runs
+ * them on its workers and sums the histograms over intervals of frames in
+ * its writer, Sec. 3.3 and Sec. 4.4; this is its one-GPU form).
+ *
+ * Trajectory file (little-endian): a 64-byte header
+ *   char magic[8] = "DHTRAJ01"; int64 n_frames; int64 n_points;
+ *   int32 box_type; zero padding to 64 bytes
+ * then n_frames frames of (double box[9], rows a, b, c; zeros for
+ * DH_BOX_NONE) followed by double coords[n_points][3]. The species layout
+ * (offsets) is the same for every frame and passed to dh_traj_histo.
+ * dh_traj_open checks the header and the file size (DH_EINVAL otherwise);
+ * the handle reads the file, it never writes it.
+ */
+typedef struct dh_traj dh_traj;
+int dh_traj_open(const char *path, dh_traj **out);
+int dh_traj_info(const dh_traj *t, int64_t *n_frames, int64_t *n_points, int32_t *box_type);
+void dh_traj_close(dh_traj *t);
+
+/*
+ * Histograms of frames [frame_begin, frame_end), summed over consecutive
+ * intervals of `interval` frames (the last interval may be shorter). A host
+ * thread reads frames into pinned buffers, the copy of frame f + 1 to the
+ * device overlaps the histogram of frame f, and each frame runs the same
+ * path as dh_histo_async (its own box, tuned shapes of ctx), adding into the
+ * interval's sums.
+ *
+ * results_path receives a 128-byte header (magic "DHRES001", a hash of all
+ * parameters and the species offsets, then the parameters) followed by one
+ * record per finished interval: uint64 hist[H][n_bins], uint64
+ * out_of_range[H], uint64 frames_in_interval. Each record is written and
+ * synced before the next interval starts, so the file is the checkpoint: a
+ * call with the same parameters and an existing file skips the intervals
+ * already recorded (a partial trailing record is cut off and redone); a
+ * file of other parameters gives DH_EINVAL. max_intervals > 0 stops after
+ * that many new intervals (0: run to frame_end). *intervals_done receives
+ * the number of complete records in the file on return. An invalid frame
+ * (its box) stops the run with that frame's error before its interval is
+ * recorded. Blocks until done; ctx must not be used by another thread
+ * meanwhile.
+ */
+int dh_traj_histo(dh_ctx *ctx, dh_traj *t, const int64_t *species_offsets, int32_t n_species,
+                  double r_max, int32_t n_bins, int32_t precision, int64_t frame_begin,
+                  int64_t frame_end, int64_t interval, const char *results_path,
+                  int64_t max_intervals, int64_t *intervals_done);
+
+/* ---------------------------------------------------------------------------
  * Launch tuning. The launch shape of a frame (i-particles per lane, LDS
  * sub-histogram copies, j-tile length, unclamped interior blocks, workgroups
  * per CU, work items per workgroup, workgroup size, and for histograms wider

@@ -566,6 +566,7 @@ struct FrameJob {
   uint64_t total = 0;
   uint64_t *d_out = nullptr;
   uint64_t *d_oor = nullptr;
+  bool accumulate = false;  // add into d_out instead of overwriting it
 };
 
 // Plans and enqueues one frame with the given knobs: stage (optional), zero,
@@ -615,8 +616,10 @@ int run_frame(dh_ctx *ctx, hipStream_t st, const FrameJob &job, const Knobs &k, 
   if (rc) return rc;
   char *db = static_cast<char *>(ctx->d_blob);
   if (stage) DH_HIP(ctx, launch_stage(job.precision, job.kind, job.d_coords, ctx->d_staged, n, fp, st));
-  DH_HIP(ctx, launch_zero(job.d_out, static_cast<int64_t>(n_hist) * fp.n_bins,
-                          reinterpret_cast<int32_t *>(db + lay.counter), st));
+  // (the work counters are zeroed with the blob upload)
+  if (!job.accumulate)
+    DH_HIP(ctx, launch_zero(job.d_out, static_cast<int64_t>(n_hist) * fp.n_bins,
+                            reinterpret_cast<int32_t *>(db + lay.counter), st));
   const int grid = std::max(1, std::min<int>(L.grid, static_cast<int>(items.size())));
   if (e0) DH_HIP(ctx, hipEventRecord(e0, st));
   for (size_t c = 0; c < n_launches && !items.empty(); ++c) {
@@ -805,6 +808,12 @@ std::map<int, dh_ctx *> g_default;
 
 namespace dh {
 
+int ctx_device(const dh_ctx *ctx) { return ctx->device; }
+
+int zero_u64(uint64_t *p, int64_t n, hipStream_t st) {
+  return launch_zero(p, n, nullptr, st) == hipSuccess ? DH_OK : DH_EDEVICE;
+}
+
 size_t ctx_device_bytes(const dh_ctx *ctx) {
   return ctx->staged_cap + ctx->blob_cap + ctx->in_cap + ctx->out_cap;
 }
@@ -929,6 +938,19 @@ const char *dh_ctx_last_error(const dh_ctx *ctx) {
 int dh_histo_async(dh_ctx *ctx, dh_stream stream, const double *d_coords, const int64_t *offsets,
                    int32_t n_species, int32_t box_type, const double *box, double r_max,
                    int32_t n_bins, int32_t precision, uint64_t *d_out, uint64_t *d_out_of_range) {
+  return dh::histo_job(ctx, static_cast<hipStream_t>(stream), d_coords, offsets, n_species,
+                       box_type, box, r_max, n_bins, precision, d_out, d_out_of_range, false,
+                       nullptr);
+}
+
+}  // extern "C"
+
+namespace dh {
+
+int histo_job(dh_ctx *ctx, hipStream_t stream, const double *d_coords, const int64_t *offsets,
+              int32_t n_species, int32_t box_type, const double *box, double r_max,
+              int32_t n_bins, int32_t precision, uint64_t *d_out, uint64_t *d_out_of_range,
+              bool accumulate, uint64_t *total_pairs) {
   if (!ctx) return DH_EINVAL;
   int rc = check(nullptr, offsets, n_species, box_type, box, r_max, n_bins, precision);
   if (rc) return fail(ctx, rc, "invalid arguments");
@@ -943,7 +965,8 @@ int dh_histo_async(dh_ctx *ctx, dh_stream stream, const double *d_coords, const 
   job.n_species = n_species;
   job.precision = precision;
   job.d_out = d_out;
-  job.d_oor = d_out_of_range;
+  job.d_oor = accumulate ? nullptr : d_out_of_range;
+  job.accumulate = accumulate;
   job.kind = frame_consts(box_type, box, r_max, n_bins, job.fp);
   if (precision == DH_FP32 && job.kind == kBoxOrtho && job.fp.L[0] == job.fp.L[1] &&
       job.fp.L[1] == job.fp.L[2])
@@ -966,11 +989,13 @@ int dh_histo_async(dh_ctx *ctx, dh_stream stream, const double *d_coords, const 
     auto it = ctx->tune_cache.find(key);
     if (it != ctx->tune_cache.end()) {
       k = Knobs::unpack(it->second);
-    } else if (ctx->tune_mode == DH_TUNE_ON && job.total > 0) {
+    } else if (ctx->tune_mode == DH_TUNE_ON && job.total > 0 && !accumulate) {
+      // (tuning overwrites the output, so accumulating calls never tune)
       rc = tune_frame(ctx, st, job, key, k);
       if (rc) return rc;
     }
   }
+  if (total_pairs) *total_pairs = job.total;
 
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ctx->profile) {
@@ -986,6 +1011,10 @@ int dh_histo_async(dh_ctx *ctx, dh_stream stream, const double *d_coords, const 
   }
   return run_frame(ctx, st, job, k, true, e0, e1);
 }
+
+}  // namespace dh
+
+extern "C" {
 
 int dh_histo(const double *coords, const int64_t *offsets, int32_t n_species, int32_t box_type,
              const double *box, double r_max, int32_t n_bins, int32_t precision, uint64_t *out) {

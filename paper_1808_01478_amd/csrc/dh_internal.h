@@ -131,4 +131,15 @@ size_t ctx_device_bytes(const dh_ctx *ctx);
 void ctx_release_scratch(dh_ctx *ctx);
 // device footprint of a single-frame job besides the caller's buffers
 size_t job_scratch_bytes(int64_t n_points, int32_t n_hist, int32_t n_bins, int32_t precision);
+// device ordinal of a context
+int ctx_device(const dh_ctx *ctx);
+// zeroes n words with a kernel on stream st (never a memset node in graphs)
+int zero_u64(uint64_t *p, int64_t n, hipStream_t st);
+// dh_histo_async with an accumulate option: when set, the frame's counts are
+// added into d_out (not zeroed first) and no out-of-range counts are written;
+// total_pairs (optional) receives the frame's pair count.
+int histo_job(dh_ctx *ctx, hipStream_t stream, const double *d_coords, const int64_t *offsets,
+              int32_t n_species, int32_t box_type, const double *box, double r_max,
+              int32_t n_bins, int32_t precision, uint64_t *d_out, uint64_t *d_out_of_range,
+              bool accumulate, uint64_t *total_pairs);
 }  // namespace dh

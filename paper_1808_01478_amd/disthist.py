@@ -46,6 +46,12 @@ SIGNATURES = {
     "dh_server_stats": ([_vp, _vp], ctypes.c_int),
     "dh_server_destroy": ([_vp], None),
     "dh_sched_select": ([_vp, _vp, _i32, _i64, _i32, _f64, _vp], ctypes.c_int32),
+    "dh_traj_open": ([ctypes.c_char_p, ctypes.POINTER(_vp)], ctypes.c_int),
+    "dh_traj_info": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i32)],
+                     ctypes.c_int),
+    "dh_traj_close": ([_vp], None),
+    "dh_traj_histo": ([_vp, _vp, _vp, _i32, _f64, _i32, _i32, _i64, _i64, _i64, ctypes.c_char_p,
+                       _i64, ctypes.POINTER(_i64)], ctypes.c_int),
     "dh_ctx_set_tuning": ([_vp, _i32, ctypes.c_char_p], ctypes.c_int),
     "dh_ctx_set_config": ([_vp, _vp], ctypes.c_int),
     "dh_ctx_last_config": ([_vp, _vp], ctypes.c_int),
@@ -383,6 +389,48 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+class Trajectory:
+    """dh_traj: a trajectory file opened for the trajectory engine."""
+
+    def __init__(self, path: str):
+        h = ctypes.c_void_p()
+        _check(LIB.dh_traj_open(os.fsencode(path), ctypes.byref(h)))
+        self.handle = h
+        self.path = path
+
+    def info(self) -> dict:
+        nf, n = ctypes.c_int64(), ctypes.c_int64()
+        bt = ctypes.c_int32()
+        _check(LIB.dh_traj_info(self.handle, ctypes.byref(nf), ctypes.byref(n), ctypes.byref(bt)))
+        return {"n_frames": nf.value, "n_points": n.value, "box_type": bt.value}
+
+    def histo(self, ctx: "Context", offsets, r_max: float, n_bins: int, precision: int,
+              results_path: str, interval: int = 1, frame_begin: int = 0,
+              frame_end: Optional[int] = None, max_intervals: int = 0) -> int:
+        """dh_traj_histo: interval sums appended to results_path (which is also
+        the checkpoint); returns the number of complete intervals recorded."""
+        o = _offsets(offsets)
+        if frame_end is None:
+            frame_end = self.info()["n_frames"]
+        done = ctypes.c_int64()
+        _check(LIB.dh_traj_histo(ctx.handle, self.handle, _np_ptr(o), len(o) - 1, float(r_max),
+                                 int(n_bins), int(precision), int(frame_begin), int(frame_end),
+                                 int(interval), os.fsencode(results_path), int(max_intervals),
+                                 ctypes.byref(done)), ctx.handle)
+        return done.value
+
+    def close(self) -> None:
+        if self.handle:
+            LIB.dh_traj_close(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def exported_symbols() -> Sequence[str]:

@@ -1,0 +1,108 @@
+"""The trajectory engine on the GPU: interval sums equal the sums of the
+per-frame histograms (identical arithmetic, integer sums), binary64
+equals the oracle, and the results file works as a checkpoint: a run
+stopped early and resumed, or one whose last record was cut short, ends
+with the same bytes as an uninterrupted run."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def make_traj(path, kind, n_frames=13, sizes=(1800, 1200), seed=41):
+    from paper_1808_01478_amd import trajfile
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = sum(sizes)
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    xs, boxes, frames = [], [], []
+    base = np.array([[14.0, 0, 0], [3.0, 13.0, 0], [-2.0, 4.0, 12.5]])
+    for f in range(n_frames):
+        s = 1.0 + 0.02 * np.sin(f)
+        if kind == workloads.BOX_NONE:
+            box = None
+            x = rng.uniform(0, 12.0, size=(n, 3))
+            r_max = 12.0
+        elif kind == workloads.BOX_ORTHO:
+            box = workloads.ortho_box(14.0 * s, 13.0 * s, 12.5 * s)
+            x = rng.uniform(-5, 20, size=(n, 3))          # unwrapped coordinates
+            r_max = 6.0
+        else:
+            box = base * s
+            x = rng.uniform(0, 1, size=(n, 3)) @ box
+            r_max = 0.8 * workloads.min_width(base)          # image search
+        xs.append(x)
+        boxes.append(box)
+        frames.append(workloads.Frame(np.ascontiguousarray(x), offs, kind, box, r_max, 300,
+                                      f"traj{kind}-{f}"))
+    trajfile.write_trajectory(path, xs, kind, None if kind == workloads.BOX_NONE else boxes)
+    return frames
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1808_01478_amd as dh
+    c = dh.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_interval_sums(ctx, tmp_path, kind, precision):
+    import paper_1808_01478_amd as dh
+    from paper_1808_01478_amd import trajfile
+    p = str(tmp_path / "t.dhtraj")
+    frames = make_traj(p, kind)
+    f0 = frames[0]
+    print(f"\n[case] trajectory box={kind} prec={precision}", flush=True)
+    res = str(tmp_path / "r.dhres")
+    with dh.Trajectory(p) as t:
+        done = t.histo(ctx, f0.offsets, f0.r_max, f0.n_bins, precision, res, interval=4,
+                       frame_begin=1, frame_end=13)
+    assert done == 3
+    info, hist, oor, nfr = trajfile.read_results(res, f0.n_hist)
+    assert info["interval"] == 4 and list(nfr) == [4, 4, 4]
+    per = [run_gpu(ctx, fr, precision) for fr in frames]
+    for k in range(3):
+        sel = range(1 + 4 * k, 5 + 4 * k)
+        want = sum(per[f][0].astype(np.uint64) for f in sel)
+        want_oor = sum(per[f][1].astype(np.uint64) for f in sel)
+        assert np.array_equal(hist[k], want), f"interval {k}"
+        assert np.array_equal(oor[k], want_oor)
+    if precision == 1:
+        ref = sum(oracle.frame_histogram(frames[f]).hist for f in (1, 2, 3, 4))
+        assert np.array_equal(hist[0], ref)
+
+
+def test_checkpoint_resume(ctx, tmp_path):
+    import paper_1808_01478_amd as dh
+    p = str(tmp_path / "t.dhtraj")
+    frames = make_traj(p, 1, n_frames=11)
+    f0 = frames[0]
+    args = (f0.offsets, f0.r_max, f0.n_bins, 0)
+    full = str(tmp_path / "full.dhres")
+    part = str(tmp_path / "part.dhres")
+    with dh.Trajectory(p) as t:
+        assert t.histo(ctx, *args, full, interval=3) == 4
+        assert t.histo(ctx, *args, part, interval=3, max_intervals=2) == 2
+        size2 = len(open(part, "rb").read())
+        assert t.histo(ctx, *args, part, interval=3) == 4          # resumes
+        assert open(part, "rb").read() == open(full, "rb").read()
+        # a cut-short last record is dropped and redone
+        raw = open(full, "rb").read()
+        cut = str(tmp_path / "cut.dhres")
+        open(cut, "wb").write(raw[:size2 + 100])
+        assert t.histo(ctx, *args, cut, interval=3) == 4
+        assert open(cut, "rb").read() == raw
+        # nothing left to do: the file is unchanged
+        assert t.histo(ctx, *args, full, interval=3) == 4
+        assert open(full, "rb").read() == raw
+        # a results file of other parameters is refused
+        with pytest.raises(dh.DisthistError):
+            t.histo(ctx, f0.offsets, f0.r_max * 0.5, f0.n_bins, 0, full, interval=3)
+        with pytest.raises(dh.DisthistError):
+            t.histo(ctx, f0.offsets, f0.r_max, f0.n_bins, 0, str(tmp_path / "x"), interval=0)
