@@ -365,6 +365,24 @@ def bench_serving(n_jobs: int, seed: int = 5):
     return out
 
 
+def cpu_tuned(frame):
+    """The library's cache-blocked, vectorized CPU kernel (dh_cpu_histo) on
+    the whole bench frame, binary32 and binary64, the same host threads as
+    the oracle: context for the oracle baseline, not the target."""
+    import paper_1808_01478_amd as dh
+    # the library's default: the affinity mask, at most OMP_NUM_THREADS
+    threads = len(os.sched_getaffinity(0))
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit() and int(os.environ["OMP_NUM_THREADS"]) > 0:
+        threads = min(threads, int(os.environ["OMP_NUM_THREADS"]))
+    out = {"unit": "pairs/s", "cores": threads, "sample": "the whole frame, once per precision"}
+    for prec, name in ((dh.FP32, "fp32"), (dh.FP64, "fp64")):
+        t0 = time.perf_counter()
+        dh.cpu_histo(frame.coords, frame.offsets, frame.box_type, frame.box, frame.r_max,
+                     frame.n_bins, prec, 0)
+        out[name] = frame.total_pairs() / (time.perf_counter() - t0)
+    return out
+
+
 def cpu_baseline(frame, target_s: float = 12.0):
     """The oracle (plain FP64 double loop, OpenMP) on the first M points of
     every species of the same frame, M sized for about target_s seconds."""
@@ -512,6 +530,7 @@ def main():
         line["trajectory_file"] = bench_trajectory_file(ctx)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(frame)
+        line["cpu_tuned"] = cpu_tuned(frame)
     ctx.close()
     del torch
     print(json.dumps(line), flush=True)

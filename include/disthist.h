@@ -296,6 +296,22 @@ int32_t dh_sched_select(const int64_t *need_bytes, const double *waited_s, int32
                         int32_t *admit);
 
 /* ---------------------------------------------------------------------------
+ * Tuned CPU kernel (the paper's cache-blocked CPU kernel, Sec. 3.1: tiles
+ * sized for the L2, triangular tiles on the diagonal, coordinates as
+ * separate arrays for the vectorizer, bin indices of a row buffered then
+ * scattered into thread-private histograms). Host memory only, no device.
+ * Same arguments and outputs as dh_histo (out [H][n_bins] overwritten;
+ * out_of_range [H] optional, may be NULL); n_threads = 0 uses the CPUs of
+ * the process's affinity mask, at most OMP_NUM_THREADS when that is set. binary64 follows the canonical sequence (counts equal to
+ * the GPU path's); binary32 rounds coordinates and constants once and runs
+ * the same sequence in binary32. DH_EINVAL as dh_histo.
+ */
+int dh_cpu_histo(const double *coords, const int64_t *species_offsets, int32_t n_species,
+                 int32_t box_type, const double *box, double r_max, int32_t n_bins,
+                 int32_t precision, int32_t n_threads, uint64_t *out_u64,
+                 uint64_t *out_of_range);
+
+/* ---------------------------------------------------------------------------
  * Trajectory engine (the paper's frame-parallel engine reads frames, runs
  * them on its workers and sums the histograms over intervals of frames in
  * its writer, Sec. 3.3 and Sec. 4.4; this is its one-GPU form).

@@ -810,6 +810,11 @@ namespace dh {
 
 int ctx_device(const dh_ctx *ctx) { return ctx->device; }
 
+int frame_constants(int32_t box_type, const double *box, double r_max, int32_t n_bins,
+                    FrameParams &fp) {
+  return frame_consts(box_type, box, r_max, n_bins, fp);
+}
+
 int zero_u64(uint64_t *p, int64_t n, hipStream_t st) {
   return launch_zero(p, n, nullptr, st) == hipSuccess ? DH_OK : DH_EDEVICE;
 }

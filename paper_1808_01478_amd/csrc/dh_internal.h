@@ -131,6 +131,10 @@ size_t ctx_device_bytes(const dh_ctx *ctx);
 void ctx_release_scratch(dh_ctx *ctx);
 // device footprint of a single-frame job besides the caller's buffers
 size_t job_scratch_bytes(int64_t n_points, int32_t n_hist, int32_t n_bins, int32_t precision);
+// binary64 constants of a frame (s, inverse cell, shifts, box kind; returns
+// the kind: none, ortho, triclinic, triclinic with image search)
+int frame_constants(int32_t box_type, const double *box, double r_max, int32_t n_bins,
+                    FrameParams &fp);
 // device ordinal of a context
 int ctx_device(const dh_ctx *ctx);
 // zeroes n words with a kernel on stream st (never a memset node in graphs)

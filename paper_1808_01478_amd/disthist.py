@@ -46,6 +46,7 @@ SIGNATURES = {
     "dh_server_stats": ([_vp, _vp], ctypes.c_int),
     "dh_server_destroy": ([_vp], None),
     "dh_sched_select": ([_vp, _vp, _i32, _i64, _i32, _f64, _vp], ctypes.c_int32),
+    "dh_cpu_histo": ([_vp, _vp, _i32, _i32, _vp, _f64, _i32, _i32, _i32, _vp, _vp], ctypes.c_int),
     "dh_traj_open": ([ctypes.c_char_p, ctypes.POINTER(_vp)], ctypes.c_int),
     "dh_traj_info": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i32)],
                      ctypes.c_int),
@@ -154,6 +155,22 @@ def histo(coords, offsets, box_type: int, box, r_max: float, n_bins: int,
     _check(LIB.dh_histo(_np_ptr(c), _np_ptr(o), len(o) - 1, int(box_type), _np_ptr(b),
                         float(r_max), int(n_bins), int(precision), _np_ptr(out)))
     return out
+
+
+def cpu_histo(coords, offsets, box_type: int, box, r_max: float, n_bins: int,
+              precision: int = FP32, n_threads: int = 0):
+    """dh_cpu_histo: the tuned CPU kernel; returns (uint64 [H, n_bins],
+    out-of-range uint64 [H])."""
+    c = np.ascontiguousarray(coords, np.float64)
+    o = _offsets(offsets)
+    b = _host_box(box)
+    k = len(o) - 1
+    out = np.empty((n_hist(k), int(n_bins)), np.uint64)
+    oor = np.empty(n_hist(k), np.uint64)
+    _check(LIB.dh_cpu_histo(_np_ptr(c), _np_ptr(o), k, int(box_type), _np_ptr(b), float(r_max),
+                            int(n_bins), int(precision), int(n_threads), _np_ptr(out),
+                            _np_ptr(oor)))
+    return out, oor
 
 
 def _stream_handle(stream) -> Optional[int]:
