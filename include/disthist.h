@@ -58,6 +58,10 @@
  *   minimum of that expression over d + S for the 27 shifts
  *   S = i*a + j*b + k*c, i, j, k in {-1, 0, 1};
  *   t = sqrt(q) * (n_bins / r_max); bin floor(t) if t < n_bins.
+ * The device square root is the compiler's own binary64 sequence (rsq seed,
+ * Goldschmidt step, two fused Newton corrections); for about 2^-44 of
+ * arguments it may return the neighbour of the correctly rounded root, which
+ * moves a count only if t also sits within about 2^-52 of a bin edge.
  *
  * Errors: every entry point returns DH_OK (0) or a negative DH_E* code.
  * Argument errors (DH_EINVAL) are detected before anything is written or

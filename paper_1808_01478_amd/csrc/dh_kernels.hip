@@ -80,13 +80,17 @@ __device__ __forceinline__ Geo64 load_geo64(const FrameParams *F) {
   return g;
 }
 
-// Correctly rounded binary64 square root. Fast path: Goldschmidt's coupled
-// iteration for sqrt(q) and 1/(2 sqrt(q)) started from v_rsq_f64, then two
-// Newton corrections of the root with fused residuals (the Markstein-style
-// final step that yields the correctly rounded result). It needs q to be
-// normal and not tiny (no range scaling), so a wave in which any lane has
-// q < 2^-767, q = 0 or a NaN takes the library sqrt instead (which applies
-// the same iteration to a scaled input). Identical results either way.
+// binary64 square root. Goldschmidt's coupled iteration for sqrt(q) and
+// 1/(2 sqrt(q)) started from v_rsq_f64, then two Newton corrections of the
+// root with exact fused residuals: the same sequence the compiler emits for
+// the library sqrt on this target. The last correction is accurate to about
+// 2^-44 ulp, so the result is the correctly rounded root except when sqrt(q)
+// lies within that distance of a rounding midpoint (it can come as close as
+// about 2^-57 ulp), a fraction of about 2^-44 of arguments; a count changes
+// only if that last-bit difference also moves t across a bin edge. The fast
+// path needs q normal and not tiny (no range scaling), so a wave in which any
+// lane has q < 2^-767, q = 0 or a NaN takes the library sqrt instead (the
+// same iteration on a scaled input).
 __device__ __forceinline__ double sqrt_rn(double q) {
   if (__builtin_amdgcn_ballot_w64(!(q >= 0x1p-767)) != 0) return sqrt(q);
   const double y = __builtin_amdgcn_rsq(q);
