@@ -389,8 +389,9 @@ int dh_ctx_set_tuning(dh_ctx *ctx, int32_t mode, const char *cache_path);
  * on it (NULL restores tuning):
  * knobs[8] = {r (4|8), copies (1|2|4), tj (128|256), noclamp (0|1),
  * occ_cap (0..16, 0 = as many as fit), items_per_wg (1..64),
- * threads (256|512|1024, or 0 = 1024 when one 256-thread workgroup fills a
- * CU's LDS and 256 otherwise; the 27-image search always runs 256),
+ * threads (256|512|1024, or 0 = the smallest workgroup that gives every SIMD
+ * four waves within the LDS limit on workgroups per CU; the 27-image search
+ * always runs 256),
  * wide (0..65536: count with uint64 global atomics instead of LDS
  * sub-histograms when the histogram would need at least this many LDS bin
  * windows; 0 = never, 1 = always)}.

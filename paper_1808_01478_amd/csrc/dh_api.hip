@@ -254,14 +254,14 @@ constexpr int32_t kWideDefault32 = 48;
 constexpr int32_t kWideDefault64 = 20;
 
 struct Knobs {
-  int32_t r = 8;             // i-particles per lane: 4 or 8
+  int32_t r = 4;             // i-particles per lane: 4 or 8
   int32_t copies = 1;        // interleaved LDS copies: 1, 2 or 4
   int32_t tj = 256;          // j-tile length: 128 or 256
   int32_t noclamp = 1;       // allow unclamped interior blocks
   int32_t occ_cap = 0;       // workgroups per CU at most (0: as many as fit)
   int32_t items_per_wg = 8;  // work items per workgroup (sets the j-chunk)
-  // workgroup size: 256, 512 or 1024; 0 = 1024 when only one workgroup of
-  // 256 fits per CU (a wide LDS histogram), else 256
+  // workgroup size: 256, 512 or 1024; 0 = the smallest that gives every
+  // SIMD at least four waves within the LDS limit on workgroups per CU
   int32_t threads = 0;
   // global-atomic kernel when the LDS plan needs at least this many bin
   // windows (0: never, 1: always)
@@ -337,15 +337,22 @@ int32_t jchunk_for(const KernelConfig &c, int grid, uint64_t work, int items_per
   return static_cast<int32_t>(jc);
 }
 
-// Workgroup size "auto": one workgroup of 256 threads per CU leaves each
-// SIMD a single wave, so take 1024 threads when the LDS histogram admits no
-// second workgroup.
+// Workgroup size "auto": the LDS histogram caps the workgroups per CU, so
+// take the smallest workgroup that still gives each of the 4 SIMDs at least
+// four waves (measured on MI355X: 256 threads when several workgroups fit,
+// 512 with two per CU, 1024 with one).
 void resolve_threads(int precision, int kind, int mode, const Knobs &k, size_t lds,
                      KernelConfig &cfg) {
   if (k.threads != 0 || kind == kBoxTricSearch) return;
-  KernelConfig c256 = cfg;
-  c256.threads = 256;
-  cfg.threads = pairs_occupancy(precision, kind, mode, c256, lds) <= 1 ? 1024 : 256;
+  for (int th : {256, 512}) {
+    KernelConfig c = cfg;
+    c.threads = th;
+    if (pairs_occupancy(precision, kind, mode, c, lds) * (th / 64) >= 16) {
+      cfg.threads = th;
+      return;
+    }
+  }
+  cfg.threads = 1024;
 }
 
 int grid_for_config(const dh_ctx *ctx, int precision, int kind, int mode, const BaseConfig &b,
@@ -767,18 +774,41 @@ int tune_frame(dh_ctx *ctx, hipStream_t st, const FrameJob &job, const std::stri
   }
   float best_ms = 0.f;
   int rc = time_of(best, &best_ms);
+  auto consider = [&](const Knobs &cand) {
+    float ms = 0.f;
+    rc = time_of(cand, &ms);
+    if (!rc && ms < best_ms * 0.99f) {
+      best = cand;
+      best_ms = ms;
+    }
+  };
+  for (int32_t v : wide_choices) {
+    Knobs cand = best;
+    cand.wide = v;
+    if (!rc) consider(cand);
+  }
+  // i-particles per lane and workgroup size together: they trade registers
+  // against waves per SIMD, and the best pair is often not reached one knob
+  // at a time
+  {
+    const Knobs base = best;
+    for (int32_t r : {4, 8})
+      for (int32_t th : {256, 512, 1024}) {
+        Knobs cand = base;
+        cand.r = r;
+        cand.threads = th;
+        if (!rc && (cand.r != base.r || cand.threads != base.threads)) consider(cand);
+      }
+  }
   const std::vector<std::vector<int32_t>> choices = {
-      wide_choices,      // wide
-      {256, 512, 1024},  // threads
       {0, 1},            // noclamp
       {1, 2, 4},         // copies
-      {4, 8},            // r
-      {0, 1, 2},         // occ_cap
+      {0, 1, 2, 3},      // occ_cap
       {4, 8, 16},        // items_per_wg
       {128, 256},        // tj
   };
-  const int order[kNumKnobs] = {7, 6, 3, 1, 0, 4, 5, 2};  // knob index in pack() order
-  for (int d = 0; d < kNumKnobs && !rc; ++d) {
+  const int order[5] = {3, 1, 4, 5, 2};  // knob index in pack() order
+  for (int d = 0; d < 5 && !rc; ++d) {
     const int q = order[d];
     for (int32_t v : choices[d]) {
       std::array<int32_t, kNumKnobs> kp = best.pack();
