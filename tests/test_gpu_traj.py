@@ -106,3 +106,29 @@ def test_checkpoint_resume(ctx, tmp_path):
             t.histo(ctx, f0.offsets, f0.r_max * 0.5, f0.n_bins, 0, full, interval=3)
         with pytest.raises(dh.DisthistError):
             t.histo(ctx, f0.offsets, f0.r_max, f0.n_bins, 0, str(tmp_path / "x"), interval=0)
+
+
+def test_invalid_frame_stops_before_its_interval(ctx, tmp_path):
+    """A frame with a cell that is not reduced stops the run with DH_EINVAL;
+    the intervals before it stay recorded and a rerun stops at the same place."""
+    import paper_1808_01478_amd as dh
+    from paper_1808_01478_amd import trajfile
+    rng = np.random.Generator(np.random.PCG64(5))
+    n, offs = 800, np.array([0, 500, 800], np.int64)
+    good = np.array([[10.0, 0, 0], [2.0, 9.0, 0], [1.0, 2.0, 8.0]])
+    bad = np.array([[10.0, 0, 0], [7.0, 9.0, 0], [1.0, 2.0, 8.0]])   # |b_x| > a_x / 2
+    boxes = [good] * 5 + [bad] + [good] * 2
+    xs = [rng.uniform(0, 1, size=(n, 3)) @ good for _ in boxes]
+    p = str(tmp_path / "t.dhtraj")
+    trajfile.write_trajectory(p, xs, workloads.BOX_TRICLINIC, boxes)
+    res = str(tmp_path / "r.dhres")
+    with dh.Trajectory(p) as t:
+        for _ in range(2):
+            with pytest.raises(dh.DisthistError) as e:
+                t.histo(ctx, offs, 4.0, 100, 1, res, interval=2)
+            assert e.value.code == -1
+            _, hist, _, nfr = trajfile.read_results(res, 3)
+            assert list(nfr) == [2, 2]                # frames 0-3 recorded, 4-5 not
+    frames = [workloads.Frame(np.ascontiguousarray(x), offs, 2, good, 4.0, 100, "f") for x in xs[:4]]
+    want = sum(oracle.frame_histogram(f).hist for f in frames[:2])
+    assert np.array_equal(hist[0], want)
