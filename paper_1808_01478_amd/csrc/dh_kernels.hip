@@ -897,12 +897,19 @@ hipError_t launch_zero(uint64_t *out, int64_t n_words, int32_t *counter, hipStre
   return hipGetLastError();
 }
 
+// Allows a pair kernel the whole LDS of a CU. Every caller sets the same
+// value, so contexts launching from several host threads cannot lower the
+// limit between another thread's check and launch.
+static void allow_full_lds(PairFn fn) {
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  (void)hipGetLastError();
+}
+
 hipError_t launch_pairs(int precision, int box_kind, int mode, const KernelConfig &cfg,
                         const PairKernelArgs &args, int grid, size_t lds_bytes, hipStream_t st) {
   PairFn fn = pick(precision, cfg.r, box_kind, mode);
-  hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
-                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes));
-  (void)hipGetLastError();
+  allow_full_lds(fn);
   hipLaunchKernelGGL(fn, dim3(grid), dim3(cfg.threads), lds_bytes, st, args);
   return hipGetLastError();
 }
@@ -910,9 +917,7 @@ hipError_t launch_pairs(int precision, int box_kind, int mode, const KernelConfi
 int pairs_occupancy(int precision, int box_kind, int mode, const KernelConfig &cfg,
                     size_t lds_bytes) {
   PairFn fn = pick(precision, cfg.r, box_kind, mode);
-  hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
-                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes));
-  (void)hipGetLastError();
+  allow_full_lds(fn);
   int blocks = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, cfg.threads, lds_bytes) !=
       hipSuccess) {
