@@ -315,7 +315,9 @@ BaseConfig base_config(const dh_ctx *ctx, int precision, const Knobs &k, int kin
   c.tj = k.tj;
   c.wg_per_cu = k.occ_cap;
   c.jchunk = c.tj;
-  b.tile_bytes = 2 * static_cast<size_t>(c.tj) * coord_bytes(precision);
+  // two j-tiles, plus one entry of pad: the look-ahead read of j may touch
+  // the entry just past the second tile
+  b.tile_bytes = (2 * static_cast<size_t>(c.tj) + 1) * coord_bytes(precision);
   // the search kernels keep their queues after the histogram; counting them
   // with the tiles leaves the histogram budget below them
   if (kind == kBoxTricSearch) b.tile_bytes += search_queue_bytes(precision, c.threads, c.r);

@@ -689,16 +689,32 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
         // one copy of the search code: a plain j loop
         for (int jj = js; jj < jcount; ++jj) pairs_of(load_j(jj), jt + jj);
       } else {
-        J pa = load_j(js);
+        // j is read through a pointer kept in a VGPR, so the two reads of an
+        // iteration use immediate offsets and one add moves it on (a uniform
+        // SGPR address would cost a v_mov per read). The zero is opaque to
+        // the compiler on purpose.
+        int vzero;
+        asm volatile("v_mov_b32 %0, 0" : "=v"(vzero));
+        const V *cur = tb + js + vzero;
+        auto load_at = [&](const V *q) -> J {
+          if constexpr (kPacked)
+            return JPacked{*reinterpret_cast<const uint64_t *>(q),
+                           reinterpret_cast<const float *>(q)[2]};
+          else
+            return *q;
+        };
+        J pa = load_at(cur);
         __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
         int jj = js;
-        for (; jj + 1 < jcount; jj += 2) {
-          const J pb = load_j(jj + 1);
+        for (; jj + 1 < jcount; jj += 2, cur += 2) {
+          const J pb = load_at(cur + 1);
           // binary32: pin the read ahead of the atomics (measured faster);
           // binary64 has enough arithmetic per j to hide it unpinned
           if constexpr (sizeof(T) == 4) __builtin_amdgcn_sched_barrier(0);
           pairs_of(pa, jt + jj);
-          pa = load_j(min(jj + 2, jcount - 1));
+          // at the end of a tile this reads the entry just past it (the
+          // next buffer, the histogram or the allocation's pad): never used
+          pa = load_at(cur + 2);
           if constexpr (sizeof(T) == 4) __builtin_amdgcn_sched_barrier(0);
           pairs_of(pb, jt + jj + 1);
         }
