@@ -232,16 +232,19 @@ void dh_batch_destroy(dh_batch *batch);
 
 /* ---------------------------------------------------------------------------
  * Serving: a request loop that runs histogram jobs of mixed sizes, boxes and
- * bin counts concurrently on one GPU (continuous batching). A scheduler
- * thread admits queued jobs while a slot (a context with its own stream) is
- * free and the job's device footprint fits the HBM budget, in arrival order
- * with backfill: a later job that fits may start while an earlier one waits
- * for memory, unless the earliest job has waited longer than the head-wait
- * limit, which then reserves the memory it needs. Admitted jobs keep their
- * frame resident on the device, run on their slot's stream and overlap with
- * the other running jobs; completion is detected with events. The paper's
- * counterpart is its producer/consumer engine that feeds frames to GPU
- * workers through queues (Sec. 3.3).
+ * bin counts on one GPU (continuous batching). A scheduler thread admits
+ * queued jobs while a slot (a context with its own stream) is free and the
+ * job's device footprint fits the HBM budget (see dh_sched_select for the
+ * order), copies the admitted job's frame to the device and stages it. The
+ * job's pair kernel is cut into launches of a bounded pair count, and the
+ * same thread paces them onto the device: one launch runs while the next
+ * waits behind it, and each launch comes from the admitted job with the
+ * least work left (shortest remaining work first), so a small job that
+ * arrives while a huge one runs is computed at the huge job's next launch
+ * boundary instead of after it. DH_SCHED_ARRIVAL selects arrival order for
+ * both admission and launches instead. Completion is detected with events.
+ * The paper's counterpart is its producer/consumer engine that feeds frames
+ * to GPU workers through queues (Sec. 3.3).
  */
 typedef struct dh_server dh_server;
 
@@ -265,6 +268,14 @@ int dh_server_create(int32_t device, int64_t hbm_budget_bytes, int32_t max_infli
 int dh_server_submit(dh_server *server, const double *coords, const int64_t *offsets,
                      int32_t n_species, int32_t box_type, const double *box, double r_max,
                      int32_t n_bins, int32_t precision, int64_t *job_id);
+
+#define DH_SCHED_SHORTEST 0 /* least work first (the default) */
+#define DH_SCHED_ARRIVAL 1  /* arrival order */
+
+/* Sets the order in which queued jobs are admitted and admitted jobs'
+ * launches are issued; takes effect at the next scheduling step. DH_EINVAL
+ * for another value. */
+int dh_server_set_policy(dh_server *server, int32_t policy);
 
 /* DH_JOB_QUEUED, DH_JOB_RUNNING, DH_JOB_DONE, or the job's negative error;
  * DH_EINVAL for an unknown id. */
@@ -291,13 +302,19 @@ void dh_server_destroy(dh_server *server);
 
 /*
  * The admission policy of the server as a pure host function (no device):
- * given the queued jobs in arrival order (footprints and seconds waited),
- * the free budget and the free slots, writes the queue positions to start
- * now into admit[] (ascending) and returns how many.
+ * given the queued jobs in arrival order (footprints, seconds waited and,
+ * optionally, their work in pairs), the free budget and the free slots,
+ * writes the queue positions to start now into admit[] (ascending) and
+ * returns how many. Jobs that have waited at least head_wait_limit_s come
+ * first, oldest first, and one of them that does not fit stops all
+ * admissions (the memory running jobs free goes to it). The others follow
+ * in order of increasing work (arrival order when work is NULL), each if it
+ * fits: small jobs do not queue behind large ones, and the wait limit
+ * bounds how long a large one can be passed over.
  */
-int32_t dh_sched_select(const int64_t *need_bytes, const double *waited_s, int32_t n_queued,
-                        int64_t free_bytes, int32_t free_slots, double head_wait_limit_s,
-                        int32_t *admit);
+int32_t dh_sched_select(const int64_t *need_bytes, const double *waited_s, const double *work,
+                        int32_t n_queued, int64_t free_bytes, int32_t free_slots,
+                        double head_wait_limit_s, int32_t *admit);
 
 /* ---------------------------------------------------------------------------
  * Tuned CPU kernel (the paper's cache-blocked CPU kernel, Sec. 3.1: tiles

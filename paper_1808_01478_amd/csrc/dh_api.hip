@@ -48,6 +48,24 @@ struct dh_ctx {
   std::array<int32_t, 13> last_config{};
   // pairs per pair-kernel launch at most (0: one launch per frame)
   uint64_t launch_pairs = 0;
+  // stepped job: pair-kernel launches held back for dh::step_job, then the
+  // closing out-of-range pass
+  struct HeldLaunch {
+    int precision, kind, mode;
+    KernelConfig cfg;
+    PairKernelArgs args;
+    int grid;
+    size_t lds;
+    uint64_t pairs;
+  };
+  bool hold = false;
+  std::vector<HeldLaunch> held;
+  size_t held_next = 0;
+  uint64_t held_left = 0;
+  bool held_oor = false;
+  uint64_t *oor_hist = nullptr, *oor_out = nullptr;
+  int32_t oor_n_hist = 0, oor_n_bins = 0;
+  const uint64_t *oor_pairs = nullptr;
   // kernel timing: event pairs recorded around pair-kernel launches
   bool profile = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
@@ -630,6 +648,11 @@ int run_frame(dh_ctx *ctx, hipStream_t st, const FrameJob &job, const Knobs &k, 
     DH_HIP(ctx, launch_zero(job.d_out, static_cast<int64_t>(n_hist) * fp.n_bins,
                             reinterpret_cast<int32_t *>(db + lay.counter), st));
   const int grid = std::max(1, std::min<int>(L.grid, static_cast<int>(items.size())));
+  if (ctx->hold) {
+    ctx->held.clear();
+    ctx->held_next = 0;
+    ctx->held_left = 0;
+  }
   if (e0) DH_HIP(ctx, hipEventRecord(e0, st));
   for (size_t c = 0; c < n_launches && !items.empty(); ++c) {
     // every launch has its own work counter (zeroed with the blob upload)
@@ -642,12 +665,29 @@ int run_frame(dh_ctx *ctx, hipStream_t st, const FrameJob &job, const Knobs &k, 
     a.stride = L.stride;
     a.tj = L.cfg.tj;
     const int g = std::max(1, std::min(grid, a.n_items));
+    if (ctx->hold) {
+      uint64_t p = 0;
+      for (size_t q = cuts[c]; q < cuts[c + 1]; ++q)
+        p += static_cast<uint64_t>(items[q].i1 - items[q].i0) *
+             static_cast<uint64_t>(items[q].j1 - items[q].j0);
+      ctx->held.push_back({job.precision, job.kind, L.mode, L.cfg, a, g, L.lds, p});
+      ctx->held_left += p;
+      continue;
+    }
     DH_HIP(ctx, launch_pairs(job.precision, job.kind, L.mode, L.cfg, a, g, L.lds, st));
   }
   if (e1) DH_HIP(ctx, hipEventRecord(e1, st));
-  if (job.d_oor)
+  if (ctx->hold) {
+    ctx->held_oor = job.d_oor != nullptr;
+    ctx->oor_hist = job.d_out;
+    ctx->oor_n_hist = n_hist;
+    ctx->oor_n_bins = fp.n_bins;
+    ctx->oor_pairs = reinterpret_cast<const uint64_t *>(db + lay.pairs);
+    ctx->oor_out = job.d_oor;
+  } else if (job.d_oor) {
     DH_HIP(ctx, launch_oor(job.d_out, n_hist, fp.n_bins,
                            reinterpret_cast<const uint64_t *>(db + lay.pairs), job.d_oor, st));
+  }
   const std::array<int32_t, kNumKnobs> kp = k.pack();
   for (int q = 0; q < kNumKnobs; ++q) ctx->last_config[q] = kp[q];
   ctx->last_config[6] = L.cfg.threads;  // the workgroup size actually launched
@@ -987,7 +1027,7 @@ namespace dh {
 int histo_job(dh_ctx *ctx, hipStream_t stream, const double *d_coords, const int64_t *offsets,
               int32_t n_species, int32_t box_type, const double *box, double r_max,
               int32_t n_bins, int32_t precision, uint64_t *d_out, uint64_t *d_out_of_range,
-              bool accumulate, uint64_t *total_pairs) {
+              bool accumulate, uint64_t *total_pairs, bool stepped) {
   if (!ctx) return DH_EINVAL;
   int rc = check(nullptr, offsets, n_species, box_type, box, r_max, n_bins, precision);
   if (rc) return fail(ctx, rc, "invalid arguments");
@@ -1026,8 +1066,9 @@ int histo_job(dh_ctx *ctx, hipStream_t stream, const double *d_coords, const int
     auto it = ctx->tune_cache.find(key);
     if (it != ctx->tune_cache.end()) {
       k = Knobs::unpack(it->second);
-    } else if (ctx->tune_mode == DH_TUNE_ON && job.total > 0 && !accumulate) {
-      // (tuning overwrites the output, so accumulating calls never tune)
+    } else if (ctx->tune_mode == DH_TUNE_ON && job.total > 0 && !accumulate && !stepped) {
+      // (tuning overwrites the output, so accumulating calls never tune;
+      // nor do stepped jobs, whose launches someone else paces)
       rc = tune_frame(ctx, st, job, key, k);
       if (rc) return rc;
     }
@@ -1035,6 +1076,13 @@ int histo_job(dh_ctx *ctx, hipStream_t stream, const double *d_coords, const int
   if (total_pairs) *total_pairs = job.total;
 
   hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (stepped) {
+    ctx->hold = true;
+    rc = run_frame(ctx, st, job, k, true, nullptr, nullptr);
+    ctx->hold = false;
+    if (rc) ctx->held.clear();
+    return rc;
+  }
   if (ctx->profile) {
     if (ctx->prof_used == ctx->prof_events.size()) {
       hipEvent_t x, y;
@@ -1047,6 +1095,29 @@ int histo_job(dh_ctx *ctx, hipStream_t stream, const double *d_coords, const int
     ++ctx->prof_used;
   }
   return run_frame(ctx, st, job, k, true, e0, e1);
+}
+
+int step_job(dh_ctx *ctx, hipStream_t st, uint64_t *pairs_left, bool *done) {
+  *done = false;
+  if (ctx->held_next < ctx->held.size()) {
+    const dh_ctx::HeldLaunch &h = ctx->held[ctx->held_next++];
+    ctx->held_left -= h.pairs;
+    DH_HIP(ctx, launch_pairs(h.precision, h.kind, h.mode, h.cfg, h.args, h.grid, h.lds, st));
+  } else {
+    if (ctx->held_oor)
+      DH_HIP(ctx, launch_oor(ctx->oor_hist, ctx->oor_n_hist, ctx->oor_n_bins, ctx->oor_pairs,
+                             ctx->oor_out, st));
+    ctx->held.clear();
+    ctx->held_next = 0;
+    ctx->held_oor = false;
+    *done = true;
+  }
+  *pairs_left = ctx->held_left;
+  return DH_OK;
+}
+
+uint64_t stepped_next_pairs(const dh_ctx *ctx) {
+  return ctx->held_next < ctx->held.size() ? ctx->held[ctx->held_next].pairs : 0;
 }
 
 }  // namespace dh

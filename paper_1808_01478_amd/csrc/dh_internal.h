@@ -145,5 +145,14 @@ int zero_u64(uint64_t *p, int64_t n, hipStream_t st);
 int histo_job(dh_ctx *ctx, hipStream_t stream, const double *d_coords, const int64_t *offsets,
               int32_t n_species, int32_t box_type, const double *box, double r_max,
               int32_t n_bins, int32_t precision, uint64_t *d_out, uint64_t *d_out_of_range,
-              bool accumulate, uint64_t *total_pairs);
+              bool accumulate, uint64_t *total_pairs, bool stepped = false);
+// A stepped job (histo_job with stepped set) enqueues staging and zeroing
+// only and holds its pair-kernel launches back in the context; step_job
+// enqueues the next one on st, or, when none is left, the closing
+// out-of-range pass (*done then becomes true). *pairs_left receives the
+// pairs of the launches still held back. The context runs nothing else
+// until the job is done.
+int step_job(dh_ctx *ctx, hipStream_t st, uint64_t *pairs_left, bool *done);
+// pairs of a stepped job's next held-back launch (0: the closing pass is next)
+uint64_t stepped_next_pairs(const dh_ctx *ctx);
 }  // namespace dh

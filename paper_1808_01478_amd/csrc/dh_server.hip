@@ -1,6 +1,8 @@
 // Serving loop of libdisthist: a scheduler thread that admits histogram jobs
-// by free slots and HBM budget and runs them concurrently, one stream per
-// slot, so jobs that arrive while others run overlap on the device.
+// by free slots and HBM budget (one stream per slot) and paces their
+// pair-kernel launches onto the device, each from the admitted job with the
+// least work left, so a job that arrives while a huge one runs is computed
+// at the huge job's next launch boundary.
 #include "disthist.h"
 #include "dh_internal.h"
 
@@ -24,6 +26,10 @@ using Clock = std::chrono::steady_clock;
 // pairs per pair-kernel launch of a served job (about 10 ms of binary32
 // orthorhombic work on MI355X)
 constexpr int64_t kServeLaunchPairs = int64_t{3} << 33;
+// pair-kernel work on the device at once (at least one launch): one launch
+// running and the next queued behind it, so the device never idles between
+// launches while a newly admitted job waits for at most these
+constexpr uint64_t kInflightPairs = 2 * static_cast<uint64_t>(kServeLaunchPairs);
 
 double seconds_since(Clock::time_point t0, Clock::time_point t1) {
   return std::chrono::duration<double>(t1 - t0).count();
@@ -42,6 +48,7 @@ struct Job {
   int32_t n_hist = 0;
   int64_t n = 0;
   int64_t need = 0;  // device footprint while running
+  double work = 0;   // pairs, the order of admission and of launches
   int status = DH_JOB_QUEUED;
   int slot = -1;
   Clock::time_point t_submit, t_admit, t_done;
@@ -65,6 +72,16 @@ struct Slot {
   uint64_t *h_oor = nullptr;
   size_t h_oor_cap = 0;
   Job *job = nullptr;
+  // scheduler thread only: the job's launches are still being paced
+  // (stepping), or its closing copies and `done` are enqueued (closing)
+  bool stepping = false, closing = false;
+  uint64_t left = 0;  // pairs of the launches not issued yet
+};
+
+// a pair-kernel launch on the device and the event recorded after it
+struct InFlight {
+  hipEvent_t ev;
+  uint64_t pairs;
 };
 
 int grow_device(void **p, size_t *cap, size_t need) {
@@ -103,7 +120,12 @@ struct dh_server {
   int32_t device = 0;
   int64_t budget = 0;
   double head_wait_limit = 1.0;
+  std::atomic<int32_t> policy{DH_SCHED_SHORTEST};
   std::vector<Slot> slots;
+  // scheduler thread only
+  std::deque<InFlight> inflight;
+  uint64_t inflight_pairs = 0;
+  std::vector<hipEvent_t> event_pool;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<Job *> queue;
@@ -118,21 +140,41 @@ struct dh_server {
 };
 
 extern "C" int32_t dh_sched_select(const int64_t *need_bytes, const double *waited_s,
-                                   int32_t n_queued, int64_t free_bytes, int32_t free_slots,
-                                   double head_wait_limit_s, int32_t *admit) {
+                                   const double *work, int32_t n_queued, int64_t free_bytes,
+                                   int32_t free_slots, double head_wait_limit_s,
+                                   int32_t *admit) {
   if (!need_bytes || !waited_s || !admit || n_queued <= 0 || free_slots <= 0) return 0;
   int32_t n = 0;
-  for (int32_t q = 0; q < n_queued && free_slots > 0; ++q) {
-    if (need_bytes[q] <= free_bytes) {
-      admit[n++] = q;
-      free_bytes -= need_bytes[q];
-      --free_slots;
-    } else if (n == 0 && q == 0 && waited_s[0] >= head_wait_limit_s) {
-      // the oldest job has waited too long: stop backfilling, so the memory
-      // that running jobs free up goes to it
-      break;
+  auto take = [&](int32_t q) {
+    admit[n++] = q;
+    free_bytes -= need_bytes[q];
+    --free_slots;
+  };
+  // jobs past the wait limit first, oldest first: one that does not fit
+  // stops all admissions, so the memory that running jobs free goes to it
+  std::vector<int32_t> rest;
+  for (int32_t q = 0; q < n_queued; ++q) {
+    if (waited_s[q] >= head_wait_limit_s) {
+      if (free_slots == 0) break;
+      if (need_bytes[q] > free_bytes) {
+        std::sort(admit, admit + n);
+        return n;
+      }
+      take(q);
+    } else {
+      rest.push_back(q);
     }
   }
+  // then the others, least work first (arrival order without work), each
+  // if it fits (backfill)
+  if (work)
+    std::stable_sort(rest.begin(), rest.end(),
+                     [&](int32_t x, int32_t y) { return work[x] < work[y]; });
+  for (int32_t q : rest) {
+    if (free_slots == 0) break;
+    if (need_bytes[q] <= free_bytes) take(q);
+  }
+  std::sort(admit, admit + n);
   return n;
 }
 
@@ -157,16 +199,30 @@ int start_job(dh_server *s, Slot &sl, Job &j) {
                        hipMemcpyHostToDevice, sl.stream) != hipSuccess)
       return DH_EDEVICE;
   }
-  rc = dh_histo_async(sl.ctx, sl.stream, sl.d_in, j.offsets.data(),
-                      static_cast<int32_t>(j.offsets.size() - 1), j.box_type,
-                      j.has_box ? j.box : nullptr, j.r_max, j.n_bins, j.precision, sl.d_out,
-                      sl.d_oor);
+  // staging and zeroing now; the pair-kernel launches wait for dispatch()
+  rc = dh::histo_job(sl.ctx, sl.stream, sl.d_in, j.offsets.data(),
+                     static_cast<int32_t>(j.offsets.size() - 1), j.box_type,
+                     j.has_box ? j.box : nullptr, j.r_max, j.n_bins, j.precision, sl.d_out,
+                     sl.d_oor, false, nullptr, true);
   if (rc) return rc;
+  sl.stepping = true;
+  sl.closing = false;
+  sl.left = static_cast<uint64_t>(j.work);
+  (void)s;
+  return DH_OK;
+}
+
+// Enqueues the copies of a job's results and its completion event.
+int close_job(Slot &sl) {
+  const Job &j = *sl.job;
+  const size_t out_b = static_cast<size_t>(j.n_hist) * j.n_bins * sizeof(uint64_t);
+  const size_t oor_b = static_cast<size_t>(j.n_hist) * sizeof(uint64_t);
   if (hipMemcpyAsync(sl.h_out, sl.d_out, out_b, hipMemcpyDeviceToHost, sl.stream) != hipSuccess ||
       hipMemcpyAsync(sl.h_oor, sl.d_oor, oor_b, hipMemcpyDeviceToHost, sl.stream) != hipSuccess ||
       hipEventRecord(sl.done, sl.stream) != hipSuccess)
     return DH_EDEVICE;
-  (void)s;
+  sl.stepping = false;
+  sl.closing = true;
   return DH_OK;
 }
 
@@ -186,12 +242,75 @@ void finish_job(dh_server *s, Slot &sl, Job &j, int status) {
   s->used -= j.need;
   --s->running;
   sl.job = nullptr;
+  sl.stepping = sl.closing = false;
+  sl.left = 0;
+}
+
+// true when slot a's job goes before slot b's: least work left first
+// (shortest remaining work), or the earliest submitted under arrival order
+bool goes_first(const dh_server *s, const Slot &a, const Slot &b) {
+  if (s->policy == DH_SCHED_SHORTEST && a.left != b.left) return a.left < b.left;
+  return a.job->id < b.job->id;
+}
+
+// Retires finished launches, then issues held launches while the pairs on
+// the device stay within kInflightPairs (one launch at least), each from the
+// job that goes first; a job with none left gets its closing pass, copies
+// and completion event. Scheduler thread, outside the lock.
+void dispatch(dh_server *s) {
+  for (auto it = s->inflight.begin(); it != s->inflight.end();) {
+    const hipError_t e = hipEventQuery(it->ev);
+    if (e == hipErrorNotReady) {
+      ++it;
+      continue;
+    }
+    if (e != hipSuccess) (void)hipGetLastError();  // the job's `done` reports it
+    s->inflight_pairs -= it->pairs;
+    s->event_pool.push_back(it->ev);
+    it = s->inflight.erase(it);
+  }
+  while (true) {
+    Slot *best = nullptr;
+    for (Slot &sl : s->slots)
+      if (sl.stepping && (!best || goes_first(s, sl, *best))) best = &sl;
+    if (!best) return;
+    const uint64_t next = dh::stepped_next_pairs(best->ctx);
+    if (next > 0 && !s->inflight.empty() && s->inflight_pairs + next > kInflightPairs) return;
+    uint64_t left = 0;
+    bool done = false;
+    int rc = dh::step_job(best->ctx, best->stream, &left, &done);
+    best->left = left;
+    if (!rc && !done) {
+      hipEvent_t ev = nullptr;
+      if (!s->event_pool.empty()) {
+        ev = s->event_pool.back();
+        s->event_pool.pop_back();
+      } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        ev = nullptr;
+      }
+      if (ev && hipEventRecord(ev, best->stream) == hipSuccess) {
+        s->inflight.push_back({ev, next});
+        s->inflight_pairs += next;
+      } else {
+        if (ev) s->event_pool.push_back(ev);
+        rc = DH_EDEVICE;
+      }
+    }
+    if (!rc && done) rc = close_job(*best);
+    if (rc) {
+      (void)hipStreamSynchronize(best->stream);
+      (void)hipGetLastError();
+      std::lock_guard<std::mutex> lk(s->mu);
+      finish_job(s, *best, *best->job, rc);
+      s->cv_done.notify_all();
+    }
+  }
 }
 
 void scheduler(dh_server *s) {
   if (hipSetDevice(s->device) != hipSuccess) (void)hipGetLastError();
   std::vector<int64_t> need;
-  std::vector<double> waited;
+  std::vector<double> waited, work;
   std::vector<int32_t> admit;
   while (true) {
     std::vector<std::pair<Slot *, Job *>> to_start;
@@ -200,7 +319,7 @@ void scheduler(dh_server *s) {
       // completions
       bool any_done = false;
       for (Slot &sl : s->slots) {
-        if (!sl.job) continue;
+        if (!sl.job || !sl.closing) continue;
         const hipError_t e = hipEventQuery(sl.done);
         if (e == hipErrorNotReady) continue;
         finish_job(s, sl, *sl.job, e == hipSuccess ? DH_OK : DH_EDEVICE);
@@ -216,12 +335,15 @@ void scheduler(dh_server *s) {
         const Clock::time_point now = Clock::now();
         need.clear();
         waited.clear();
+        work.clear();
         for (Job *j : s->queue) {
           need.push_back(j->need);
           waited.push_back(seconds_since(j->t_submit, now));
+          work.push_back(j->work);
         }
         admit.assign(s->queue.size(), 0);
         const int32_t n = dh_sched_select(need.data(), waited.data(),
+                                          s->policy == DH_SCHED_SHORTEST ? work.data() : nullptr,
                                           static_cast<int32_t>(need.size()), s->budget - s->used,
                                           free_slots, s->head_wait_limit, admit.data());
         std::vector<Job *> chosen;
@@ -262,6 +384,7 @@ void scheduler(dh_server *s) {
         s->cv_done.notify_all();
       }
     }
+    dispatch(s);
     if (to_start.empty()) std::this_thread::sleep_for(std::chrono::microseconds(20));
   }
 }
@@ -324,6 +447,7 @@ int dh_server_submit(dh_server *s, const double *coords, const int64_t *offsets,
   auto j = std::make_unique<Job>();
   j->n = n;
   j->n_hist = n_species * (n_species + 1) / 2;
+  j->work = 0.5 * static_cast<double>(n) * static_cast<double>(n > 0 ? n - 1 : 0);
   j->need = static_cast<int64_t>(std::max<int64_t>(1, n) * 3 * sizeof(double) +
                                  static_cast<size_t>(j->n_hist) * n_bins * sizeof(uint64_t) +
                                  dh::job_scratch_bytes(n, j->n_hist, n_bins, precision));
@@ -346,6 +470,13 @@ int dh_server_submit(dh_server *s, const double *coords, const int64_t *offsets,
     ++s->n_submitted;
   }
   s->cv_work.notify_all();
+  return DH_OK;
+}
+
+int dh_server_set_policy(dh_server *s, int32_t policy) {
+  if (!s || (policy != DH_SCHED_SHORTEST && policy != DH_SCHED_ARRIVAL)) return DH_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->policy = policy;
   return DH_OK;
 }
 
@@ -405,6 +536,8 @@ void dh_server_destroy(dh_server *s) {
   if (s->worker.joinable()) s->worker.join();
   if (hipSetDevice(s->device) == hipSuccess) (void)hipDeviceSynchronize();
   for (Slot &sl : s->slots) release_slot(sl);
+  for (const InFlight &f : s->inflight) (void)hipEventDestroy(f.ev);
+  for (hipEvent_t ev : s->event_pool) (void)hipEventDestroy(ev);
   (void)hipGetLastError();
   delete s;
 }

@@ -42,10 +42,11 @@ SIGNATURES = {
     "dh_server_submit": ([_vp, _vp, _vp, _i32, _i32, _vp, _f64, _i32, _i32, ctypes.POINTER(_i64)],
                          ctypes.c_int),
     "dh_server_status": ([_vp, _i64], ctypes.c_int),
+    "dh_server_set_policy": ([_vp, _i32], ctypes.c_int),
     "dh_server_wait": ([_vp, _i64, _vp, _vp, _vp], ctypes.c_int),
     "dh_server_stats": ([_vp, _vp], ctypes.c_int),
     "dh_server_destroy": ([_vp], None),
-    "dh_sched_select": ([_vp, _vp, _i32, _i64, _i32, _f64, _vp], ctypes.c_int32),
+    "dh_sched_select": ([_vp, _vp, _vp, _i32, _i64, _i32, _f64, _vp], ctypes.c_int32),
     "dh_cpu_histo": ([_vp, _vp, _i32, _i32, _vp, _f64, _i32, _i32, _i32, _vp, _vp], ctypes.c_int),
     "dh_traj_open": ([ctypes.c_char_p, ctypes.POINTER(_vp)], ctypes.c_int),
     "dh_traj_info": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i32)],
@@ -335,16 +336,19 @@ class Batch:
 
 
 JOB_DONE, JOB_QUEUED, JOB_RUNNING = 0, 1, 2
+SCHED_SHORTEST, SCHED_ARRIVAL = 0, 1
 
 
 def sched_select(need_bytes, waited_s, free_bytes: int, free_slots: int,
-                 head_wait_limit_s: float):
+                 head_wait_limit_s: float, work=None):
     """dh_sched_select: queue positions the server would start now."""
     need = np.ascontiguousarray(np.asarray(need_bytes, np.int64))
     wait = np.ascontiguousarray(np.asarray(waited_s, np.float64))
+    wk = None if work is None else np.ascontiguousarray(np.asarray(work, np.float64))
     out = np.zeros(max(1, len(need)), np.int32)
-    n = LIB.dh_sched_select(_np_ptr(need), _np_ptr(wait), len(need), int(free_bytes),
-                            int(free_slots), float(head_wait_limit_s), _np_ptr(out))
+    n = LIB.dh_sched_select(_np_ptr(need), _np_ptr(wait), _np_ptr(wk), len(need),
+                            int(free_bytes), int(free_slots), float(head_wait_limit_s),
+                            _np_ptr(out))
     return [int(v) for v in out[:n]]
 
 
@@ -352,12 +356,18 @@ class Server:
     """dh_server: continuous-batching request loop on one GPU."""
 
     def __init__(self, device: int = 0, hbm_budget_bytes: int = 8 << 30, max_inflight: int = 4,
-                 head_wait_limit_s: float = 1.0):
+                 head_wait_limit_s: float = 1.0, policy: int = None):
         h = ctypes.c_void_p()
         _check(LIB.dh_server_create(int(device), int(hbm_budget_bytes), int(max_inflight),
                                     float(head_wait_limit_s), ctypes.byref(h)))
         self.handle = h
         self._shapes = {}
+        if policy is not None:
+            self.set_policy(policy)
+
+    def set_policy(self, policy: int):
+        """SCHED_SHORTEST (least work first, the default) or SCHED_ARRIVAL."""
+        _check(LIB.dh_server_set_policy(self.handle, int(policy)))
 
     def submit(self, coords, offsets, box_type: int, box, r_max: float, n_bins: int,
                precision: int = FP32) -> int:

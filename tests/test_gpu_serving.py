@@ -140,3 +140,42 @@ def test_small_job_overtakes_huge_job():
     print(f"\nsmall job {t_small[2] * 1e3:.1f} ms, huge job {t_big[2] * 1e3:.1f} ms", flush=True)
     assert still_running, "the small job waited for the whole huge job"
     assert t_small[2] < 0.25 * t_big[2]
+
+
+@pytest.mark.parametrize("policy", ["shortest", "arrival"])
+def test_launch_order_policy(policy):
+    """Two slots, a huge job running and a small one submitted behind it:
+    least-work-first computes the small job at the huge job's next launch
+    boundary; arrival order runs the huge job's launches first, so the small
+    job finishes after it. Results are the same either way."""
+    import paper_1808_01478_amd as dh
+    huge = workloads.random_frame(621, [1_200_000], workloads.BOX_NONE, n_bins=1000)
+    small = workloads.random_frame(622, [2000, 1000], workloads.BOX_ORTHO, n_bins=1000)
+    pol = dh.SCHED_SHORTEST if policy == "shortest" else dh.SCHED_ARRIVAL
+    print(f"\n[case] policy {policy}", flush=True)
+    with dh.Server(0, hbm_budget_bytes=8 << 30, max_inflight=2, policy=pol) as srv:
+        with pytest.raises(dh.DisthistError):
+            srv.set_policy(7)
+        srv.wait(srv.submit(small.coords, small.offsets, small.box_type, small.box, small.r_max,
+                            small.n_bins, 0))
+        t0 = time.perf_counter()
+        big = srv.submit(huge.coords, huge.offsets, huge.box_type, huge.box, huge.r_max,
+                         huge.n_bins, 0)
+        while srv.status(big) == dh.JOB_QUEUED and time.perf_counter() - t0 < 5.0:
+            time.sleep(0.001)
+        time.sleep(0.02)
+        t_sub = time.perf_counter() - t0
+        sid = srv.submit(small.coords, small.offsets, small.box_type, small.box, small.r_max,
+                         small.n_bins, 0)
+        h, _, t_small = srv.wait(sid)
+        hb, _, t_big = srv.wait(big)
+    assert np.array_equal(h, alone(small, 0))
+    assert np.array_equal(hb, alone(huge, 0))
+    end_small, end_big = t_sub + t_small[2], t_big[2]
+    print(f"small job ends at {end_small * 1e3:.1f} ms, huge job at {end_big * 1e3:.1f} ms",
+          flush=True)
+    if policy == "shortest":
+        assert end_small < 0.5 * end_big
+    else:
+        # (the small kernel may run beside the huge job's last launch)
+        assert end_small >= 0.8 * end_big

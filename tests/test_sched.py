@@ -15,9 +15,10 @@ def dh():
     return dh
 
 
-def simulate(dh, arrivals, need, work, budget, slots, limit, rate=1.0):
+def simulate(dh, arrivals, need, work, budget, slots, limit, rate=1.0, by_work=False):
     """Event-driven processor-sharing simulation; returns per-job (start, end)
-    and a log of (time, used_bytes, running)."""
+    and a log of (time, used_bytes, running). by_work passes the jobs' work to
+    the policy (shortest work first)."""
     n = len(arrivals)
     start = np.full(n, np.nan)
     end = np.full(n, np.nan)
@@ -31,7 +32,8 @@ def simulate(dh, arrivals, need, work, budget, slots, limit, rate=1.0):
         if queue and len(running) < slots:
             waited = [t - arrivals[q] for q in queue]
             pick = dh.sched_select([need[q] for q in queue], waited, budget - used,
-                                   slots - len(running), limit)
+                                   slots - len(running), limit,
+                                   [work[q] for q in queue] if by_work else None)
             chosen = [queue[k] for k in pick]
             for q in chosen:
                 queue.remove(q)
@@ -112,3 +114,48 @@ def test_select_edge_cases(dh):
     assert dh.sched_select([200, 10], [0.5, 0.1], 100, 4, 1.0) == [1]
     assert dh.sched_select([200, 10], [1.5, 0.1], 100, 4, 1.0) == []
     assert dh.sched_select([30, 40, 50], [0, 0, 0], 100, 4, 1.0) == [0, 1]
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+@pytest.mark.parametrize("slots", [1, 2])
+def test_shortest_work_first_lowers_latency(dh, seed, slots):
+    """With jobs queueing (few slots, offered load below one), admitting the
+    least work first lowers mean and median latency against arrival order;
+    the worst latency grows by at most the wait limit."""
+    arrivals, need, work = trace(seed)
+    budget, limit, rate = 1 << 40, 10.0, 80.0
+    _, end_a, _ = simulate(dh, arrivals, need, work, budget, slots, limit, rate)
+    start, end_w, log = simulate(dh, arrivals, need, work, budget, slots, limit, rate,
+                                 by_work=True)
+    assert np.all(np.isfinite(end_w)) and np.all(start >= arrivals - 1e-12)
+    assert all(running <= slots for _, _, running in log)
+    lat_a, lat_w = end_a - arrivals, end_w - arrivals
+    assert lat_w.mean() < 0.95 * lat_a.mean()
+    assert np.percentile(lat_w, 50) <= np.percentile(lat_a, 50)
+    assert lat_w.max() <= lat_a.max() + limit
+
+
+def test_wait_limit_bounds_passing_over(dh):
+    """Shortest work first: a large job is passed over by smaller ones only
+    until it has waited the limit; after that no job arriving later starts
+    before it."""
+    arrivals = np.array([0.0] + list(0.01 + 0.02 * np.arange(200)))
+    need = np.array([10] * 201)
+    work = np.array([50.0] + [0.05] * 200)
+    limit = 0.5
+    start, end, _ = simulate(dh, arrivals, need, work, 1000, slots=1, limit=limit,
+                             by_work=True)
+    assert np.all(np.isfinite(end))
+    big = 0
+    assert start[big] <= arrivals[big] + limit + 0.05 + 1e-9     # one small job's length late at most
+    for q in range(1, len(arrivals)):
+        if start[q] > arrivals[big] + limit + 0.05 + 1e-9:
+            assert start[q] >= start[big] - 1e-12, f"job {q} jumped the large job past its limit"
+
+
+def test_select_by_work(dh):
+    assert dh.sched_select([10, 10, 10], [0, 0, 0], 100, 2, 1.0, work=[5.0, 1.0, 3.0]) == [1, 2]
+    # a job past the limit goes first whatever its work
+    assert dh.sched_select([10, 10, 10], [0, 2.0, 0], 100, 1, 1.0, work=[1.0, 9.0, 2.0]) == [1]
+    # and one that does not fit stops everything
+    assert dh.sched_select([10, 500, 10], [0, 2.0, 0], 100, 3, 1.0, work=[1.0, 9.0, 2.0]) == []
