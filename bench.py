@@ -449,7 +449,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the histogram of a frame runs on a single "
-              "MI355X; multi-GPU runs are not part of this build", file=sys.stderr)
+              "MI355X, and runs on more than one GPU are not supported", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -5,8 +5,7 @@ the histogram arithmetic, so both the CPU oracle and the HIP path can consume
 exactly the same bytes from it.
 
 The benchmark inputs follow the paper's practice of pseudo-random particle
-coordinates in a box (Sec. 4, opening paragraphs), scaled to the shapes of the
-workloads described in the design doc:
+coordinates in a box (Sec. 4, opening paragraphs), scaled to these workloads:
 
 * ``tiny``      1 frame, N=5,000 uniform in [0,10)^3, 1 species, no box,
                 r_max = 10*sqrt(3), 1,000 bins.
