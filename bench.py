@@ -304,32 +304,49 @@ def bench_trajectory(ctx, n_frames: int, steps: int):
     }
 
 
-def run_trace(server_args, frames, gaps):
+def run_trace(server_args, frames, gaps, progress: str = ""):
     """Submits frames at the given inter-arrival gaps (seconds) to a new
-    server; returns per-job latencies and the makespan."""
+    server; returns per-job latencies and the makespan. With progress set,
+    prints a line to stderr every 250 completed jobs."""
     import threading
     import paper_1808_01478_amd as dh
     with dh.Server(0, **server_args) as srv:
         ids, t_sub = [None] * len(frames), [0.0] * len(frames)
+        submitted = [threading.Event() for _ in frames]
+        failure = []
         t0 = time.perf_counter()
 
         def client():
             t_next = t0
-            for k, (f, g) in enumerate(zip(frames, gaps)):
-                t_next += g
-                delay = t_next - time.perf_counter()
-                if delay > 0:
-                    time.sleep(delay)
-                t_sub[k] = time.perf_counter() - t0
-                ids[k] = srv.submit(f.coords, f.offsets, f.box_type, f.box, f.r_max, f.n_bins,
-                                    dh.FP32)
+            try:
+                for k, (f, g) in enumerate(zip(frames, gaps)):
+                    t_next += g
+                    delay = t_next - time.perf_counter()
+                    if delay > 0:
+                        time.sleep(delay)
+                    t_sub[k] = time.perf_counter() - t0
+                    ids[k] = srv.submit(f.coords, f.offsets, f.box_type, f.box, f.r_max,
+                                        f.n_bins, dh.FP32)
+                    submitted[k].set()
+            except BaseException as e:  # the waits below must not block on it
+                failure.append(e)
+                for ev in submitted:
+                    ev.set()
         th = threading.Thread(target=client)
         th.start()
-        th.join()
+        # wait for each job as soon as it is submitted, in submission order
         lat = []
         for k in range(len(frames)):
+            submitted[k].wait()
+            if failure:
+                break
             _, _, times = srv.wait(ids[k])
             lat.append(times[2])
+            if progress and (k + 1) % 250 == 0:
+                print(f"[serving] {progress}: {k + 1} jobs done", file=sys.stderr, flush=True)
+        th.join()
+        if failure:
+            raise failure[0]
         st = srv.stats()
     end = max(t + l for t, l in zip(t_sub, lat))
     return np.array(lat), end, st
@@ -373,6 +390,57 @@ def bench_serving(n_jobs: int, seed: int = 5):
                      "p99_ms": float(np.percentile(lat, 99) * 1e3),
                      "throughput_pairs_per_s": pairs / end, "jobs_per_s": n_jobs / end,
                      "max_running": st["max_running"], "peak_bytes": st["peak_bytes"]}
+    return out
+
+
+def bench_serving_sweep(policy: str, n_jobs: int = 1000, n_warm: int = 50, seed: int = 5,
+                        loads=(0.25, 0.5, 0.75, 0.9)):
+    """The full serving protocol for one policy: n_warm warm-up jobs, then
+    n_jobs measured jobs (N log-uniform in [1e3, 2e6], box none/orthorhombic/
+    triclinic, 1-3 species, 1k/10k/50k bins, binary32) at Poisson arrival
+    rates of each load times the saturated capacity, with an 8 GiB budget;
+    for the default policy also one run at 0.75 with a 256 MiB budget
+    (admission back-pressure). policy: "shortest" (the server's default,
+    4 slots) or "fifo" (arrival order, one slot). Prints one progress line
+    per run to stderr."""
+    import paper_1808_01478_amd as dh
+    rng = np.random.Generator(np.random.PCG64(seed))
+    frames = [workloads.serving_job(rng, j, 0.0).frame for j in range(n_warm + n_jobs)]
+    warm, frames = frames[:n_warm], frames[n_warm:]
+    pairs = sum(f.total_pairs() for f in frames)
+    fifo = {"hbm_budget_bytes": 8 << 30, "max_inflight": 1, "policy": dh.SCHED_ARRIVAL}
+    if policy == "fifo":
+        args = fifo
+    elif policy == "shortest":
+        args = {"hbm_budget_bytes": 8 << 30, "max_inflight": 4, "policy": dh.SCHED_SHORTEST}
+    else:
+        raise ValueError(policy)
+    t0 = time.perf_counter()
+    run_trace(args, warm, [0.0] * len(warm))
+    # capacity: the measured jobs all submitted at once, one at a time
+    _, sat_end, _ = run_trace(fifo, frames, [0.0] * n_jobs, progress="capacity")
+    capacity = n_jobs / sat_end
+    print(f"[serving] {policy}: capacity {capacity:.2f} jobs/s "
+          f"({time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
+    runs = [(lam, args) for lam in loads]
+    if policy == "shortest":
+        runs.append((0.75, dict(args, hbm_budget_bytes=256 << 20)))
+    out = {"policy": policy, "jobs": n_jobs, "warmup_jobs": n_warm, "pairs": pairs,
+           "saturated_jobs_per_s": capacity, "runs": []}
+    for k, (lam, a) in enumerate(runs):
+        gaps = np.random.Generator(np.random.PCG64(seed * 100 + k)).exponential(
+            1.0 / (lam * capacity), size=n_jobs)
+        lat, end, st = run_trace(a, frames, gaps, progress=f"load {lam}")
+        row = {"load": lam, "budget_bytes": a["hbm_budget_bytes"],
+               "p50_ms": float(np.percentile(lat, 50) * 1e3),
+               "p90_ms": float(np.percentile(lat, 90) * 1e3),
+               "p99_ms": float(np.percentile(lat, 99) * 1e3),
+               "jobs_per_s": n_jobs / end, "throughput_pairs_per_s": pairs / end,
+               "max_running": st["max_running"], "peak_bytes": st["peak_bytes"]}
+        out["runs"].append(row)
+        print(f"[serving] {policy} load {lam} budget {a['hbm_budget_bytes'] >> 20} MiB: "
+              f"p50 {row['p50_ms']:.1f} ms p99 {row['p99_ms']:.1f} ms "
+              f"({time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
     return out
 
 
@@ -446,6 +514,9 @@ def main():
                     help="frames of the batched trajectory comparison (0 = skip)")
     ap.add_argument("--no-wide", dest="wide", action="store_false",
                     help="skip the wide-histogram comparison")
+    ap.add_argument("--serving-sweep", choices=("shortest", "fifo"), default=None,
+                    help="run only the full serving protocol for one policy (1000 jobs at "
+                         "each of four loads, several minutes) and print its JSON line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the histogram of a frame runs on a single "
@@ -454,6 +525,10 @@ def main():
 
     import torch
     import paper_1808_01478_amd as dh
+
+    if args.serving_sweep:
+        print(json.dumps({"serving_sweep": bench_serving_sweep(args.serving_sweep)}), flush=True)
+        return
 
     frame, desc = workload(args.workload)
     kind = box_kind(frame)
