@@ -166,8 +166,11 @@ int dh_histo_async(dh_ctx *ctx, dh_stream stream, const double *d_coords,
 
 /*
  * Scaled distances t = r * n_bins / r_max of explicit particle pairs,
- * evaluated with exactly the device arithmetic that the histogram kernels
- * use for the given precision and box (Algorithm 1 without the increment).
+ * evaluated with the device arithmetic that the histogram kernels use for
+ * the given precision and box (Algorithm 1 without the increment): exactly
+ * in binary64; in binary32 with periodic cells the pair kernel takes the c
+ * differences of two i-particles from one 64-bit addition, which can lower
+ * the second one by one fixed-point unit (2^-32 of the cell vector).
  * For checking sampled pairs of frames too large for an exhaustive CPU
  * comparison.
  *   d_coords   device [n][3] binary64 (one species; n <= 2^31 - 1).

@@ -193,6 +193,9 @@ __device__ __forceinline__ float frac_diff(float ui, float uj) {
 template <int BOX>
 __device__ __forceinline__ float t32_packed(uint64_t ab_j, uint64_t neg_ab_i, float zi, float zj,
                                             const Geo32 &g);
+template <int BOX>
+__device__ __forceinline__ float t32_packed_c(uint64_t ab_j, uint64_t neg_ab_i, float fc,
+                                              const Geo32 &g);
 
 // Triclinic reduced vector (t units) from packed fractional words.
 __device__ __forceinline__ void tric_vec32(uint64_t ab_j, uint64_t neg_ab_i, float zi, float zj,
@@ -247,11 +250,17 @@ __device__ __forceinline__ float t32(float xi, float yi, float zi, float xj, flo
 template <int BOX>
 __device__ __forceinline__ float t32_packed(uint64_t ab_j, uint64_t neg_ab_i, float zi, float zj,
                                             const Geo32 &g) {
+  return t32_packed_c<BOX>(ab_j, neg_ab_i, frac_diff(zi, zj), g);
+}
+
+// The same with the c difference given (as a float of fixed-point units).
+template <int BOX>
+__device__ __forceinline__ float t32_packed_c(uint64_t ab_j, uint64_t neg_ab_i, float fc,
+                                              const Geo32 &g) {
   {
     const uint64_t dab = ab_j + neg_ab_i;
     const float fa = static_cast<float>(static_cast<int32_t>(static_cast<uint32_t>(dab)));
     const float fb = static_cast<float>(static_cast<int32_t>(static_cast<uint32_t>(dab >> 32)));
-    const float fc = frac_diff(zi, zj);
     if constexpr (BOX == kBoxCube) {
       return __builtin_amdgcn_sqrtf(fmaf(fc, fc, fmaf(fb, fb, fa * fa))) * g.kx;
     } else if constexpr (BOX == kBoxOrtho) {
@@ -341,12 +350,15 @@ __device__ __forceinline__ float4 stage_point32(double x, double y, double z,
     return make_float4(static_cast<float>(x * p.s), static_cast<float>(y * p.s),
                        static_cast<float>(z * p.s), 0.f);
   } else if constexpr (BOX == kBoxOrtho) {
-    return make_float4(fixfrac(x * p.iL[0]), fixfrac(y * p.iL[1]), fixfrac(z * p.iL[2]), 0.f);
+    // c twice: the pair kernel reads (c : c) as one 64-bit word
+    const float c = fixfrac(z * p.iL[2]);
+    return make_float4(fixfrac(x * p.iL[0]), fixfrac(y * p.iL[1]), c, c);
   } else {
     const double fa = fma(z, p.h13, fma(y, p.h12, x * p.h11));
     const double fb = fma(z, p.h23, y * p.h22);
     const double fc = z * p.h33;
-    return make_float4(fixfrac(fa), fixfrac(fb), fixfrac(fc), 0.f);
+    const float c = fixfrac(fc);
+    return make_float4(fixfrac(fa), fixfrac(fb), c, c);
   }
 }
 
@@ -500,6 +512,19 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
     else
       nab[r] = 0ull;
   }
+  // -(c' : c) of i-particles 2k and 2k+1: one 64-bit addition to j's (c : c)
+  // gives both c differences, the second lowered by one unit when the first
+  // borrows (as for b above)
+  static_assert(R % 2 == 0, "i-particles are paired for the c difference");
+  uint64_t nzz[R / 2];
+#pragma unroll
+  for (int k = 0; k < R / 2; ++k) {
+    if constexpr (sizeof(T) == 4)
+      nzz[k] = 0ull - ((static_cast<uint64_t>(__float_as_uint(zi[2 * k + 1])) << 32) |
+                       __float_as_uint(zi[2 * k]));
+    else
+      nzz[k] = 0ull;
+  }
   float lof[R];
   const float hif = static_cast<float>(hi);
 #pragma unroll
@@ -613,18 +638,18 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
     if constexpr (DIAG) js = max(0, min(jcount, wbase + 1 - jt));
     if (wave_active && js < jcount) {
       const V *__restrict__ tb = tile + buf * tj;
-      // periodic binary32: j as its packed (b:a) word plus c (see t32_packed)
+      // periodic binary32: j as its packed (b:a) and (c:c) words, one
+      // 16-byte read (see t32_packed and the staging)
       constexpr bool kPacked = sizeof(T) == 4 && BOX != kBoxNone;
       struct JPacked {
         uint64_t ab;
-        float z;
+        uint64_t cc;
       };
       using J = typename std::conditional<kPacked, JPacked, V>::type;
       const uint64_t *__restrict__ tb64 = reinterpret_cast<const uint64_t *>(tb);
-      const float *__restrict__ tbf = reinterpret_cast<const float *>(tb);
       auto load_j = [&](int k) -> J {
         if constexpr (kPacked)
-          return JPacked{tb64[2 * k], tbf[4 * k + 2]};
+          return JPacked{tb64[2 * k], tb64[2 * k + 1]};
         else
           return tb[k];
       };
@@ -642,7 +667,8 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
           if constexpr (SEARCH) {
             T dx, dy, dz;
             if constexpr (kPacked)
-              tric_vec32(pj.ab, nab[r], zi[r], pj.z, g, dx, dy, dz);
+              tric_vec32(pj.ab, nab[r], zi[r], __uint_as_float(static_cast<uint32_t>(pj.cc)),
+                         g, dx, dy, dz);
             else
               reduce64<BOX>(xi[r], yi[r], zi[r], pj.x, pj.y, pj.z, g, dx, dy, dz);
             const T q0 = fmaT(dz, dz, fmaT(dy, dy, dx * dx));
@@ -669,13 +695,14 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
               }
               qn += __builtin_popcountll(m);
             }
+          } else if constexpr (kPacked) {
+            // c differences of i-particles r and r+1 from one 64-bit add
+            const uint64_t dcc = pj.cc + nzz[r / 2];
+            const float fc = static_cast<float>(static_cast<int32_t>(
+                static_cast<uint32_t>(r % 2 == 0 ? dcc : dcc >> 32)));
+            count_t(t32_packed_c<BOX>(pj.ab, nab[r], fc, g), l, lf);
           } else {
-            T t;
-            if constexpr (kPacked)
-              t = t32_packed<BOX>(pj.ab, nab[r], zi[r], pj.z, g);
-            else
-              t = pair_t<T, BOX>(xi[r], yi[r], zi[r], pj.x, pj.y, pj.z, g);
-            count_t(t, l, lf);
+            count_t(pair_t<T, BOX>(xi[r], yi[r], zi[r], pj.x, pj.y, pj.z, g), l, lf);
           }
         }
         if constexpr (SEARCH)
@@ -698,8 +725,8 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
         const V *cur = tb + js + vzero;
         auto load_at = [&](const V *q) -> J {
           if constexpr (kPacked)
-            return JPacked{*reinterpret_cast<const uint64_t *>(q),
-                           reinterpret_cast<const float *>(q)[2]};
+            return JPacked{reinterpret_cast<const uint64_t *>(q)[0],
+                           reinterpret_cast<const uint64_t *>(q)[1]};
           else
             return *q;
         };
