@@ -33,12 +33,19 @@
  *                 positive diagonal, reduced so that |b_x| <= a_x/2,
  *                 |c_x| <= a_x/2 and |c_y| <= b_y/2.
  *   r_max         finite, > 0.
- *   n_bins        1..2^24.
+ *   n_bins        1..2^24 for DH_FP64, 1..2^22 for DH_FP32 (beyond 2^22 a
+ *                 binary32 t is spaced half a bin or more apart).
  *   precision     DH_FP64: the canonical binary64 evaluation below; counts
  *                 are exactly those of that op sequence.
  *                 DH_FP32: a binary32 evaluation; a pair may change bin
  *                 only if its binary64 distance lies within a few binary32
- *                 ulps of the bin edge.
+ *                 ulps of the bin edge. The bin is taken from the bits of
+ *                 t + (2^23 - 1/2) rounded to nearest, which is floor(t)
+ *                 except that an exactly integer odd t counts one bin
+ *                 lower (a tie); in a cube r * s and the offset are one
+ *                 fused operation. Every device path (LDS histograms, bin
+ *                 windows, global atomics, batches) bins alike, so binary32
+ *                 counts do not depend on the launch shape.
  *   histograms    uint64 [H][n_bins], H = n_species*(n_species+1)/2, in the
  *                 order (0,0),(1,1),...,(k-1,k-1), then (s,t) for s < t in
  *                 lexicographic order. Always overwritten.

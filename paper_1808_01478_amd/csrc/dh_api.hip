@@ -101,6 +101,8 @@ namespace {
 
 constexpr int32_t kMaxSpecies = 64;
 constexpr int32_t kMaxBins = 1 << 24;
+// binary32 bins come from t + (2^23 - 1/2), exact for t < 2^22
+constexpr int32_t kMaxBins32 = 1 << 22;
 constexpr int64_t kMaxN = 2147483647LL;
 
 // message of the last failure that had no context to hold it
@@ -151,6 +153,7 @@ int check(const double *coords, const int64_t *offsets, int32_t n_species, int32
   if (!(r_max > 0) || !std::isfinite(r_max)) return DH_EINVAL;
   if (n_bins < 1 || n_bins > kMaxBins) return DH_EINVAL;
   if (precision != DH_FP32 && precision != DH_FP64) return DH_EINVAL;
+  if (precision == DH_FP32 && n_bins > kMaxBins32) return DH_EINVAL;
   if (!box_ok(box_type, box)) return DH_EINVAL;
   if (coords)
     for (int64_t i = 0; i < 3 * n; ++i)

@@ -197,6 +197,31 @@ template <int BOX>
 __device__ __forceinline__ float t32_packed_c(uint64_t ab_j, uint64_t neg_ab_i, float fc,
                                               const Geo32 &g);
 
+// Binary32 bins without a float-to-integer conversion: t + (2^23 - 1/2)
+// rounded to nearest lies in [2^23, 2^24) for 1/2 <= t < 2^22, where the
+// spacing is 1, so its bits minus those of 2^23 are floor(t), except at an
+// integer t: that is a tie, which goes to the even neighbour, so an odd
+// integer t counts one bin lower (a pair at a bin edge, inside the binary32
+// tolerance). For t < 1/4 the difference is -1 (bin 0; the counting code
+// maps it there); it grows monotonically with t and is at least 2^22 for
+// t >= 2^22, +inf and NaN (read as unsigned). Binary32 histograms have at
+// most 2^22 bins, so a pair counts iff the difference is below n_bins.
+constexpr float kMagic32 = 8388607.5f;        // 2^23 - 1/2
+constexpr int kGuardBytes = 16;               // >= 4 bytes per copy, 4 copies at most
+constexpr uint32_t kMagicBits = 0x4B000000u;  // bits of 2^23
+
+__device__ __forceinline__ uint32_t bin_bits32(float t) {
+  return __float_as_uint(t + kMagic32);
+}
+
+// median of three unsigned values: x clamped to [lo, hi] when lo <= hi (the
+// compiler forms v_med3_u32 only for constant bounds)
+__device__ __forceinline__ uint32_t med3_u32(uint32_t x, uint32_t lo, uint32_t hi) {
+  uint32_t r;
+  asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo), "v"(hi));
+  return r;
+}
+
 // Triclinic reduced vector (t units) from packed fractional words.
 __device__ __forceinline__ void tric_vec32(uint64_t ab_j, uint64_t neg_ab_i, float zi, float zj,
                                            const Geo32 &g, float &dx, float &dy, float &dz) {
@@ -274,6 +299,22 @@ __device__ __forceinline__ float t32_packed_c(uint64_t ab_j, uint64_t neg_ab_i, 
       if constexpr (BOX == kBoxTricSearch) q = search_q32(dx, dy, dz, q, g);
       return __builtin_amdgcn_sqrtf(q);
     }
+  }
+}
+
+// Bin bits (see bin_bits32) of the same distance; in a cube the scale and
+// the offset are one fused multiply-add on the root.
+template <int BOX>
+__device__ __forceinline__ uint32_t bits32_packed_c(uint64_t ab_j, uint64_t neg_ab_i, float fc,
+                                                    const Geo32 &g) {
+  if constexpr (BOX == kBoxCube) {
+    const uint64_t dab = ab_j + neg_ab_i;
+    const float fa = static_cast<float>(static_cast<int32_t>(static_cast<uint32_t>(dab)));
+    const float fb = static_cast<float>(static_cast<int32_t>(static_cast<uint32_t>(dab >> 32)));
+    const float r = __builtin_amdgcn_sqrtf(fmaf(fc, fc, fmaf(fb, fb, fa * fa)));
+    return __float_as_uint(fmaf(r, g.kx, kMagic32));
+  } else {
+    return bin_bits32(t32_packed_c<BOX>(ab_j, neg_ab_i, fc, g));
   }
 }
 
@@ -443,8 +484,9 @@ __device__ __forceinline__ void flush_hist(uint32_t *hist, const PairKernelArgs 
   const int clear = a.stride;
   for (int b = threadIdx.x; b < clear; b += blockDim.x) {
     uint64_t v = 0;
-    uint32_t *p = hist + b * a.copies;
-    for (int c = 0; c < a.copies; ++c) {
+    // bin 0 also takes the guard words below the histogram (binary32 bin -1)
+    uint32_t *p = hist + (b == 0 ? -a.copies : b * a.copies);
+    for (int c = 0; c < (b == 0 ? 2 : 1) * a.copies; ++c) {
       v += p[c];
       p[c] = 0u;
     }
@@ -484,6 +526,15 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
   const int log_copies = a.copies == 4 ? 2 : (a.copies == 2 ? 1 : 0);
   const uint32_t shift_bytes = static_cast<uint32_t>(log_copies + 2);
   char *const my_bytes = reinterpret_cast<char *>(my);
+  // binary32 counts address LDS as 32-bit integers: this lane's copy of bin 0,
+  // less the bin-bit offset (the wrap-around is intended)
+  using LdsU32 = __attribute__((address_space(3))) uint32_t;
+  const uint32_t my_lds =
+      static_cast<uint32_t>(reinterpret_cast<uintptr_t>((LdsU32 *)my));
+  uint32_t my_lds_m = my_lds - (kMagicBits << shift_bytes);
+  // opaque, so the compiler keeps (bits << shift) + my_lds_m as one
+  // v_lshl_add_u32 instead of subtracting the offset from every bin
+  asm volatile("" : "+v"(my_lds_m));
   // canonical once here, so fmin below needs no per-pair canonicalisation
   const double cap64 = __builtin_canonicalize(static_cast<double>(a.stride - 1));
 
@@ -525,10 +576,6 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
     else
       nzz[k] = 0ull;
   }
-  float lof[R];
-  const float hif = static_cast<float>(hi);
-#pragma unroll
-  for (int r = 0; r < R; ++r) lof[r] = static_cast<float>(lo[r]);
   const int n_bins = uni(F->n_bins);
   // the output is global memory: say so, so the atomics are global_atomic_*
   // (a generic pointer would give flat atomics, which also count as LDS
@@ -537,39 +584,56 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
   GlobalU64 *const gout =
       (GlobalU64 *)(F->out + static_cast<size_t>(w.hist) * static_cast<size_t>(n_bins));
 
-  // Counts one pair at scaled distance t. l / lf: lower clamp, 0 for a pair
-  // that counts, the lane's discard slot for one that must not.
-  auto count_t = [&](T t, uint32_t l, float lf) {
-    if constexpr (GLOBAL) {
-      // a pair counts iff t < n_bins (in the working precision)
-      if (l == 0u && t < static_cast<T>(n_bins))
-        __hip_atomic_fetch_add(gout + static_cast<uint32_t>(t), 1ull, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      uint32_t idx;
-      if constexpr (!CLAMP) {
-        if constexpr (sizeof(T) == 4) {
-          // fixed-point staging bounds every binary32 t below the stride
-          idx = static_cast<uint32_t>(t);
+  // Counts one pair: binary64 at scaled distance v = t, binary32 from its bin
+  // bits v (bin_bits32). l: 0 for a pair that counts, the lane's discard slot
+  // for one that must not (the lower clamp).
+  auto count_t = [&](auto v, uint32_t l) {
+    if constexpr (sizeof(T) == 4) {
+      const uint32_t b = v;
+      if constexpr (GLOBAL) {
+        const uint32_t k = max(b, kMagicBits) - kMagicBits;
+        if (l == 0u && k < static_cast<uint32_t>(n_bins))
+          __hip_atomic_fetch_add(gout + k, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        uint32_t m;  // bin + kMagicBits
+        if constexpr (!CLAMP) {
+          // fixed-point staging bounds every t below the stride; bin -1 is
+          // the guard word below the histogram, added to bin 0 on flush
+          m = b;
+        } else if constexpr (!SWEEP) {
+          const uint32_t lb = l == 0u ? kMagicBits - 1u : kMagicBits + hi;
+          m = med3_u32(b, lb, kMagicBits + hi);
         } else {
+          // bins below the window wrap to large values and are discarded
+          const uint32_t u = max(b, kMagicBits) - (kMagicBits + static_cast<uint32_t>(b_lo));
+          m = med3_u32(u, l, hi) + kMagicBits;
+        }
+        __hip_atomic_fetch_add((LdsU32 *)(uintptr_t)(my_lds_m + (m << shift_bytes)), 1u,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+    } else {
+      const T t = v;
+      if constexpr (GLOBAL) {
+        // a pair counts iff t < n_bins (in the working precision)
+        if (l == 0u && t < static_cast<T>(n_bins))
+          __hip_atomic_fetch_add(gout + static_cast<uint32_t>(t), 1ull, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        uint32_t idx;
+        if constexpr (!CLAMP) {
           // binary64 reads raw device coordinates: cap t so that even
           // non-finite or absurd input stays inside the LDS histogram
           idx = static_cast<uint32_t>(fmin(t, cap64));
-        }
-      } else if constexpr (sizeof(T) == 4 && !SWEEP) {
-        idx = static_cast<uint32_t>(__builtin_amdgcn_fmed3f(t, lf, hif));
-      } else {
-        // floor(t), saturated; t >= 0 always
-        if constexpr (sizeof(T) == 4)
-          idx = static_cast<uint32_t>(fminf(t, 4294967040.0f));
-        else
+        } else {
+          // floor(t), saturated; t >= 0 always
           idx = static_cast<uint32_t>(fmin(t, 4294967295.0));
-        if constexpr (SWEEP) idx -= static_cast<uint32_t>(b_lo);
-        idx = max(min(idx, hi), l);
+          if constexpr (SWEEP) idx -= static_cast<uint32_t>(b_lo);
+          idx = max(min(idx, hi), l);
+        }
+        // byte offset with one shift (copies interleaved bin-major), so the
+        // address is a single v_lshl_add_u32
+        atomicAdd(reinterpret_cast<uint32_t *>(my_bytes + (idx << shift_bytes)), 1u);
       }
-      // byte offset with one shift (copies interleaved bin-major), so the
-      // address is a single v_lshl_add_u32
-      atomicAdd(reinterpret_cast<uint32_t *>(my_bytes + (idx << shift_bytes)), 1u);
     }
   };
 
@@ -605,12 +669,10 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
       const V e = wq[idx];
       T q = fmaT(e.z, e.z, fmaT(e.y, e.y, e.x * e.x));
       q = search_lds<T>(e.x, e.y, e.z, q, sh);
-      T t;
       if constexpr (sizeof(T) == 4)
-        t = __builtin_amdgcn_sqrtf(q);
+        count_t(bin_bits32(__builtin_amdgcn_sqrtf(q)), v ? 0u : hi);
       else
-        t = sqrt_rn(q) * g.s;
-      count_t(t, v ? 0u : hi, v ? 0.f : hif);
+        count_t(sqrt_rn(q) * g.s, v ? 0u : hi);
       head += cnt;
       if (head >= cap) head -= cap;
       qn -= cnt;
@@ -658,11 +720,9 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           uint32_t l = lo[r];
-          float lf = lof[r];
           if constexpr (DIAG) {
             const bool up = j > wbase + r * 64 + lane;
             l = up ? l : hi;
-            lf = up ? lf : hif;
           }
           if constexpr (SEARCH) {
             T dx, dy, dz;
@@ -675,12 +735,10 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
             // valid pairs at least half the shortest lattice vector long
             // are searched later; they must not count now
             const bool need = l == 0u && q0 >= qskip;
-            T t;
             if constexpr (sizeof(T) == 4)
-              t = __builtin_amdgcn_sqrtf(q0);
+              count_t(bin_bits32(__builtin_amdgcn_sqrtf(q0)), need ? hi : l);
             else
-              t = sqrt_rn(q0) * g.s;
-            count_t(t, need ? hi : l, need ? hif : lf);
+              count_t(sqrt_rn(q0) * g.s, need ? hi : l);
             const uint64_t m = __builtin_amdgcn_ballot_w64(need);
             if (m != 0) {
               const int below = __builtin_amdgcn_mbcnt_hi(
@@ -700,9 +758,11 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
             const uint64_t dcc = pj.cc + nzz[r / 2];
             const float fc = static_cast<float>(static_cast<int32_t>(
                 static_cast<uint32_t>(r % 2 == 0 ? dcc : dcc >> 32)));
-            count_t(t32_packed_c<BOX>(pj.ab, nab[r], fc, g), l, lf);
+            count_t(bits32_packed_c<BOX>(pj.ab, nab[r], fc, g), l);
+          } else if constexpr (sizeof(T) == 4) {
+            count_t(bin_bits32(pair_t<T, BOX>(xi[r], yi[r], zi[r], pj.x, pj.y, pj.z, g)), l);
           } else {
-            count_t(pair_t<T, BOX>(xi[r], yi[r], zi[r], pj.x, pj.y, pj.z, g), l, lf);
+            count_t(pair_t<T, BOX>(xi[r], yi[r], zi[r], pj.x, pj.y, pj.z, g), l);
           }
         }
         if constexpr (SEARCH)
@@ -767,20 +827,23 @@ __global__ __launch_bounds__(max_threads<BOX>()) void pairs_kernel(PairKernelArg
   extern __shared__ __align__(32) unsigned char smem[];
   __shared__ int s_item;
   V *tile = reinterpret_cast<V *>(smem);
-  uint32_t *hist = reinterpret_cast<uint32_t *>(smem + 2 * a.tj * sizeof(V));
+  // the histogram follows the two j-tiles and a guard of kGuardBytes: one
+  // word per copy for binary32 bin -1 (t < 1/4), added to bin 0 on flush.
+  // The host's allocation has one spare coordinate entry there.
+  uint32_t *hist = reinterpret_cast<uint32_t *>(smem + 2 * a.tj * sizeof(V) + kGuardBytes);
   const int tid = threadIdx.x;
   // lane-interleaved sub-histogram copies: lanes of one instruction that
   // hit the same bin use different words (and banks) when copies > 1
   uint32_t *my = hist + (tid & 63) % a.copies;
   // image-search queues after the histogram, 32-byte aligned
-  const size_t q_off = (2 * static_cast<size_t>(a.tj) * sizeof(V) +
+  const size_t q_off = (2 * static_cast<size_t>(a.tj) * sizeof(V) + kGuardBytes +
                         static_cast<size_t>(a.copies) * a.stride * 4 + 31) / 32 * 32;
   V *queue = reinterpret_cast<V *>(smem + q_off);
   V *shifts = queue + (blockDim.x / 64) * queue_cap(R);
 
   constexpr bool GLOBAL = MODE == kModeGlobal;
   if constexpr (!GLOBAL)
-    for (int k = tid; k < a.copies * a.stride; k += blockDim.x) hist[k] = 0u;
+    for (int k = tid - a.copies; k < a.copies * a.stride; k += blockDim.x) hist[k] = 0u;
 
   int cur_frame = -1, cur_hist = -1, cur_sweep = -1;
   uint64_t acc = 0;

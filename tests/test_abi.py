@@ -50,8 +50,10 @@ TRIC = np.array([[10.0, 0, 0], [3.0, 9.0, 0], [-4.0, 4.0, 8.0]])
     (dict(r_max=float("inf")), -1),
     (dict(r_max=float("nan")), -1),
     (dict(n_bins=0), -1),
-    (dict(n_bins=1 << 24), 0),
-    (dict(n_bins=(1 << 24) + 1), -1),
+    (dict(n_bins=1 << 24, precision=1), 0),
+    (dict(n_bins=(1 << 24) + 1, precision=1), -1),
+    (dict(n_bins=1 << 22), 0),                      # binary32: at most 2^22 bins
+    (dict(n_bins=(1 << 22) + 1), -1),
     (dict(precision=2), -1),
     (dict(offsets=[0, 5, 3]), -1),
     (dict(offsets=[1, 5]), -1),

@@ -84,8 +84,9 @@ def test_mode_selection(ctx):
 
 
 def test_max_bins(ctx):
-    """n_bins = 2^24 (the largest accepted): global mode against the oracle
-    (binary64) and against 400+ LDS bin windows (binary32)."""
+    """The largest accepted bin counts: binary64 with n_bins = 2^24 in global
+    mode against the oracle; binary32 with n_bins = 2^22 in global mode
+    against 100+ LDS bin windows (both bin alike)."""
     fr = workloads.random_frame(34, [3000], workloads.BOX_NONE, r_max=17.0, n_bins=1 << 24)
     print(f"\n[case] max bins N={fr.n}", flush=True)
     ctx.set_config(None)
@@ -93,12 +94,19 @@ def test_max_bins(ctx):
     assert ctx.last_config()["mode"] == MODE_GLOBAL
     ref = oracle.frame_histogram(fr, n_threads=4)   # per-thread copies of 128 MiB
     assert np.array_equal(g64, ref.hist) and np.array_equal(oor64, ref.out_of_range)
-    g32, _ = run_gpu(ctx, fr, 0)
+    f32 = workloads.Frame(fr.coords, fr.offsets, fr.box_type, fr.box, fr.r_max, 1 << 22,
+                          "max-bins-binary32")
+    g32, _ = run_gpu(ctx, f32, 0)
+    assert ctx.last_config()["mode"] == MODE_GLOBAL
     ctx.set_config(knobs(wide=0))
-    s32, _ = run_gpu(ctx, fr, 0)
-    assert ctx.last_config()["sweeps"] > 400
+    s32, _ = run_gpu(ctx, f32, 0)
+    assert ctx.last_config()["sweeps"] > 100
     ctx.set_config(None)
     assert np.array_equal(g32, s32)
+    ref32 = oracle.frame_histogram(f32, edge_window=oracle.edge_window(f32.coords, f32.box,
+                                                                       f32.r_max), n_threads=4)
+    bad = fp32_bound_violations(g32, ref32.hist, ref32.edges)
+    assert not bad, "; ".join(bad[:5])
 
 
 def test_full_size_wide(ctx):
