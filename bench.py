@@ -352,6 +352,24 @@ def run_trace(server_args, frames, gaps, progress: str = ""):
     return np.array(lat), end, st
 
 
+def bench_triclinic(ctx, steps: int):
+    """The clustered 1M-point triclinic frame (6 histograms, 5.0e11 pairs,
+    r_max below half the smallest width, so no image search) in binary32 and
+    binary64: pairs/s, kernel time and FLOP roofline fraction."""
+    import paper_1808_01478_amd as dh
+    frame, desc = workload("triclinic1M")
+    kind = box_kind(frame)
+    pairs = frame.total_pairs()
+    out = {"workload": desc, "pairs_per_step": pairs, "flops_per_pair": FLOPS_PER_PAIR[kind]}
+    for prec, name in ((dh.FP32, "fp32"), (dh.FP64, "fp64")):
+        r = time_path(ctx, frame, prec, steps, 1)
+        ach = pairs * FLOPS_PER_PAIR[kind] / (r["kernel_ms_avg"] * 1e-3) / 1e12
+        out[name] = {"value": pairs * steps / r["wall_s"], "unit": "pairs/s", "steps": steps,
+                     "kernel_ms_avg": r["kernel_ms_avg"], "achieved_tflops": ach,
+                     "roofline_frac": ach / PEAK_TFLOPS[prec], "launch_shape": ctx.last_config()}
+    return out
+
+
 def bench_serving(n_jobs: int, seed: int = 5):
     """Histogram jobs with N log-uniform in [1e3, 2e6], box none/orthorhombic/
     triclinic, 1-3 species, 1k/10k/50k bins, binary32, Poisson arrivals at
@@ -514,6 +532,8 @@ def main():
                     help="frames of the batched trajectory comparison (0 = skip)")
     ap.add_argument("--no-wide", dest="wide", action="store_false",
                     help="skip the wide-histogram comparison")
+    ap.add_argument("--triclinic-steps", type=int, default=3,
+                    help="timed steps per precision on the 1M-point triclinic frame (0 = skip)")
     ap.add_argument("--serving-sweep", choices=("shortest", "fifo"), default=None,
                     help="run only the full serving protocol for one policy (1000 jobs at "
                          "each of four loads, several minutes) and print its JSON line")
@@ -608,6 +628,8 @@ def main():
         line["serving"] = bench_serving(args.serving_jobs)
         line["latency_ms"]["serving_p50"] = line["serving"]["shortest_remaining_work"]["p50_ms"]
         line["latency_ms"]["serving_p99"] = line["serving"]["shortest_remaining_work"]["p99_ms"]
+    if args.triclinic_steps > 0 and args.workload != "triclinic1M":
+        line["triclinic1M"] = bench_triclinic(ctx, args.triclinic_steps)
     if args.wide:
         line["wide"] = bench_wide(frame)
         line["image_search"] = bench_image_search()
