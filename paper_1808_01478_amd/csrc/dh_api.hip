@@ -483,6 +483,35 @@ void plan_frame(int32_t frame, const int64_t *off, int32_t k, const Launch &L,
     for (int32_t t = s + 1; t < k; ++t) plan_hist(s, t);
 }
 
+// Splits the last `grid` items of a work list (the ones workgroups take
+// when the rest is done) into pieces of about a quarter of their j-range,
+// in whole j-tiles, so that the workgroups finish close together instead of
+// idling for up to one full item. Diagonal items stay whole; the grouping
+// by (histogram, window) is kept.
+void refine_tail(std::vector<WorkItem> &items, int grid, int tj) {
+  const size_t n = items.size();
+  const size_t tail = std::min<size_t>(n, static_cast<size_t>(std::max(grid, 0)));
+  if (tail == 0) return;
+  std::vector<WorkItem> out(items.begin(), items.end() - static_cast<std::ptrdiff_t>(tail));
+  out.reserve(n + 3 * tail);
+  for (size_t q = n - tail; q < n; ++q) {
+    const WorkItem &w = items[q];
+    const int32_t len = w.j1 - w.j0;
+    const int32_t piece = std::max<int32_t>(tj, (len / 4 + tj - 1) / tj * tj);
+    if ((w.flags & kItemDiag) || len <= piece) {
+      out.push_back(w);
+      continue;
+    }
+    for (int32_t j = w.j0; j < w.j1; j += piece) {
+      WorkItem p = w;
+      p.j0 = j;
+      p.j1 = std::min(j + piece, w.j1);
+      out.push_back(p);
+    }
+  }
+  items.swap(out);
+}
+
 int ensure_device(dh_ctx *ctx, void **ptr, size_t *cap, size_t need) {
   if (need <= *cap) return DH_OK;
   size_t want = std::max(need, *cap + *cap / 2);
@@ -624,6 +653,7 @@ int run_frame(dh_ctx *ctx, hipStream_t st, const FrameJob &job, const Knobs &k, 
   std::vector<WorkItem> items;
   std::vector<uint64_t> pairs;
   plan_frame(0, job.offsets, job.n_species, L, items, pairs);
+  refine_tail(items, L.grid, L.cfg.tj);
   std::vector<size_t> cuts(1, 0);
   if (limit > 0 && work > limit) {
     uint64_t acc = 0;
