@@ -32,6 +32,9 @@ struct dh_ctx {
   size_t hblob_cap = 0;
   hipEvent_t blob_evt = nullptr;
   bool blob_pending = false;
+  // bytes of the last work blob uploaded to d_blob (its counters excepted):
+  // an identical plan is not uploaded again
+  std::vector<char> blob_last;
   double *d_in = nullptr;
   size_t in_cap = 0;
   uint64_t *d_out = nullptr;
@@ -566,9 +569,18 @@ BlobLayout blob_layout(size_t n_frames, size_t n_items, size_t n_pairs, size_t n
   return b;
 }
 
+// Uploads frames, items and pair counts with zeroed work counters. With
+// reuse set, a blob identical to the one already on the device (same plan,
+// same buffers) is not uploaded again; the caller then zeroes the counters.
 int upload_blob(dh_ctx *ctx, hipStream_t st, const BlobLayout &lay,
                 const std::vector<FrameParams> &frames, const std::vector<WorkItem> &items,
-                const std::vector<uint64_t> &pairs) {
+                const std::vector<uint64_t> &pairs, bool reuse = false) {
+  std::vector<char> next(lay.counter, 0);
+  if (!frames.empty()) std::memcpy(next.data() + lay.frames, frames.data(), frames.size() * sizeof(FrameParams));
+  if (!items.empty()) std::memcpy(next.data() + lay.items, items.data(), items.size() * sizeof(WorkItem));
+  if (!pairs.empty()) std::memcpy(next.data() + lay.pairs, pairs.data(), pairs.size() * sizeof(uint64_t));
+  if (reuse && ctx->d_blob && ctx->blob_cap >= lay.total && next == ctx->blob_last) return DH_OK;
+  ctx->blob_last.clear();
   int rc = ensure_pinned(ctx, lay.total);
   if (rc) return rc;
   rc = ensure_device(ctx, &ctx->d_blob, &ctx->blob_cap, lay.total);
@@ -578,13 +590,12 @@ int upload_blob(dh_ctx *ctx, hipStream_t st, const BlobLayout &lay,
     ctx->blob_pending = false;
   }
   char *h = static_cast<char *>(ctx->h_blob);
-  if (!frames.empty()) std::memcpy(h + lay.frames, frames.data(), frames.size() * sizeof(FrameParams));
-  if (!items.empty()) std::memcpy(h + lay.items, items.data(), items.size() * sizeof(WorkItem));
-  if (!pairs.empty()) std::memcpy(h + lay.pairs, pairs.data(), pairs.size() * sizeof(uint64_t));
+  std::memcpy(h, next.data(), next.size());
   std::memset(h + lay.counter, 0, lay.total - lay.counter);
   DH_HIP(ctx, hipMemcpyAsync(ctx->d_blob, h, lay.total, hipMemcpyHostToDevice, st));
   DH_HIP(ctx, hipEventRecord(ctx->blob_evt, st));
   ctx->blob_pending = true;
+  ctx->blob_last.swap(next);
   return DH_OK;
 }
 
@@ -670,16 +681,23 @@ int run_frame(dh_ctx *ctx, hipStream_t st, const FrameJob &job, const Knobs &k, 
   const size_t n_launches = cuts.size() - 1;
   fp.coords = ctx->d_staged;
   fp.out = job.d_out;
+  // with LDS histograms the flushes count the out-of-range pairs: oor starts
+  // at the pair count (zero kernel) and every flush subtracts its counts
+  const bool oor_flush = job.d_oor && L.mode != kModeGlobal;
+  fp.oor = oor_flush ? job.d_oor : nullptr;
+  fp.oor_by_flush = oor_flush ? 1 : 0;
   const BlobLayout lay = blob_layout(1, items.size(), pairs.size(), n_launches);
   std::vector<FrameParams> frames(1, fp);
-  int rc = upload_blob(ctx, st, lay, frames, items, pairs);
+  // an unchanged plan is reused when the zero kernel below resets the counters
+  int rc = upload_blob(ctx, st, lay, frames, items, pairs, !job.accumulate);
   if (rc) return rc;
   char *db = static_cast<char *>(ctx->d_blob);
   if (stage) DH_HIP(ctx, launch_stage(job.precision, job.kind, job.d_coords, ctx->d_staged, n, fp, st));
-  // (the work counters are zeroed with the blob upload)
   if (!job.accumulate)
     DH_HIP(ctx, launch_zero(job.d_out, static_cast<int64_t>(n_hist) * fp.n_bins,
-                            reinterpret_cast<int32_t *>(db + lay.counter), st));
+                            reinterpret_cast<int32_t *>(db + lay.counter),
+                            static_cast<int32_t>(n_launches), fp.oor,
+                            reinterpret_cast<const uint64_t *>(db + lay.pairs), n_hist, st));
   const int grid = std::max(1, std::min<int>(L.grid, static_cast<int>(items.size())));
   if (ctx->hold) {
     ctx->held.clear();
@@ -711,13 +729,13 @@ int run_frame(dh_ctx *ctx, hipStream_t st, const FrameJob &job, const Knobs &k, 
   }
   if (e1) DH_HIP(ctx, hipEventRecord(e1, st));
   if (ctx->hold) {
-    ctx->held_oor = job.d_oor != nullptr;
+    ctx->held_oor = job.d_oor != nullptr && !oor_flush;
     ctx->oor_hist = job.d_out;
     ctx->oor_n_hist = n_hist;
     ctx->oor_n_bins = fp.n_bins;
     ctx->oor_pairs = reinterpret_cast<const uint64_t *>(db + lay.pairs);
     ctx->oor_out = job.d_oor;
-  } else if (job.d_oor) {
+  } else if (job.d_oor && !oor_flush) {
     DH_HIP(ctx, launch_oor(job.d_out, n_hist, fp.n_bins,
                            reinterpret_cast<const uint64_t *>(db + lay.pairs), job.d_oor, st));
   }
@@ -921,7 +939,8 @@ int frame_constants(int32_t box_type, const double *box, double r_max, int32_t n
 }
 
 int zero_u64(uint64_t *p, int64_t n, hipStream_t st) {
-  return launch_zero(p, n, nullptr, st) == hipSuccess ? DH_OK : DH_EDEVICE;
+  return launch_zero(p, n, nullptr, 0, nullptr, nullptr, 0, st) == hipSuccess ? DH_OK
+                                                                           : DH_EDEVICE;
 }
 
 size_t ctx_device_bytes(const dh_ctx *ctx) {
@@ -938,6 +957,7 @@ void ctx_release_scratch(dh_ctx *ctx) {
     *bufs[k] = nullptr;
     *caps[k] = 0;
   }
+  ctx->blob_last.clear();
   (void)hipGetLastError();
 }
 

@@ -54,7 +54,7 @@ struct FrameParams {
   const uint64_t *pairs;  // pairs per histogram [H] (device)
   int64_t n_points;
   int32_t n_hist;
-  int32_t pad0_;
+  int32_t oor_by_flush;  // 1: oor starts at pairs and every flush subtracts its counts
   int32_t n_bins;
   int32_t box;         // BoxKind
   int32_t win;         // bin window of one sweep (<= n_bins)
@@ -102,7 +102,10 @@ struct KernelConfig {
 // host-side launchers (dh_kernels.hip)
 hipError_t launch_stage(int precision, int box_kind, const double *in, void *out, int64_t n,
                         const FrameParams &fp, hipStream_t st);
-hipError_t launch_zero(uint64_t *out, int64_t n_words, int32_t *counter, hipStream_t st);
+// zeroes out[n_words] and counters[n_counters]; with oor, sets oor[h] =
+// pairs[h] for h < n_hist (the flushes then subtract the in-range counts)
+hipError_t launch_zero(uint64_t *out, int64_t n_words, int32_t *counters, int32_t n_counters,
+                       uint64_t *oor, const uint64_t *pairs, int32_t n_hist, hipStream_t st);
 hipError_t launch_pairs(int precision, int box_kind, int mode, const KernelConfig &cfg,
                         const PairKernelArgs &args, int grid, size_t lds_bytes, hipStream_t st);
 hipError_t launch_oor(const uint64_t *hist, int32_t n_hist, int32_t n_bins, const uint64_t *pairs,

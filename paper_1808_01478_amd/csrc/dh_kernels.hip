@@ -482,6 +482,7 @@ __device__ __forceinline__ void flush_hist(uint32_t *hist, const PairKernelArgs 
   // the whole stride: slots past the window may hold counts of out-of-range
   // pairs of unclamped items, and the next frame may use a wider window
   const int clear = a.stride;
+  uint64_t in_range = 0;
   for (int b = threadIdx.x; b < clear; b += blockDim.x) {
     uint64_t v = 0;
     // bin 0 also takes the guard words below the histogram (binary32 bin -1)
@@ -490,9 +491,19 @@ __device__ __forceinline__ void flush_hist(uint32_t *hist, const PairKernelArgs 
       v += p[c];
       p[c] = 0u;
     }
-    if (b < count && v != 0)
+    if (b < count && v != 0) {
       atomicAdd(reinterpret_cast<unsigned long long *>(out + b),
                 static_cast<unsigned long long>(v));
+      in_range += v;
+    }
+  }
+  if (uni(F->oor_by_flush)) {
+    // the out-of-range count is the pair count less every flushed count: one
+    // subtraction per wave
+    for (int o = 32; o > 0; o >>= 1) in_range += __shfl_xor(in_range, o);
+    if ((threadIdx.x & 63) == 0 && in_range != 0)
+      atomicAdd(reinterpret_cast<unsigned long long *>(F->oor + hist_idx),
+                0ull - static_cast<unsigned long long>(in_range));
   }
 }
 
@@ -896,10 +907,14 @@ __global__ __launch_bounds__(max_threads<BOX>()) void pairs_kernel(PairKernelArg
 // Small kernels
 // --------------------------------------------------------------------------
 
-__global__ void zero_kernel(uint64_t *__restrict__ out, int64_t n, int32_t *counter) {
+__global__ void zero_kernel(uint64_t *__restrict__ out, int64_t n, int32_t *counters,
+                            int32_t n_counters, uint64_t *oor, const uint64_t *pairs,
+                            int32_t n_hist) {
   const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
   const int64_t i0 = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (i0 == 0 && counter) *counter = 0;
+  for (int64_t i = i0; i < n_counters; i += step) counters[i] = 0;
+  if (oor)
+    for (int64_t i = i0; i < n_hist; i += step) oor[i] = pairs[i];
   for (int64_t i = i0; i < n; i += step) out[i] = 0ull;
 }
 
@@ -996,10 +1011,12 @@ hipError_t launch_stage(int precision, int box_kind, const double *in, void *out
   return hipGetLastError();
 }
 
-hipError_t launch_zero(uint64_t *out, int64_t n_words, int32_t *counter, hipStream_t st) {
+hipError_t launch_zero(uint64_t *out, int64_t n_words, int32_t *counters, int32_t n_counters,
+                       uint64_t *oor, const uint64_t *pairs, int32_t n_hist, hipStream_t st) {
   const int threads = 256;
-  zero_kernel<<<grid_for(n_words > 0 ? n_words : 1, threads), threads, 0, st>>>(out, n_words,
-                                                                               counter);
+  const int64_t n = std::max<int64_t>({n_words, n_counters, oor ? n_hist : 0, 1});
+  zero_kernel<<<grid_for(n, threads), threads, 0, st>>>(out, n_words, counters, n_counters, oor,
+                                                        pairs, n_hist);
   return hipGetLastError();
 }
 
