@@ -270,11 +270,11 @@ constexpr int kNumKnobs = 8;
 
 // Bin windows from which the global-atomic kernel replaces LDS windows when
 // no tuned shape says otherwise. Measured on MI355X (100k points, periodic
-// cube, half the pairs in range): a binary32 window pass costs about 2.2 ms
+// cube, half the pairs in range): a binary32 window pass costs about 1.75 ms
 // and a binary64 one about 5.5 ms, while uint64 global atomics run at about
 // 2.4e10 per second whatever the bin count, so global atomics pay off from
-// about 50 windows (binary32) and 20 windows (binary64).
-constexpr int32_t kWideDefault32 = 48;
+// about 63 windows (binary32) and 20 windows (binary64).
+constexpr int32_t kWideDefault32 = 60;
 constexpr int32_t kWideDefault64 = 20;
 
 struct Knobs {

@@ -538,14 +538,19 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
   const uint32_t shift_bytes = static_cast<uint32_t>(log_copies + 2);
   char *const my_bytes = reinterpret_cast<char *>(my);
   // binary32 counts address LDS as 32-bit integers: this lane's copy of bin 0,
-  // less the bin-bit offset (the wrap-around is intended)
+  // less the offset of the index that is shifted in (the wrap-around is
+  // intended): the bin bits for one LDS histogram; for bin windows the slot
+  // of the window, where window 0 starts at bin -1 (slot 0 is the guard word)
   using LdsU32 = __attribute__((address_space(3))) uint32_t;
   const uint32_t my_lds =
       static_cast<uint32_t>(reinterpret_cast<uintptr_t>((LdsU32 *)my));
-  uint32_t my_lds_m = my_lds - (kMagicBits << shift_bytes);
-  // opaque, so the compiler keeps (bits << shift) + my_lds_m as one
+  const uint32_t s0 = w.sweep == 0 ? 1u : 0u;
+  uint32_t my_lds_m = SWEEP ? my_lds - (s0 << shift_bytes) : my_lds - (kMagicBits << shift_bytes);
+  // opaque, so the compiler keeps (index << shift) + my_lds_m as one
   // v_lshl_add_u32 instead of subtracting the offset from every bin
   asm volatile("" : "+v"(my_lds_m));
+  // bin bits of slot 0 of this window
+  const uint32_t sweep_base = kMagicBits + static_cast<uint32_t>(b_lo) - s0;
   // canonical once here, so fmin below needs no per-pair canonicalisation
   const double cap64 = __builtin_canonicalize(static_cast<double>(a.stride - 1));
 
@@ -615,9 +620,11 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
           const uint32_t lb = l == 0u ? kMagicBits - 1u : kMagicBits + hi;
           m = med3_u32(b, lb, kMagicBits + hi);
         } else {
-          // bins below the window wrap to large values and are discarded
-          const uint32_t u = max(b, kMagicBits) - (kMagicBits + static_cast<uint32_t>(b_lo));
-          m = med3_u32(u, l, hi) + kMagicBits;
+          // slot in the window; bins below it wrap to large values and are
+          // discarded with those above (window 0 has no bins below it: bin -1
+          // is its slot 0, the guard word)
+          const uint32_t hs = hi + s0;
+          m = med3_u32(b - sweep_base, l == 0u ? 0u : hs, hs);
         }
         __hip_atomic_fetch_add((LdsU32 *)(uintptr_t)(my_lds_m + (m << shift_bytes)), 1u,
                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
