@@ -161,7 +161,7 @@ const char *dh_ctx_last_error(const dh_ctx *ctx);
  *   offsets, box     host memory, read during the call only.
  *   d_out            device uint64 [H][n_bins], overwritten on `stream`.
  *   d_out_of_range   device uint64 [H] or NULL: pairs of each histogram
- *                    with t >= n_bins.
+ *                    in no bin (t >= n_bins; binary32 by its bin rule).
  * The work is enqueued on `stream` and the call returns without waiting.
  * Device coordinates are not checked for finiteness; non-finite input
  * yields meaningless counts but never out-of-bounds accesses.
@@ -177,7 +177,9 @@ int dh_histo_async(dh_ctx *ctx, dh_stream stream, const double *d_coords,
  * the given precision and box (Algorithm 1 without the increment): exactly
  * in binary64; in binary32 with periodic cells the pair kernel takes the c
  * differences of two i-particles from one 64-bit addition, which can lower
- * the second one by one fixed-point unit (2^-32 of the cell vector).
+ * the second one by one fixed-point unit (2^-32 of the cell vector), and in
+ * a cube it fuses the final scale with the bin offset, so the returned t is
+ * the unfused product.
  * For checking sampled pairs of frames too large for an exhaustive CPU
  * comparison.
  *   d_coords   device [n][3] binary64 (one species; n <= 2^31 - 1).
