@@ -335,9 +335,11 @@ int32_t dh_sched_select(const int64_t *need_bytes, const double *waited_s, const
  * scattered into thread-private histograms). Host memory only, no device.
  * Same arguments and outputs as dh_histo (out [H][n_bins] overwritten;
  * out_of_range [H] optional, may be NULL); n_threads = 0 uses the CPUs of
- * the process's affinity mask, at most OMP_NUM_THREADS when that is set. binary64 follows the canonical sequence (counts equal to
- * the GPU path's); binary32 rounds coordinates and constants once and runs
- * the same sequence in binary32. DH_EINVAL as dh_histo.
+ * the process's affinity mask, at most OMP_NUM_THREADS when that is set.
+ * binary64 follows the canonical sequence (counts equal to the GPU path's);
+ * binary32 rounds coordinates and constants once and runs the same sequence
+ * in binary32, with bin floor(t) (the device's binary32 bin rule differs
+ * from it only at integer t). DH_EINVAL as dh_histo.
  */
 int dh_cpu_histo(const double *coords, const int64_t *species_offsets, int32_t n_species,
                  int32_t box_type, const double *box, double r_max, int32_t n_bins,
