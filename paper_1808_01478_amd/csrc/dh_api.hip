@@ -209,6 +209,9 @@ int frame_consts(int32_t box_type, const double *box, double r_max, int32_t n_bi
     }
     constexpr double kTwo32 = 4294967296.0;
     for (int c = 0; c < 3; ++c) fp.k32[c] = static_cast<float>(fp.L[c] * fp.s / kTwo32);
+    if (fp.L[0] > 0)
+      for (int c = 0; c < 2; ++c)
+        fp.ryz32[c] = static_cast<float>((fp.L[c + 1] / fp.L[0]) * (fp.L[c + 1] / fp.L[0]));
     const double B[6] = {fp.ax, fp.bx, fp.by, fp.cx, fp.cy, fp.cz};
     for (int c = 0; c < 6; ++c) fp.Bk[c] = static_cast<float>(B[c] * fp.s / kTwo32);
     for (int q = 0; q < kShifts; ++q)

@@ -65,6 +65,7 @@ struct FrameParams {
   double h11, h12, h13, h22, h23, h33;
   double shift64[kShifts][3];
   float k32[3];        // orthorhombic: L_c * s / 2^32 (cube: k32[0])
+  float ryz32[2];      // orthorhombic: (L_y / L_x)^2, (L_z / L_x)^2
   float Bk[6];         // ax bx by cx cy cz, times s / 2^32
   float shift32[kShifts][3];  // image shifts times s
   int32_t noclamp;     // 1: every t of a full block fits below `stride` slots

@@ -172,6 +172,7 @@ __device__ __forceinline__ double t64(double xi, double yi, double zi, double xj
 // float and applying the cell matrix scaled by s / 2^32 gives t units.
 struct Geo32 {
   float kx, ky, kz;                 // orthorhombic: L_c * s / 2^32
+  float ry, rz;                     // orthorhombic: (L_y / L_x)^2, (L_z / L_x)^2
   float ax, bx, by, cx, cy, cz;     // triclinic: cell matrix * s / 2^32
   const float (*shift)[3];          // image shifts * s
 };
@@ -179,6 +180,7 @@ struct Geo32 {
 __device__ __forceinline__ Geo32 load_geo32(const FrameParams *F) {
   Geo32 g;
   g.kx = uni(F->k32[0]); g.ky = uni(F->k32[1]); g.kz = uni(F->k32[2]);
+  g.ry = uni(F->ryz32[0]); g.rz = uni(F->ryz32[1]);
   g.ax = uni(F->Bk[0]); g.bx = uni(F->Bk[1]); g.by = uni(F->Bk[2]);
   g.cx = uni(F->Bk[3]); g.cy = uni(F->Bk[4]); g.cz = uni(F->Bk[5]);
   g.shift = F->shift32;
@@ -289,8 +291,9 @@ __device__ __forceinline__ float t32_packed_c(uint64_t ab_j, uint64_t neg_ab_i, 
     if constexpr (BOX == kBoxCube) {
       return __builtin_amdgcn_sqrtf(fmaf(fc, fc, fmaf(fb, fb, fa * fa))) * g.kx;
     } else if constexpr (BOX == kBoxOrtho) {
-      const float dx = fa * g.kx, dy = fb * g.ky, dz = fc * g.kz;
-      return __builtin_amdgcn_sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+      // q / kx^2, the y and z squares weighted by (L_y/L_x)^2 and (L_z/L_x)^2
+      const float q = fmaf(fc * g.rz, fc, fmaf(fb * g.ry, fb, fa * fa));
+      return __builtin_amdgcn_sqrtf(q) * g.kx;
     } else {
       const float dx = fmaf(g.cx, fc, fmaf(g.bx, fb, g.ax * fa));
       const float dy = fmaf(g.cy, fc, g.by * fb);
@@ -302,17 +305,21 @@ __device__ __forceinline__ float t32_packed_c(uint64_t ab_j, uint64_t neg_ab_i, 
   }
 }
 
-// Bin bits (see bin_bits32) of the same distance; in a cube the scale and
-// the offset are one fused multiply-add on the root.
+// Bin bits (see bin_bits32) of the same distance; in orthorhombic cells the
+// scale L_x * s / 2^32 and the offset are one fused multiply-add on the root.
 template <int BOX>
 __device__ __forceinline__ uint32_t bits32_packed_c(uint64_t ab_j, uint64_t neg_ab_i, float fc,
                                                     const Geo32 &g) {
-  if constexpr (BOX == kBoxCube) {
+  if constexpr (BOX == kBoxCube || BOX == kBoxOrtho) {
     const uint64_t dab = ab_j + neg_ab_i;
     const float fa = static_cast<float>(static_cast<int32_t>(static_cast<uint32_t>(dab)));
     const float fb = static_cast<float>(static_cast<int32_t>(static_cast<uint32_t>(dab >> 32)));
-    const float r = __builtin_amdgcn_sqrtf(fmaf(fc, fc, fmaf(fb, fb, fa * fa)));
-    return __float_as_uint(fmaf(r, g.kx, kMagic32));
+    float q;
+    if constexpr (BOX == kBoxCube)
+      q = fmaf(fc, fc, fmaf(fb, fb, fa * fa));
+    else
+      q = fmaf(fc * g.rz, fc, fmaf(fb * g.ry, fb, fa * fa));
+    return __float_as_uint(fmaf(__builtin_amdgcn_sqrtf(q), g.kx, kMagic32));
   } else {
     return bin_bits32(t32_packed_c<BOX>(ab_j, neg_ab_i, fc, g));
   }
