@@ -214,6 +214,8 @@ int frame_consts(int32_t box_type, const double *box, double r_max, int32_t n_bi
         fp.ryz32[c] = static_cast<float>((fp.L[c + 1] / fp.L[0]) * (fp.L[c + 1] / fp.L[0]));
     const double B[6] = {fp.ax, fp.bx, fp.by, fp.cx, fp.cy, fp.cz};
     for (int c = 0; c < 6; ++c) fp.Bk[c] = static_cast<float>(B[c] * fp.s / kTwo32);
+    if (fp.ax > 0)
+      for (int c = 0; c < 5; ++c) fp.Bn[c] = static_cast<float>(B[c + 1] / fp.ax);
     for (int q = 0; q < kShifts; ++q)
       for (int c = 0; c < 3; ++c) fp.shift32[q][c] = static_cast<float>(fp.shift64[q][c] * fp.s);
     // A reduced vector shorter than half the shortest lattice vector lambda

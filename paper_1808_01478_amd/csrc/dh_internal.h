@@ -67,6 +67,7 @@ struct FrameParams {
   float k32[3];        // orthorhombic: L_c * s / 2^32 (cube: k32[0])
   float ryz32[2];      // orthorhombic: (L_y / L_x)^2, (L_z / L_x)^2
   float Bk[6];         // ax bx by cx cy cz, times s / 2^32
+  float Bn[5];         // bx by cx cy cz divided by ax
   float shift32[kShifts][3];  // image shifts times s
   int32_t noclamp;     // 1: every t of a full block fits below `stride` slots
   float qskip32;       // binary32 q (t units) below which no image is nearer

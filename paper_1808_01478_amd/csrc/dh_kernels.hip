@@ -174,6 +174,7 @@ struct Geo32 {
   float kx, ky, kz;                 // orthorhombic: L_c * s / 2^32
   float ry, rz;                     // orthorhombic: (L_y / L_x)^2, (L_z / L_x)^2
   float ax, bx, by, cx, cy, cz;     // triclinic: cell matrix * s / 2^32
+  float nbx, nby, ncx, ncy, ncz;    // triclinic: cell matrix / a_x
   const float (*shift)[3];          // image shifts * s
 };
 
@@ -183,6 +184,8 @@ __device__ __forceinline__ Geo32 load_geo32(const FrameParams *F) {
   g.ry = uni(F->ryz32[0]); g.rz = uni(F->ryz32[1]);
   g.ax = uni(F->Bk[0]); g.bx = uni(F->Bk[1]); g.by = uni(F->Bk[2]);
   g.cx = uni(F->Bk[3]); g.cy = uni(F->Bk[4]); g.cz = uni(F->Bk[5]);
+  g.nbx = uni(F->Bn[0]); g.nby = uni(F->Bn[1]); g.ncx = uni(F->Bn[2]);
+  g.ncy = uni(F->Bn[3]); g.ncz = uni(F->Bn[4]);
   g.shift = F->shift32;
   return g;
 }
@@ -294,6 +297,12 @@ __device__ __forceinline__ float t32_packed_c(uint64_t ab_j, uint64_t neg_ab_i, 
       // q / kx^2, the y and z squares weighted by (L_y/L_x)^2 and (L_z/L_x)^2
       const float q = fmaf(fc * g.rz, fc, fmaf(fb * g.ry, fb, fa * fa));
       return __builtin_amdgcn_sqrtf(q) * g.kx;
+    } else if constexpr (BOX == kBoxTric) {
+      // d / (a_x s 2^-32): the cell matrix divided by a_x
+      const float dx = fmaf(g.ncx, fc, fmaf(g.nbx, fb, fa));
+      const float dy = fmaf(g.ncy, fc, g.nby * fb);
+      const float dz = g.ncz * fc;
+      return __builtin_amdgcn_sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx))) * g.ax;
     } else {
       const float dx = fmaf(g.cx, fc, fmaf(g.bx, fb, g.ax * fa));
       const float dy = fmaf(g.cy, fc, g.by * fb);
@@ -305,21 +314,31 @@ __device__ __forceinline__ float t32_packed_c(uint64_t ab_j, uint64_t neg_ab_i, 
   }
 }
 
-// Bin bits (see bin_bits32) of the same distance; in orthorhombic cells the
-// scale L_x * s / 2^32 and the offset are one fused multiply-add on the root.
+// Bin bits (see bin_bits32) of the same distance; without the image search
+// the scale (L_x or a_x times s / 2^32) and the offset are one fused
+// multiply-add on the root.
 template <int BOX>
 __device__ __forceinline__ uint32_t bits32_packed_c(uint64_t ab_j, uint64_t neg_ab_i, float fc,
                                                     const Geo32 &g) {
-  if constexpr (BOX == kBoxCube || BOX == kBoxOrtho) {
+  if constexpr (BOX == kBoxCube || BOX == kBoxOrtho || BOX == kBoxTric) {
     const uint64_t dab = ab_j + neg_ab_i;
     const float fa = static_cast<float>(static_cast<int32_t>(static_cast<uint32_t>(dab)));
     const float fb = static_cast<float>(static_cast<int32_t>(static_cast<uint32_t>(dab >> 32)));
-    float q;
-    if constexpr (BOX == kBoxCube)
+    float q, k;
+    if constexpr (BOX == kBoxCube) {
       q = fmaf(fc, fc, fmaf(fb, fb, fa * fa));
-    else
+      k = g.kx;
+    } else if constexpr (BOX == kBoxOrtho) {
       q = fmaf(fc * g.rz, fc, fmaf(fb * g.ry, fb, fa * fa));
-    return __float_as_uint(fmaf(__builtin_amdgcn_sqrtf(q), g.kx, kMagic32));
+      k = g.kx;
+    } else {
+      const float dx = fmaf(g.ncx, fc, fmaf(g.nbx, fb, fa));
+      const float dy = fmaf(g.ncy, fc, g.nby * fb);
+      const float dz = g.ncz * fc;
+      q = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+      k = g.ax;
+    }
+    return __float_as_uint(fmaf(__builtin_amdgcn_sqrtf(q), k, kMagic32));
   } else {
     return bin_bits32(t32_packed_c<BOX>(ab_j, neg_ab_i, fc, g));
   }
