@@ -249,9 +249,9 @@ void dh_batch_destroy(dh_batch *batch);
  * job's device footprint fits the HBM budget (see dh_sched_select for the
  * order), copies the admitted job's frame to the device and stages it. The
  * job's pair kernel is cut into launches of a bounded pair count, and the
- * same thread paces them onto the device: one launch runs while the next
- * waits behind it, and each launch comes from the admitted job with the
- * least work left (shortest remaining work first), so a small job that
+ * same thread paces them onto the device one at a time, each from the
+ * admitted job with the least work left (shortest remaining work first),
+ * so a small job that
  * arrives while a huge one runs is computed at the huge job's next launch
  * boundary instead of after it. DH_SCHED_ARRIVAL selects arrival order for
  * both admission and launches instead. Completion is detected with events.

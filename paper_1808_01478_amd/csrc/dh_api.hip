@@ -669,7 +669,6 @@ int run_frame(dh_ctx *ctx, hipStream_t st, const FrameJob &job, const Knobs &k, 
   std::vector<WorkItem> items;
   std::vector<uint64_t> pairs;
   plan_frame(0, job.offsets, job.n_species, L, items, pairs);
-  refine_tail(items, L.grid, L.cfg.tj);
   std::vector<size_t> cuts(1, 0);
   if (limit > 0 && work > limit) {
     uint64_t acc = 0;
@@ -683,6 +682,20 @@ int run_frame(dh_ctx *ctx, hipStream_t st, const FrameJob &job, const Knobs &k, 
     }
   }
   cuts.push_back(items.size());
+  // every launch drains its own list: refine the tail of each
+  {
+    std::vector<WorkItem> all, seg;
+    std::vector<size_t> at(1, 0);
+    for (size_t c = 0; c + 1 < cuts.size(); ++c) {
+      seg.assign(items.begin() + static_cast<std::ptrdiff_t>(cuts[c]),
+                 items.begin() + static_cast<std::ptrdiff_t>(cuts[c + 1]));
+      refine_tail(seg, L.grid, L.cfg.tj);
+      all.insert(all.end(), seg.begin(), seg.end());
+      at.push_back(all.size());
+    }
+    items.swap(all);
+    cuts.swap(at);
+  }
   const size_t n_launches = cuts.size() - 1;
   fp.coords = ctx->d_staged;
   fp.out = job.d_out;
