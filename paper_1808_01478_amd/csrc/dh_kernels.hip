@@ -577,7 +577,8 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
   asm volatile("" : "+v"(my_lds_m));
   // bin bits of slot 0 of this window
   const uint32_t sweep_base = kMagicBits + static_cast<uint32_t>(b_lo) - s0;
-  // canonical once here, so fmin below needs no per-pair canonicalisation
+  // largest slot index of binary64 unclamped items (fmin's operands must be
+  // canonical; the compiler may still re-canonicalise it in the loop)
   const double cap64 = __builtin_canonicalize(static_cast<double>(a.stride - 1));
 
   // i-particles: wave w holds [wbase, wbase + 64R), lane l the R values
