@@ -979,17 +979,22 @@ void ctx_release_scratch(dh_ctx *ctx) {
   (void)hipGetLastError();
 }
 
-size_t job_scratch_bytes(int64_t n_points, int32_t n_hist, int32_t n_bins, int32_t precision) {
+size_t job_scratch_bytes(int64_t n_points, int32_t n_hist, int32_t n_bins, int32_t precision,
+                         int64_t launch_pairs) {
   // staged coordinates plus the work blob (frame constants, pair counts and
   // work items: a few MB, plus one item per kMinItemPairs pairs of every bin
-  // window when the frame runs as bounded launches; at least 9,000 bins fit
-  // one window, and beyond 64 windows the global-atomic mode needs one pass)
+  // window when the frame runs as bounded launches, and the tail pieces of
+  // every launch, at most three more items per workgroup of a grid of at
+  // most 2,048; at least 9,000 bins fit one window, and beyond 64 windows
+  // the global-atomic mode needs one pass)
   const uint64_t n = static_cast<uint64_t>(std::max<int64_t>(1, n_points));
   const uint64_t windows = std::min<uint64_t>(64, (static_cast<uint64_t>(n_bins) + 8999) / 9000);
   const uint64_t work = n * (n - 1) / 2 * windows;
+  const uint64_t launches =
+      launch_pairs > 0 ? work / static_cast<uint64_t>(launch_pairs) + 1 : 1;
   return static_cast<size_t>(n) * coord_bytes(precision) + (4u << 20) +
          static_cast<size_t>(n_hist) * 8 +
-         static_cast<size_t>(work / kMinItemPairs) * sizeof(WorkItem);
+         static_cast<size_t>(work / kMinItemPairs + launches * 3 * 2048) * sizeof(WorkItem);
 }
 
 }  // namespace dh

@@ -135,7 +135,9 @@ size_t ctx_device_bytes(const dh_ctx *ctx);
 // frees a context's scratch (the context must be idle); it regrows on use
 void ctx_release_scratch(dh_ctx *ctx);
 // device footprint of a single-frame job besides the caller's buffers
-size_t job_scratch_bytes(int64_t n_points, int32_t n_hist, int32_t n_bins, int32_t precision);
+// (launch_pairs: the bounded launch size the job runs with, 0 = one launch)
+size_t job_scratch_bytes(int64_t n_points, int32_t n_hist, int32_t n_bins, int32_t precision,
+                         int64_t launch_pairs);
 // binary64 constants of a frame (s, inverse cell, shifts, box kind; returns
 // the kind: none, ortho, triclinic, triclinic with image search)
 int frame_constants(int32_t box_type, const double *box, double r_max, int32_t n_bins,

@@ -454,7 +454,8 @@ int dh_server_submit(dh_server *s, const double *coords, const int64_t *offsets,
   j->work = 0.5 * static_cast<double>(n) * static_cast<double>(n > 0 ? n - 1 : 0);
   j->need = static_cast<int64_t>(std::max<int64_t>(1, n) * 3 * sizeof(double) +
                                  static_cast<size_t>(j->n_hist) * n_bins * sizeof(uint64_t) +
-                                 dh::job_scratch_bytes(n, j->n_hist, n_bins, precision));
+                                 dh::job_scratch_bytes(n, j->n_hist, n_bins, precision,
+                                                       kServeLaunchPairs));
   if (j->need > s->budget) return DH_EBUDGET;
   j->coords.assign(coords, coords + 3 * n);
   j->offsets.assign(offsets, offsets + n_species + 1);

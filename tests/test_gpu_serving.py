@@ -63,8 +63,9 @@ def test_budget_back_pressure():
     def footprint(f, p):
         windows = min(64, (f.n_bins + 8999) // 9000)
         work = f.n * (f.n - 1) // 2 * windows
+        launches = work // (3 << 33) + 1
         return (f.n * 24 + f.n_hist * f.n_bins * 8 + f.n * (32 if p else 16) + (4 << 20)
-                + f.n_hist * 8 + (work >> 21) * 32)
+                + f.n_hist * 8 + ((work >> 21) + launches * 3 * 2048) * 32)
     sizes = [footprint(f, p) for f, p in jobs]
     budget = int(max(sizes) * 1.2)
     with dh.Server(0, hbm_budget_bytes=budget, max_inflight=4, head_wait_limit_s=0.05) as srv:
