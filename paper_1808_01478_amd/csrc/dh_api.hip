@@ -52,7 +52,8 @@ struct dh_ctx {
   // pairs per pair-kernel launch at most (0: one launch per frame)
   uint64_t launch_pairs = 0;
   // stepped job: pair-kernel launches held back for dh::step_job, then the
-  // closing out-of-range pass
+  // closing out-of-range pass (global-atomic launches only; LDS launches
+  // count out-of-range pairs in their flushes)
   struct HeldLaunch {
     int precision, kind, mode;
     KernelConfig cfg;
@@ -724,7 +725,8 @@ int run_frame(dh_ctx *ctx, hipStream_t st, const FrameJob &job, const Knobs &k, 
   }
   if (e0) DH_HIP(ctx, hipEventRecord(e0, st));
   for (size_t c = 0; c < n_launches && !items.empty(); ++c) {
-    // every launch has its own work counter (zeroed with the blob upload)
+    // every launch has its own work counter (zeroed by the upload or, for a
+    // reused blob, by the zero kernel)
     PairKernelArgs a;
     a.frames = reinterpret_cast<const FrameParams *>(db + lay.frames);
     a.items = reinterpret_cast<const WorkItem *>(db + lay.items) + cuts[c];

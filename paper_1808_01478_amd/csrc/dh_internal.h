@@ -156,7 +156,7 @@ int histo_job(dh_ctx *ctx, hipStream_t stream, const double *d_coords, const int
 // A stepped job (histo_job with stepped set) enqueues staging and zeroing
 // only and holds its pair-kernel launches back in the context; step_job
 // enqueues the next one on st, or, when none is left, the closing
-// out-of-range pass (*done then becomes true). *pairs_left receives the
+// out-of-range pass if the job needs one (*done then becomes true). *pairs_left receives the
 // pairs of the launches still held back. The context runs nothing else
 // until the job is done.
 int step_job(dh_ctx *ctx, hipStream_t st, uint64_t *pairs_left, bool *done);

@@ -259,7 +259,7 @@ bool goes_first(const dh_server *s, const Slot &a, const Slot &b) {
 
 // Retires finished launches, then issues held launches while the pairs on
 // the device stay within kInflightPairs (one launch at least), each from the
-// job that goes first; a job with none left gets its closing pass, copies
+// job that goes first; a job with none left gets its closing step, copies
 // and completion event. Scheduler thread, outside the lock.
 void dispatch(dh_server *s) {
   for (auto it = s->inflight.begin(); it != s->inflight.end();) {
