@@ -61,3 +61,24 @@ def test_triclinic1m_full(ctx):
     l1_sub = np.abs(s32.astype(np.int64) - s64.astype(np.int64)).sum() / max(1, s64.sum())
     e_sub = ref.edges.sum() / max(1, ref.hist.sum())
     assert l1_full <= 2 * e_sub + 1e-9, (l1_full, l1_sub, e_sub)
+    # sampled pairs of the full frame, one by one: binary64 scaled distances
+    # equal to the oracle's, binary32 within the edge window
+    import torch
+    print("[case] triclinic1M sampled pairs", flush=True)
+    rng = np.random.Generator(np.random.PCG64(41))
+    m = 200_000
+    pi = rng.integers(0, fr.n, size=m)
+    pj = rng.integers(0, fr.n, size=m)
+    t_ref = oracle.pair_t(fr.coords, fr.box_type, fr.box, fr.r_max, fr.n_bins, pi, pj)
+    dev = torch.device("cuda")
+    x = torch.from_numpy(fr.coords).to(dev)
+    dpi = torch.from_numpy(pi.astype(np.int32)).to(dev)
+    dpj = torch.from_numpy(pj.astype(np.int32)).to(dev)
+    t = torch.empty(m, dtype=torch.float64, device=dev)
+    ctx.pair_t_async(x, fr.box_type, fr.box, fr.r_max, fr.n_bins, 1, dpi, dpj, t)
+    torch.cuda.synchronize()
+    assert np.array_equal(t.cpu().numpy(), t_ref)
+    ctx.pair_t_async(x, fr.box_type, fr.box, fr.r_max, fr.n_bins, 0, dpi, dpj, t)
+    torch.cuda.synchronize()
+    win = oracle.edge_window(fr.coords, fr.box, fr.r_max) * fr.n_bins / fr.r_max
+    assert np.abs(t.cpu().numpy() - t_ref).max() <= win
