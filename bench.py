@@ -186,13 +186,8 @@ def bench_image_search(steps=3):
     4,000 bins."""
     import torch
     import paper_1808_01478_amd as dh
-    rng = np.random.Generator(np.random.PCG64(31))
-    shape = np.array([[10.0, 0, 0], [3.0, 9.5, 0], [-2.0, 3.5, 9.0]])
-    n = 200_000
-    box = shape * (n / workloads.DENSITY / abs(np.linalg.det(shape))) ** (1.0 / 3.0)
-    x = rng.uniform(0.0, 1.0, size=(n, 3)) @ box
-    offs = [0, 120_000, n]
-    r_max = 0.8 * workloads.min_width(box)
+    fr = workloads.image_search()
+    x, box, offs, r_max, n = fr.coords, fr.box, list(fr.offsets), fr.r_max, fr.n
     pairs = n * (n - 1) // 2
     out = {"workload": "image search: 200,000 uniform points in a skewed triclinic cell, "
                        "species 120,000/80,000, r_max = 0.8 of the smallest width, 4,000 bins",

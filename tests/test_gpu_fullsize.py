@@ -4,7 +4,10 @@ ortho100k (N=100,000, 2 species, 10,000 bins): binary64 bit-exact against the
 oracle over all 4,999,950,000 pairs, binary32 within the edge-pair bound.
 triclinic1M (N=1,000,000 clustered, 3 species, 20,000 bins): pair-count
 identity at full size, binary64 and binary32 histograms related by the bound
-computed from a seeded subset, and sampled pairs checked one by one."""
+computed from a seeded subset, and sampled pairs checked one by one.
+image search (N=200,000 in a skewed cell, r_max = 0.8 of the smallest width,
+the 27-image search running): pair-count identity, a subset against the
+oracle, sampled pairs one by one."""
 import numpy as np
 import pytest
 
@@ -67,6 +70,45 @@ def test_triclinic1m_full(ctx):
     print("[case] triclinic1M sampled pairs", flush=True)
     rng = np.random.Generator(np.random.PCG64(41))
     m = 200_000
+    pi = rng.integers(0, fr.n, size=m)
+    pj = rng.integers(0, fr.n, size=m)
+    t_ref = oracle.pair_t(fr.coords, fr.box_type, fr.box, fr.r_max, fr.n_bins, pi, pj)
+    dev = torch.device("cuda")
+    x = torch.from_numpy(fr.coords).to(dev)
+    dpi = torch.from_numpy(pi.astype(np.int32)).to(dev)
+    dpj = torch.from_numpy(pj.astype(np.int32)).to(dev)
+    t = torch.empty(m, dtype=torch.float64, device=dev)
+    ctx.pair_t_async(x, fr.box_type, fr.box, fr.r_max, fr.n_bins, 1, dpi, dpj, t)
+    torch.cuda.synchronize()
+    assert np.array_equal(t.cpu().numpy(), t_ref)
+    ctx.pair_t_async(x, fr.box_type, fr.box, fr.r_max, fr.n_bins, 0, dpi, dpj, t)
+    torch.cuda.synchronize()
+    win = oracle.edge_window(fr.coords, fr.box, fr.r_max) * fr.n_bins / fr.r_max
+    assert np.abs(t.cpu().numpy() - t_ref).max() <= win
+
+
+def test_image_search_full(ctx):
+    import torch
+    fr = workloads.image_search()
+    print("\n[case] image search 200k gpu", flush=True)
+    pairs = fr.hist_pairs()
+    h64, oor64 = run_gpu(ctx, fr, 1)
+    assert list(h64.sum(axis=1).astype(np.int64) + oor64.astype(np.int64)) == pairs
+    h32, oor32 = run_gpu(ctx, fr, 0)
+    assert list(h32.sum(axis=1).astype(np.int64) + oor32.astype(np.int64)) == pairs
+    # a 15,000-point subset in the same cell, r_max and bins, against the oracle
+    sub = fr.subset([9_000, 6_000])
+    print("[case] image search subset oracle", flush=True)
+    w = oracle.edge_window(sub.coords, sub.box, sub.r_max)
+    ref = oracle.frame_histogram(sub, edge_window=w)
+    s64, so64 = run_gpu(ctx, sub, 1)
+    assert np.array_equal(s64, ref.hist) and np.array_equal(so64, ref.out_of_range)
+    s32, _ = run_gpu(ctx, sub, 0)
+    assert not fp32_bound_violations(s32, ref.hist, ref.edges)
+    # sampled pairs of the full frame (searched images included), one by one
+    print("[case] image search sampled pairs", flush=True)
+    rng = np.random.Generator(np.random.PCG64(43))
+    m = 100_000
     pi = rng.integers(0, fr.n, size=m)
     pj = rng.integers(0, fr.n, size=m)
     t_ref = oracle.pair_t(fr.coords, fr.box_type, fr.box, fr.r_max, fr.n_bins, pi, pj)

@@ -233,6 +233,19 @@ class Job:
     job_id: int
 
 
+def image_search(n: int = 200_000, seed: int = 31) -> Frame:
+    """n uniform points (the bench density) in a skewed triclinic cell, the
+    first 60 % one species and the rest another, r_max = 0.8 of the smallest
+    cell width (so the 27-image search runs), 4,000 bins."""
+    rng = _rng(seed)
+    shape = np.array([[10.0, 0, 0], [3.0, 9.5, 0], [-2.0, 3.5, 9.0]])
+    box = shape * (n / DENSITY / abs(np.linalg.det(shape))) ** (1.0 / 3.0)
+    x = rng.uniform(0.0, 1.0, size=(n, 3)) @ box
+    na = (n * 3) // 5
+    return Frame(np.ascontiguousarray(x), _offsets([na, n - na]), BOX_TRICLINIC, box,
+                 0.8 * min_width(box), 4000, f"image-search-{n}")
+
+
 def serving_job(rng: np.random.Generator, job_id: int, arrival: float,
                 n_lo: float = 1e3, n_hi: float = 2e6,
                 bins=(1000, 10_000, 50_000)) -> Job:
