@@ -596,6 +596,12 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
     xi[r] = p.x; yi[r] = p.y; zi[r] = p.z;
     lo[r] = ok ? 0u : hi;
   }
+  // binary32 clamp bounds in bin bits: the guard word below bin 0 for a
+  // lane that counts, its discard slot for one that must not
+  const uint32_t hib = kMagicBits + hi;
+  uint32_t lob[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) lob[r] = lo[r] == 0u ? kMagicBits - 1u : hib;
   // -(b:a) of each i-particle for the packed periodic binary32 difference
   uint64_t nab[R];
 #pragma unroll
@@ -629,8 +635,10 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
 
   // Counts one pair: binary64 at scaled distance v = t, binary32 from its bin
   // bits v (bin_bits32). l: 0 for a pair that counts, the lane's discard slot
-  // for one that must not (the lower clamp).
-  auto count_t = [&](auto v, uint32_t l) {
+  // for one that must not (the lower clamp); lb: the same bound in bin bits
+  // for the binary32 LDS clamp (guard word or discard slot), passed by the
+  // caller so that a diagonal item selects it directly.
+  auto count_t = [&](auto v, uint32_t l, uint32_t lb) {
     if constexpr (sizeof(T) == 4) {
       const uint32_t b = v;
       if constexpr (GLOBAL) {
@@ -644,7 +652,6 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
           // the guard word below the histogram, added to bin 0 on flush
           m = b;
         } else if constexpr (!SWEEP) {
-          const uint32_t lb = l == 0u ? kMagicBits - 1u : kMagicBits + hi;
           m = med3_u32(b, lb, kMagicBits + hi);
         } else {
           // slot in the window; bins below it wrap to large values and are
@@ -715,9 +722,9 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
       T q = fmaT(e.z, e.z, fmaT(e.y, e.y, e.x * e.x));
       q = search_lds<T>(e.x, e.y, e.z, q, sh);
       if constexpr (sizeof(T) == 4)
-        count_t(bin_bits32(__builtin_amdgcn_sqrtf(q)), v ? 0u : hi);
+        count_t(bin_bits32(__builtin_amdgcn_sqrtf(q)), v ? 0u : hi, v ? kMagicBits - 1u : hib);
       else
-        count_t(sqrt_rn(q) * g.s, v ? 0u : hi);
+        count_t(sqrt_rn(q) * g.s, v ? 0u : hi, 0u);
       head += cnt;
       if (head >= cap) head -= cap;
       qn -= cnt;
@@ -764,10 +771,11 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
       auto pairs_of = [&](const J &pj, int j) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          uint32_t l = lo[r];
+          uint32_t l = lo[r], lb = lob[r];
           if constexpr (DIAG) {
             const bool up = j > wbase + r * 64 + lane;
             l = up ? l : hi;
+            lb = up ? lb : hib;
           }
           if constexpr (SEARCH) {
             T dx, dy, dz;
@@ -781,9 +789,9 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
             // are searched later; they must not count now
             const bool need = l == 0u && q0 >= qskip;
             if constexpr (sizeof(T) == 4)
-              count_t(bin_bits32(__builtin_amdgcn_sqrtf(q0)), need ? hi : l);
+              count_t(bin_bits32(__builtin_amdgcn_sqrtf(q0)), need ? hi : l, need ? hib : lb);
             else
-              count_t(sqrt_rn(q0) * g.s, need ? hi : l);
+              count_t(sqrt_rn(q0) * g.s, need ? hi : l, 0u);
             const uint64_t m = __builtin_amdgcn_ballot_w64(need);
             if (m != 0) {
               const int below = __builtin_amdgcn_mbcnt_hi(
@@ -803,11 +811,11 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
             const uint64_t dcc = pj.cc + nzz[r / 2];
             const float fc = static_cast<float>(static_cast<int32_t>(
                 static_cast<uint32_t>(r % 2 == 0 ? dcc : dcc >> 32)));
-            count_t(bits32_packed_c<BOX>(pj.ab, nab[r], fc, g), l);
+            count_t(bits32_packed_c<BOX>(pj.ab, nab[r], fc, g), l, lb);
           } else if constexpr (sizeof(T) == 4) {
-            count_t(bin_bits32(pair_t<T, BOX>(xi[r], yi[r], zi[r], pj.x, pj.y, pj.z, g)), l);
+            count_t(bin_bits32(pair_t<T, BOX>(xi[r], yi[r], zi[r], pj.x, pj.y, pj.z, g)), l, lb);
           } else {
-            count_t(pair_t<T, BOX>(xi[r], yi[r], zi[r], pj.x, pj.y, pj.z, g), l);
+            count_t(pair_t<T, BOX>(xi[r], yi[r], zi[r], pj.x, pj.y, pj.z, g), l, lb);
           }
         }
         if constexpr (SEARCH)
