@@ -87,6 +87,11 @@ def traffic_for(workload_name: str, precision: int, launches_bytes_alg: float):
         return None
 
 
+def progress(what: str):
+    """One line per bench section on stderr (stdout carries only the JSON line)."""
+    print(f"[bench] {what}", file=sys.stderr, flush=True)
+
+
 def time_path(ctx, frame, precision, steps, warmup):
     import torch
     dev = torch.device("cuda")
@@ -559,9 +564,11 @@ def main():
         if os.path.exists(DEFAULT_CACHE):
             os.environ.setdefault("DH_TUNE", str(dh.TUNE_CACHED))
             os.environ.setdefault("DH_TUNE_CACHE", DEFAULT_CACHE)
+    progress(f"{args.workload} binary32, {args.steps} steps")
     r32 = time_path(ctx, frame, dh.FP32, args.steps, max(1, args.warmup))
     shape32 = ctx.last_config()
     fp64_steps = args.fp64_steps if args.fp64_steps is not None else max(1, args.steps // 2)
+    progress(f"{args.workload} binary64, {fp64_steps} steps")
     r64 = time_path(ctx, frame, dh.FP64, fp64_steps, 1)
     shape64 = ctx.last_config()
 
@@ -618,21 +625,30 @@ def main():
         "cpu_baseline": None,
     }
     # PCIe-inclusive rate of the synchronous host-buffer entry point
+    progress("host buffers")
     line["host_buffers"] = time_host_buffers(frame, dh.FP32, max(1, args.steps // 4))
     if args.serving_jobs > 0:
+        progress(f"serving, {args.serving_jobs} jobs")
         line["serving"] = bench_serving(args.serving_jobs)
         line["latency_ms"]["serving_p50"] = line["serving"]["shortest_remaining_work"]["p50_ms"]
         line["latency_ms"]["serving_p99"] = line["serving"]["shortest_remaining_work"]["p99_ms"]
     if args.triclinic_steps > 0 and args.workload != "triclinic1M":
+        progress("triclinic1M")
         line["triclinic1M"] = bench_triclinic(ctx, args.triclinic_steps)
     if args.wide:
+        progress("wide histograms")
         line["wide"] = bench_wide(frame)
+        progress("image search")
         line["image_search"] = bench_image_search()
     if args.trajectory_frames > 0:
+        progress(f"trajectory, {args.trajectory_frames} frames")
         line["trajectory"] = bench_trajectory(ctx, args.trajectory_frames, max(1, args.steps // 5))
+        progress("trajectory file")
         line["trajectory_file"] = bench_trajectory_file(ctx)
     if not args.no_cpu_baseline:
+        progress("CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(frame)
+        progress("tuned CPU kernel")
         line["cpu_tuned"] = cpu_tuned(frame)
     ctx.close()
     del torch
