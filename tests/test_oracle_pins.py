@@ -86,3 +86,30 @@ def test_invalid_arguments(lib):
         oracle.histogram(fr.coords, fr.offsets, 1, bad, 3.0, 10)
     with pytest.raises(ValueError):
         oracle.histogram(fr.coords, [0, 5, 3], 1, fr.box, 3.0, 10)
+
+
+def test_edge_window_values():
+    """The binary32 tolerance window 4 ulp32(S), S = max(max |coordinate|,
+    max |box entry|, r_max): exact values on the three single-frame
+    workloads (S = 10*sqrt(3), 40 and about 75), and on crafted S at and
+    just below powers of two, against numpy's float32 spacing."""
+    assert oracle.edge_window(workloads.tiny().coords, None, 10.0 * np.sqrt(3.0)) == 7.62939453125e-06
+    fr = workloads.ortho(n=1000)
+    assert oracle.edge_window(fr.coords, fr.box, fr.r_max) == 1.52587890625e-05
+    fr = workloads.triclinic(n=20_000)
+    assert oracle.edge_window(fr.coords, fr.box, fr.r_max) == 3.0517578125e-05
+    pts = np.zeros((2, 3))
+    for e in (-3, 0, 4, 5, 9):
+        s = 2.0 ** e
+        below = np.nextafter(s, 0.0)
+        # S exactly 2^e: ulp32 is the spacing of float32 at 2^e
+        want = 4.0 * float(np.spacing(np.float32(s)))
+        assert oracle.edge_window(pts, None, s) == want
+        pts2 = pts.copy()
+        pts2[1, 2] = -s                       # |coordinate| sets S, sign ignored
+        assert oracle.edge_window(pts2, None, 0.5 * s) == want
+        box = np.diag([0.25 * s, s, 0.5 * s])  # box entry sets S
+        assert oracle.edge_window(pts, box, 0.125 * s) == want
+        # S just below 2^e lies in the binade below: half the window
+        assert oracle.edge_window(pts, None, below) == want / 2
+        assert oracle.edge_window(pts, None, below) == 4.0 * float(np.spacing(np.float32(s / 2)))
