@@ -109,17 +109,16 @@ constexpr int32_t kMaxBins = 1 << 24;
 constexpr int32_t kMaxBins32 = 1 << 22;
 constexpr int64_t kMaxN = 2147483647LL;
 
-// message of the last failure that had no context to hold it
-thread_local std::string t_last_error;
+// message of the last failure that had no context to hold it (a fixed
+// buffer: recording an error allocates nothing)
+thread_local char t_last_error[512];
 
 int fail(dh_ctx *ctx, int code, const char *fmt, ...) {
-  char buf[512];
   va_list ap;
   va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
+  vsnprintf(t_last_error, sizeof t_last_error, fmt, ap);
   va_end(ap);
-  t_last_error = buf;
-  if (ctx) ctx->last_error = buf;
+  if (ctx) ctx->last_error = t_last_error;
   return code;
 }
 
@@ -334,7 +333,7 @@ struct BaseConfig {
   bool noclamp;
 };
 
-BaseConfig base_config(const dh_ctx *ctx, int precision, const Knobs &k, int kind) {
+BaseConfig base_config(size_t lds_per_block, int precision, const Knobs &k, int kind) {
   BaseConfig b;
   KernelConfig &c = b.cfg;
   // the image-search kernels are built for at most 256 threads; "auto" is
@@ -351,7 +350,7 @@ BaseConfig base_config(const dh_ctx *ctx, int precision, const Knobs &k, int kin
   // the search kernels keep their queues after the histogram; counting them
   // with the tiles leaves the histogram budget below them
   if (kind == kBoxTricSearch) b.tile_bytes += search_queue_bytes(precision, c.threads, c.r);
-  const size_t budget = std::min<size_t>(ctx->lds_per_block, 160 * 1024) - b.tile_bytes - 256;
+  const size_t budget = std::min<size_t>(lds_per_block, 160 * 1024) - b.tile_bytes - 256;
   b.win_max = static_cast<int64_t>(budget / 4 / c.copies) - kDump;
   b.occ_cap = k.occ_cap;
   b.items_per_wg = k.items_per_wg;
@@ -387,18 +386,19 @@ void resolve_threads(int precision, int kind, int mode, const Knobs &k, size_t l
   cfg.threads = 1024;
 }
 
-int grid_for_config(const dh_ctx *ctx, int precision, int kind, int mode, const BaseConfig &b,
+int grid_for_config(int n_cu, int precision, int kind, int mode, const BaseConfig &b,
                     size_t lds, const KernelConfig &cfg) {
   int occ = pairs_occupancy(precision, kind, mode, cfg, lds);
   if (b.occ_cap > 0) occ = std::min(occ, b.occ_cap);
-  return ctx->n_cu * std::max(1, occ);
+  return n_cu * std::max(1, occ);
 }
 
-// Launch shape for one frame.
-Launch choose_launch(const dh_ctx *ctx, int precision, const FrameParams &fp,
+// Launch shape for one frame on a device with n_cu compute units and
+// lds_per_block bytes of LDS per workgroup.
+Launch choose_launch(int n_cu, size_t lds_per_block, int precision, const FrameParams &fp,
                      uint64_t total_pairs, const Knobs &k) {
   Launch L;
-  const BaseConfig b = base_config(ctx, precision, k, fp.box);
+  const BaseConfig b = base_config(lds_per_block, precision, k, fp.box);
   L.cfg = b.cfg;
   const int32_t n_bins = fp.n_bins;
   if (n_bins <= b.win_max) {
@@ -416,7 +416,7 @@ Launch choose_launch(const dh_ctx *ctx, int precision, const FrameParams &fp,
     L.stride = 0;
     L.lds = b.tile_bytes;
     resolve_threads(precision, fp.box, L.mode, k, L.lds, L.cfg);
-    L.grid = grid_for_config(ctx, precision, fp.box, L.mode, b, L.lds, L.cfg);
+    L.grid = grid_for_config(n_cu, precision, fp.box, L.mode, b, L.lds, L.cfg);
     L.cfg.jchunk = jchunk_for(L.cfg, L.grid, total_pairs, b.items_per_wg);
     return L;
   }
@@ -436,60 +436,45 @@ Launch choose_launch(const dh_ctx *ctx, int precision, const FrameParams &fp,
   }
   L.lds = b.tile_bytes + static_cast<size_t>(L.cfg.copies) * L.stride * 4;
   resolve_threads(precision, fp.box, L.mode, k, L.lds, L.cfg);
-  L.grid = grid_for_config(ctx, precision, fp.box, L.mode, b, L.lds, L.cfg);
+  L.grid = grid_for_config(n_cu, precision, fp.box, L.mode, b, L.lds, L.cfg);
   L.cfg.jchunk = jchunk_for(L.cfg, L.grid, total_pairs * static_cast<uint64_t>(L.n_sweeps),
                             b.items_per_wg);
   return L;
 }
 
-// Work items of one frame, grouped by (histogram, sweep).
+Launch choose_launch(const dh_ctx *ctx, int precision, const FrameParams &fp,
+                     uint64_t total_pairs, const Knobs &k) {
+  return choose_launch(ctx->n_cu, ctx->lds_per_block, precision, fp, total_pairs, k);
+}
+
+// Work items of one frame, grouped by (histogram, sweep); the rows and items
+// of each histogram as hist_rows / emit_row cut them (shared with the
+// device-side planner).
 void plan_frame(int32_t frame, const int64_t *off, int32_t k, const Launch &L,
                 std::vector<WorkItem> &items, std::vector<uint64_t> &pairs) {
   const int64_t bi = static_cast<int64_t>(L.cfg.threads) * L.cfg.r;
   const int64_t jc = L.cfg.jchunk;
-  auto emit = [&](int32_t h, int64_t i0, int64_t i1, int64_t j0, int64_t j1, int32_t diag) {
-    WorkItem w;
-    w.frame = frame; w.hist = h; w.sweep = 0;
-    w.flags = (diag ? kItemDiag : 0) | (i1 - i0 == bi ? kItemFull : 0);
-    w.i0 = static_cast<int32_t>(i0); w.i1 = static_cast<int32_t>(i1);
-    w.j0 = static_cast<int32_t>(j0); w.j1 = static_cast<int32_t>(j1);
-    items.push_back(w);
-  };
-  int32_t h = 0;
-  auto plan_hist = [&](int32_t s, int32_t t) {
+  const int32_t n_hist = k * (k + 1) / 2;
+  for (int32_t h = 0; h < n_hist; ++h) {
+    const HistRows r = hist_rows(off, k, h);
+    pairs.push_back(r.pairs);
     const size_t first = items.size();
-    if (s == t) {
-      const int64_t base = off[s], n = off[s + 1] - off[s];
-      pairs.push_back(static_cast<uint64_t>(n) * static_cast<uint64_t>(n > 0 ? n - 1 : 0) / 2);
-      for (int64_t b0 = base; b0 < base + n; b0 += bi) {
-        const int64_t b1 = std::min(b0 + bi, base + n);
-        if (b1 - b0 >= 2) emit(h, b0, b1, b0, b1, 1);
-        for (int64_t j = b1; j < base + n; j += jc) emit(h, b0, b1, j, std::min(j + jc, base + n), 0);
-      }
-    } else {
-      const int64_t ns = off[s + 1] - off[s], nt = off[t + 1] - off[t];
-      pairs.push_back(static_cast<uint64_t>(ns) * static_cast<uint64_t>(nt));
-      // the larger species fills the lanes, the smaller one is streamed
-      const int32_t si = ns >= nt ? s : t, sj = ns >= nt ? t : s;
-      for (int64_t b0 = off[si]; b0 < off[si + 1]; b0 += bi) {
-        const int64_t b1 = std::min(b0 + bi, off[si + 1]);
-        for (int64_t j = off[sj]; j < off[sj + 1]; j += jc)
-          emit(h, b0, b1, j, std::min(j + jc, off[sj + 1]), 0);
-      }
+    const int64_t nr = hist_row_count(r, bi);
+    for (int64_t b = 0; b < nr; ++b) {
+      const size_t at = items.size();
+      items.resize(at + static_cast<size_t>(row_item_count(r, b, bi, jc)));
+      emit_row(r, h, 0, b, bi, jc, items.data() + at);
     }
-    // replicate for every bin window, keeping items grouped by (h, sweep)
     const size_t last = items.size();
+    for (size_t q = first; q < last; ++q) items[q].frame = frame;
+    // replicate for every bin window, keeping items grouped by (h, sweep)
     for (int32_t sw = 1; sw < L.n_sweeps; ++sw)
       for (size_t q = first; q < last; ++q) {
         WorkItem w = items[q];
         w.sweep = sw;
         items.push_back(w);
       }
-    ++h;
-  };
-  for (int32_t s = 0; s < k; ++s) plan_hist(s, s);
-  for (int32_t s = 0; s < k; ++s)
-    for (int32_t t = s + 1; t < k; ++t) plan_hist(s, t);
+  }
 }
 
 // Splits the last `grid` items of a work list (the ones workgroups take
@@ -953,6 +938,30 @@ namespace dh {
 
 int ctx_device(const dh_ctx *ctx) { return ctx->device; }
 
+LaunchPlan default_launch(int n_cu, size_t lds_per_block, int precision, const FrameParams &fp,
+                          uint64_t total_pairs) {
+  const Launch L = choose_launch(n_cu, lds_per_block, precision, fp, total_pairs,
+                                 default_knobs(precision));
+  LaunchPlan p;
+  p.cfg = L.cfg;
+  p.mode = L.mode;
+  p.win = L.win;
+  p.n_sweeps = L.n_sweeps;
+  p.stride = L.stride;
+  p.grid = L.grid;
+  p.noclamp = L.noclamp;
+  p.lds = L.lds;
+  return p;
+}
+
+int thread_fail(int code, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(t_last_error, sizeof t_last_error, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
 int frame_constants(int32_t box_type, const double *box, double r_max, int32_t n_bins,
                     FrameParams &fp) {
   return frame_consts(box_type, box, r_max, n_bins, fp);
@@ -1087,7 +1096,7 @@ void dh_ctx_destroy(dh_ctx *ctx) {
 }
 
 const char *dh_ctx_last_error(const dh_ctx *ctx) {
-  return ctx ? ctx->last_error.c_str() : t_last_error.c_str();
+  return ctx ? ctx->last_error.c_str() : t_last_error;
 }
 
 int dh_histo_async(dh_ctx *ctx, dh_stream stream, const double *d_coords, const int64_t *offsets,
@@ -1296,7 +1305,7 @@ int dh_batch_create(dh_ctx *ctx, const dh_frame_desc *frames, int32_t n_frames, 
   };
   std::vector<FrameInfo> info(n_frames);
   const Knobs bk = ctx->forced ? Knobs::unpack(ctx->forced_knobs) : default_knobs(precision);
-  const BaseConfig base = base_config(ctx, precision, bk, kBoxNone);
+  const BaseConfig base = base_config(ctx->lds_per_block, precision, bk, kBoxNone);
   for (int32_t f = 0; f < n_frames; ++f) {
     const dh_frame_desc &d = frames[f];
     int rc = check(nullptr, d.offsets, d.n_species, d.box_type, d.box, d.r_max, d.n_bins,
@@ -1359,7 +1368,7 @@ int dh_batch_create(dh_ctx *ctx, const dh_frame_desc *frames, int32_t n_frames, 
     dh_batch::Group g;
     g.kind = kv.first.first;
     g.mode = kv.first.second;
-    const BaseConfig gbase = base_config(ctx, precision, bk, g.kind);
+    const BaseConfig gbase = base_config(ctx->lds_per_block, precision, bk, g.kind);
     g.cfg = gbase.cfg;
     int64_t stride = 0;
     uint64_t work = 0;
@@ -1382,7 +1391,7 @@ int dh_batch_create(dh_ctx *ctx, const dh_frame_desc *frames, int32_t n_frames, 
     g.stride = static_cast<int>(stride);
     g.lds = gbase.tile_bytes + static_cast<size_t>(g.cfg.copies) * g.stride * 4;
     resolve_threads(precision, g.kind, g.mode, bk, g.lds, g.cfg);
-    g.grid = grid_for_config(ctx, precision, g.kind, g.mode, gbase, g.lds, g.cfg);
+    g.grid = grid_for_config(ctx->n_cu, precision, g.kind, g.mode, gbase, g.lds, g.cfg);
     g.cfg.jchunk = jchunk_for(g.cfg, g.grid, work, gbase.items_per_wg);
     // large frames first: the tail of the work list is made of small items
     std::stable_sort(fs.begin(), fs.end(),

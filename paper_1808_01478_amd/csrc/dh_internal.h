@@ -101,6 +101,92 @@ struct KernelConfig {
   int32_t wg_per_cu; // 0 = as many as fit
 };
 
+// Species pair (s, t) of histogram h among k species, in the library order:
+// (0,0), (1,1), ..., (k-1,k-1), then (s,t) for s < t lexicographically.
+__host__ __device__ inline void hist_pair(int32_t k, int32_t h, int32_t &s, int32_t &t) {
+  s = t = h;
+  if (h < k) return;
+  int32_t idx = h - k;
+  for (s = 0; s < k; ++s) {
+    const int32_t m = k - 1 - s;
+    if (idx < m) {
+      t = s + 1 + idx;
+      return;
+    }
+    idx -= m;
+  }
+}
+
+// How the work list of one histogram is cut (the host planner and the
+// device planner of the allocation-free entry point emit the same items):
+// rows are blocks of bi particles in the lanes; an intra-species row has a
+// diagonal item (when its block holds at least two particles) followed by
+// j-chunks of at most jc particles from the end of its block to the end of
+// the species; a cross-species row puts the larger species in the lanes and
+// streams the smaller one in j-chunks.
+struct HistRows {
+  int64_t lane0, lane1;  // particles in the lanes
+  int64_t str0, str1;    // particles streamed as j (cross-species)
+  bool intra;
+  uint64_t pairs;        // pairs of the histogram
+};
+
+__host__ __device__ inline HistRows hist_rows(const int64_t *off, int32_t k, int32_t h) {
+  int32_t s, t;
+  hist_pair(k, h, s, t);
+  HistRows r;
+  const int64_t ns = off[s + 1] - off[s], nt = off[t + 1] - off[t];
+  r.intra = s == t;
+  if (r.intra) {
+    r.lane0 = r.str0 = off[s];
+    r.lane1 = r.str1 = off[s + 1];
+    r.pairs = static_cast<uint64_t>(ns) * static_cast<uint64_t>(ns > 0 ? ns - 1 : 0) / 2;
+  } else {
+    const int32_t si = ns >= nt ? s : t, sj = ns >= nt ? t : s;
+    r.lane0 = off[si]; r.lane1 = off[si + 1];
+    r.str0 = off[sj]; r.str1 = off[sj + 1];
+    r.pairs = static_cast<uint64_t>(ns) * static_cast<uint64_t>(nt);
+  }
+  return r;
+}
+
+__host__ __device__ inline int64_t hist_row_count(const HistRows &r, int64_t bi) {
+  return (r.lane1 - r.lane0 + bi - 1) / bi;
+}
+
+__host__ __device__ inline int64_t row_item_count(const HistRows &r, int64_t row, int64_t bi,
+                                                  int64_t jc) {
+  const int64_t b0 = r.lane0 + row * bi;
+  const int64_t b1 = b0 + bi < r.lane1 ? b0 + bi : r.lane1;
+  if (r.intra) return (b1 - b0 >= 2 ? 1 : 0) + (r.lane1 - b1 + jc - 1) / jc;
+  return (r.str1 - r.str0 + jc - 1) / jc;
+}
+
+// Writes the items of one row (for bin window `sweep`) from dst on; returns
+// how many. Flags as in WorkItem.
+__host__ __device__ inline int64_t emit_row(const HistRows &r, int32_t h, int32_t sweep,
+                                            int64_t row, int64_t bi, int64_t jc,
+                                            WorkItem *dst) {
+  const int64_t b0 = r.lane0 + row * bi;
+  const int64_t b1 = b0 + bi < r.lane1 ? b0 + bi : r.lane1;
+  const int32_t full = b1 - b0 == bi ? kItemFull : 0;
+  int64_t n = 0;
+  auto put = [&](int64_t j0, int64_t j1, int32_t diag) {
+    WorkItem w;
+    w.frame = 0; w.hist = h; w.sweep = sweep; w.flags = diag | full;
+    w.i0 = static_cast<int32_t>(b0); w.i1 = static_cast<int32_t>(b1);
+    w.j0 = static_cast<int32_t>(j0); w.j1 = static_cast<int32_t>(j1);
+    dst[n++] = w;
+  };
+  if (r.intra) {
+    if (b1 - b0 >= 2) put(b0, b1, kItemDiag);
+    for (int64_t j = b1; j < r.lane1; j += jc) put(j, j + jc < r.lane1 ? j + jc : r.lane1, 0);
+  } else {
+    for (int64_t j = r.str0; j < r.str1; j += jc) put(j, j + jc < r.str1 ? j + jc : r.str1, 0);
+  }
+  return n;
+}
+
 // host-side launchers (dh_kernels.hip)
 hipError_t launch_stage(int precision, int box_kind, const double *in, void *out, int64_t n,
                         const FrameParams &fp, hipStream_t st);
@@ -144,6 +230,21 @@ int frame_constants(int32_t box_type, const double *box, double r_max, int32_t n
                     FrameParams &fp);
 // device ordinal of a context
 int ctx_device(const dh_ctx *ctx);
+// The launch shape a frame gets with the built-in default knobs (no tuning
+// cache) on a device with n_cu compute units and lds_per_block bytes of LDS
+// per workgroup; fp comes from frame_constants (box kind, n_bins).
+struct LaunchPlan {
+  KernelConfig cfg;
+  int32_t mode, win, n_sweeps, stride, grid;
+  bool noclamp;
+  size_t lds;
+};
+LaunchPlan default_launch(int n_cu, size_t lds_per_block, int precision, const FrameParams &fp,
+                          uint64_t total_pairs);
+// Records the message of a failure that has no context (read back by
+// dh_ctx_last_error(NULL); a fixed thread-local buffer, so it allocates
+// nothing) and returns code.
+int thread_fail(int code, const char *fmt, ...);
 // zeroes n words with a kernel on stream st (never a memset node in graphs)
 int zero_u64(uint64_t *p, int64_t n, hipStream_t st);
 // dh_histo_async with an accumulate option: when set, the frame's counts are

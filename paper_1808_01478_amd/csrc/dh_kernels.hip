@@ -80,29 +80,84 @@ __device__ __forceinline__ Geo64 load_geo64(const FrameParams *F) {
   return g;
 }
 
-// binary64 square root. Goldschmidt's coupled iteration for sqrt(q) and
-// 1/(2 sqrt(q)) started from v_rsq_f64, then two Newton corrections of the
-// root with exact fused residuals: the same sequence the compiler emits for
-// the library sqrt on this target. The last correction is accurate to about
-// 2^-44 ulp, so the result is the correctly rounded root except when sqrt(q)
-// lies within that distance of a rounding midpoint (it can come as close as
-// about 2^-57 ulp), a fraction of about 2^-44 of arguments; a count changes
-// only if that last-bit difference also moves t across a bin edge. The fast
-// path needs q normal and not tiny (no range scaling), so a wave in which any
-// lane has q < 2^-767, q = 0 or a NaN takes the library sqrt instead (the
-// same iteration on a scaled input).
-__device__ __forceinline__ double sqrt_rn(double q) {
-  if (__builtin_amdgcn_ballot_w64(!(q >= 0x1p-767)) != 0) return sqrt(q);
+// Correctly rounded binary64 square root (IEEE-754 sqrt) for every
+// argument. The candidate y comes from v_rsq_f64 refined by one Goldschmidt
+// step and two Newton corrections with fused residuals, which leaves y within
+// half an ulp plus a tiny fraction of sqrt(q): at most one ulp from the
+// correctly rounded root. Tuckerman's rounding test then settles the last
+// bit. With u = ulp(y) and the remainder r = q - y*y (one fma), sqrt(q) lies
+// above the midpoint y + u/2 iff r > u*y, and below the midpoint under y iff
+// r <= -u*y (-u*y/2 when y is a power of two, whose lower neighbour is only
+// u/2 away): q and y*y are multiples of u*u, so r is too, and the midpoint
+// conditions r < u*y + u*u/4 and r > -u*y + u*u/4 reduce to those
+// thresholds. The thresholds and the next multiples of u*u beyond them are
+// representable, so the comparisons are exact even where the fma rounds r.
+// Arguments below 2^-767 are scaled by 2^1024 (exactly) so that the
+// iteration and the remainder stay in the normal range, and the root is
+// scaled back by 2^-512; 0, +inf and NaN are returned as IEEE sqrt returns
+// them.
+__device__ __forceinline__ double sqrt_cr(double q) {
+  const bool tiny = q < 0x1p-767;
+  const double qs = tiny ? ldexp(q, 1024) : q;
+  const double y0 = __builtin_amdgcn_rsq(qs);
+  double g = qs * y0;
+  double h = 0.5 * y0;
+  const double e = fma(-h, g, 0.5);
+  h = fma(h, e, h);
+  g = fma(g, e, g);
+  double d = fma(-g, g, qs);
+  g = fma(d, h, g);
+  d = fma(-g, g, qs);
+  double y = fma(d, h, g);
+  const double r = fma(-y, y, qs);
+  const uint64_t yb = static_cast<uint64_t>(__double_as_longlong(y));
+  // y = f * 2^ex with f in [1/2, 1); y is normal here
+  const int ex = static_cast<int>((yb >> 52) & 0x7ff) - 1022;
+  const double uy = ldexp(y, ex - 53);  // ulp(y) * y, exact
+  const bool pow2 = (yb & 0xFFFFFFFFFFFFFull) == 0;
+  const double low = pow2 ? -0.5 * uy : -uy;
+  const uint64_t step = r > uy ? 1ull : (r <= low ? ~0ull : 0ull);
+  y = __longlong_as_double(static_cast<long long>(yb + step));
+  if (tiny) y = ldexp(y, -512);
+  if (qs > 0.0 && qs <= 0x1.fffffffffffffp+1023) return y;
+  return q == 0.0 ? q : (q > 0.0 ? q : __builtin_nan(""));
+}
+
+// The scaled distance t = sqrt(q) * s from a short root: v_rsq_f64 (relative
+// error at most 2^-23, the precision the ISA states for it) and one
+// Goldschmidt step give sqrt(q) within about 1.5 * 2^-46 relative, so this t
+// lies within 2^13 ulps of the canonical t (correctly rounded root times s).
+// It decides the bin whenever it is farther than 2^16 ulps from every
+// integer. The lanes where that is not certain are added to the wave mask
+// `near`: t within 2^16 ulps of an integer, and q below 2^-767, zero or NaN.
+// For t < 2^20 the integers are multiples of 2^32 ulps of t, so t is that
+// far from every integer when the low 32 bits of its encoding are at least
+// 2^16 away from a multiple of 2^32 (a conservative test: two integer
+// operations). Every t at or above 2^20 is out of range, as is the canonical
+// t, when n_bins < 2^20 - 2; with more bins the callers take the correctly
+// rounded root for every pair. A NaN t (q = +inf) counts out of range like
+// the canonical +inf.
+__device__ __forceinline__ double t_fast64(double q, double s, uint64_t &near) {
   const double y = __builtin_amdgcn_rsq(q);
   double g = q * y;
-  double h = 0.5 * y;
-  const double r = fma(-h, g, 0.5);
-  h = fma(h, r, h);
-  g = fma(g, r, g);
-  double d = fma(-g, g, q);
-  g = fma(d, h, g);
-  d = fma(-g, g, q);
-  return fma(d, h, g);
+  const double h = 0.5 * y;
+  const double e = fma(-h, g, 0.5);
+  g = fma(g, e, g);
+  const double t = g * s;
+  const uint32_t lo = static_cast<uint32_t>(__double_as_longlong(t)) + 0x10000u;
+  near |= __builtin_amdgcn_ballot_w64(!(q >= 0x1p-767));
+  near |= __builtin_amdgcn_ballot_w64(lo < 0x20000u);
+  return t;
+}
+
+// t with the canonical arithmetic for one pair: the short root, or, when any
+// lane of the wave needs it, the correctly rounded one (a uniform branch).
+// big_bins: n_bins >= 2^20 - 2 (always the correctly rounded root).
+__device__ __forceinline__ double t_guarded64(double q, double s, bool big_bins) {
+  uint64_t near = big_bins ? ~0ull : 0ull;
+  const double t = t_fast64(q, s, near);
+  if (__builtin_expect(near != 0, 0)) return sqrt_cr(q) * s;
+  return t;
 }
 
 // d = x_j - x_i reduced by the minimum-image rule of the box kind.
@@ -161,7 +216,16 @@ __device__ __forceinline__ double t64(double xi, double yi, double zi, double xj
   reduce64<BOX>(xi, yi, zi, xj, yj, zj, g, dx, dy, dz);
   double q = fma(dz, dz, fma(dy, dy, dx * dx));
   if constexpr (BOX == kBoxTricSearch) q = search_q64(dx, dy, dz, q, g);
-  return sqrt_rn(q) * g.s;
+  return sqrt_cr(q) * g.s;
+}
+
+// q of the canonical sequence before the root (no image search)
+template <int BOX>
+__device__ __forceinline__ double q64(double xi, double yi, double zi, double xj, double yj,
+                                      double zj, const Geo64 &g) {
+  double dx, dy, dz;
+  reduce64<BOX>(xi, yi, zi, xj, yj, zj, g, dx, dy, dz);
+  return fma(dz, dz, fma(dy, dy, dx * dx));
 }
 
 // binary32. Without a box the staged coordinates are x * s, so the
@@ -626,6 +690,9 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
       nzz[k] = 0ull;
   }
   const int n_bins = uni(F->n_bins);
+  // binary64: t at or above 2^20 can lie near a bin edge only with this many
+  // bins (see t_fast64)
+  [[maybe_unused]] const bool big_bins = n_bins >= (1 << 20) - 2;
   // the output is global memory: say so, so the atomics are global_atomic_*
   // (a generic pointer would give flat atomics, which also count as LDS
   // operations in lgkmcnt)
@@ -724,7 +791,7 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
       if constexpr (sizeof(T) == 4)
         count_t(bin_bits32(__builtin_amdgcn_sqrtf(q)), v ? 0u : hi, v ? kMagicBits - 1u : hib);
       else
-        count_t(sqrt_rn(q) * g.s, v ? 0u : hi, 0u);
+        count_t(t_guarded64(q, g.s, big_bins), v ? 0u : hi, 0u);
       head += cnt;
       if (head >= cap) head -= cap;
       qn -= cnt;
@@ -769,6 +836,28 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
       };
       // R pairs of one j: distance, bin, one atomic each
       auto pairs_of = [&](const J &pj, int j) {
+        if constexpr (sizeof(T) == 8 && !SEARCH) {
+          // binary64: the short root for all R pairs, one ballot, and the
+          // correctly rounded root for all of them when any lane of the wave
+          // has a t near an integer (see t_fast64)
+          double q[R], t[R];
+          uint64_t near = big_bins ? ~0ull : 0ull;
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            q[r] = q64<BOX>(xi[r], yi[r], zi[r], pj.x, pj.y, pj.z, g);
+            t[r] = t_fast64(q[r], g.s, near);
+          }
+          if (__builtin_expect(near != 0, 0))
+#pragma unroll
+            for (int r = 0; r < R; ++r) t[r] = sqrt_cr(q[r]) * g.s;
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            uint32_t l = lo[r];
+            if constexpr (DIAG) l = j > wbase + r * 64 + lane ? l : hi;
+            count_t(t[r], l, 0u);
+          }
+          return;
+        }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           uint32_t l = lo[r], lb = lob[r];
@@ -791,7 +880,7 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
             if constexpr (sizeof(T) == 4)
               count_t(bin_bits32(__builtin_amdgcn_sqrtf(q0)), need ? hi : l, need ? hib : lb);
             else
-              count_t(sqrt_rn(q0) * g.s, need ? hi : l, 0u);
+              count_t(t_guarded64(q0, g.s, big_bins), need ? hi : l, 0u);
             const uint64_t m = __builtin_amdgcn_ballot_w64(need);
             if (m != 0) {
               const int below = __builtin_amdgcn_mbcnt_hi(
