@@ -9,7 +9,8 @@ import pytest
 
 import oracle
 import workloads
-from gpu_util import run_gpu
+from gpu_util import fp32_bound_violations, oor_bound_violations, run_gpu
+from golden.make_golden import input_hash, load as load_golden
 
 pytestmark = pytest.mark.gpu
 
@@ -120,23 +121,38 @@ def test_graph_replay_follows_new_coordinates(ctx):
 
 
 def test_trajectory_subset_batched(ctx):
-    """32 frames of the trajectory workload at full size: batched binary64
-    equals the oracle for two of them and per-frame launches for all."""
+    """The first 32 frames of the trajectory workload at full size in one
+    batched graph launch: binary64 equal to the oracle's stored histograms and
+    out-of-range counts for every frame, binary32 within the edge-pair bound,
+    and both precisions equal to per-frame launches."""
     import paper_1808_01478_amd as dh
     import torch
+    g = load_golden("trajectory32")
     frames = [workloads.trajectory_frame(f) for f in range(32)]
+    for k, f in enumerate(frames):
+        assert str(g["input_sha256"][k]) == input_hash(f), f"{f.name}: input differs"
     bufs = _alloc(frames)
+    off = g["hist_offsets"]
     for prec in (0, 1):
+        print(f"\n[case] trajectory 32 frames batched, precision {prec}", flush=True)
         batch = dh.Batch(ctx, bufs, prec, graph=True)
         batch.launch()
         torch.cuda.synchronize()
-        for f, b in zip(frames, bufs):
-            ref_h, _ = run_gpu(ctx, f, prec)
-            assert np.array_equal(b["d_out"].cpu().numpy().view(np.uint64), ref_h), f.name
-        if prec == 1:
-            for k in (0, 5):
-                ref = oracle.frame_histogram(frames[k])
-                assert np.array_equal(bufs[k]["d_out"].cpu().numpy().view(np.uint64), ref.hist)
+        for k, (f, b) in enumerate(zip(frames, bufs)):
+            got = b["d_out"].cpu().numpy().view(np.uint64)
+            got_oor = b["d_out_of_range"].cpu().numpy().view(np.uint64)
+            ref_h, ref_oor = g["hist"][off[k]:off[k + 1]], g["oor"][off[k]:off[k + 1]]
+            edges = g["edges"][off[k]:off[k + 1]]
+            if prec == 1:
+                assert np.array_equal(got, ref_h), f.name
+                assert np.array_equal(got_oor, ref_oor), f.name
+            else:
+                bad = fp32_bound_violations(got, ref_h, edges)
+                bad += oor_bound_violations(got_oor, ref_oor, edges)
+                assert not bad, f"{f.name}: " + "; ".join(bad[:5])
+            alone_h, alone_oor = run_gpu(ctx, f, prec)
+            assert np.array_equal(got, alone_h), f.name
+            assert np.array_equal(got_oor, alone_oor), f.name
         batch.close()
 
 

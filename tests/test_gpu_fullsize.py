@@ -1,19 +1,25 @@
 """The full-size workloads in the launch configuration that bench.py times.
 
 ortho100k (N=100,000, 2 species, 10,000 bins): binary64 bit-exact against the
-oracle over all 4,999,950,000 pairs, binary32 within the edge-pair bound.
-triclinic1M (N=1,000,000 clustered, 3 species, 20,000 bins): pair-count
-identity at full size, binary64 and binary32 histograms related by the bound
-computed from a seeded subset, and sampled pairs checked one by one.
-image search (N=200,000 in a skewed cell, r_max = 0.8 of the smallest width,
-the 27-image search running): pair-count identity, a subset against the
-oracle, sampled pairs one by one."""
+oracle over all 4,999,950,000 pairs (run here), binary32 within the edge-pair
+bound. triclinic1M (N=1,000,000 clustered, 3 species, 20,000 bins,
+499,999,500,000 pairs) and the image-search frame (N=200,000 in a skewed
+cell, r_max = 0.8 of the smallest width, the 27-image search running): against
+the oracle's full histograms, out-of-range and edge counts stored in
+tests/golden/ (written by tests/golden/make_golden.py, which calls only the
+oracle), binary64 bit for bit and binary32 within the per-edge bound; plus
+sampled pairs one by one.
+
+The device's out-of-range counts are its pair count less the flushed in-range
+counts, so bins + out-of-range = pairs holds by construction and is not used
+as evidence here."""
 import numpy as np
 import pytest
 
 import oracle
 import workloads
-from gpu_util import fp32_bound_violations, run_gpu
+from gpu_util import fp32_bound_violations, oor_bound_violations, run_gpu
+from golden.make_golden import input_hash, load as load_golden
 
 pytestmark = pytest.mark.gpu
 
@@ -38,32 +44,30 @@ def test_ortho100k_full(ctx):
     print("[case] ortho100k gpu fp32", flush=True)
     h32, oor32 = run_gpu(ctx, fr, 0)
     bad = fp32_bound_violations(h32, ref.hist, ref.edges)
+    bad += oor_bound_violations(oor32, ref.out_of_range, ref.edges)
     assert not bad, "; ".join(bad[:5])
+
+
+def _against_golden(ctx, fr, name):
+    """Binary64 bit-exact and binary32 within the edge-pair bound against the
+    stored oracle result of workload `name`."""
+    g = load_golden(name)
+    assert str(g["input_sha256"][0]) == input_hash(fr), \
+        f"{name}: the generated input differs from the one the stored oracle result was made from"
+    print(f"\n[case] {name} gpu fp64 against the stored oracle result", flush=True)
+    h64, oor64 = run_gpu(ctx, fr, 1)
+    assert np.array_equal(h64, g["hist"]), f"{name}: {int((h64 != g['hist']).sum())} bins differ"
+    assert np.array_equal(oor64, g["oor"])
+    print(f"[case] {name} gpu fp32 against the edge-pair bound", flush=True)
+    h32, oor32 = run_gpu(ctx, fr, 0)
+    bad = fp32_bound_violations(h32, g["hist"], g["edges"])
+    bad += oor_bound_violations(oor32, g["oor"], g["edges"])
+    assert not bad, f"{name}: " + "; ".join(bad[:5])
 
 
 def test_triclinic1m_full(ctx):
     fr = workloads.triclinic()
-    print("\n[case] triclinic1M gpu fp64", flush=True)
-    h64, oor64 = run_gpu(ctx, fr, 1)
-    pairs = fr.hist_pairs()
-    assert list(h64.sum(axis=1).astype(np.int64) + oor64.astype(np.int64)) == pairs
-    print("[case] triclinic1M gpu fp32", flush=True)
-    h32, oor32 = run_gpu(ctx, fr, 0)
-    assert list(h32.sum(axis=1).astype(np.int64) + oor32.astype(np.int64)) == pairs
-    # a seeded 40,000-point subset in the same launch path, against the oracle
-    sub = fr.subset([20_000, 12_000, 8_000])
-    print("[case] triclinic1M subset oracle", flush=True)
-    w = oracle.edge_window(sub.coords, sub.box, sub.r_max)
-    ref = oracle.frame_histogram(sub, edge_window=w)
-    s64, _ = run_gpu(ctx, sub, 1)
-    assert np.array_equal(s64, ref.hist)
-    s32, _ = run_gpu(ctx, sub, 0)
-    assert not fp32_bound_violations(s32, ref.hist, ref.edges)
-    # binary32 vs binary64 at full size: relative L1 in line with the subset's
-    l1_full = np.abs(h32.astype(np.int64) - h64.astype(np.int64)).sum() / max(1, h64.sum())
-    l1_sub = np.abs(s32.astype(np.int64) - s64.astype(np.int64)).sum() / max(1, s64.sum())
-    e_sub = ref.edges.sum() / max(1, ref.hist.sum())
-    assert l1_full <= 2 * e_sub + 1e-9, (l1_full, l1_sub, e_sub)
+    _against_golden(ctx, fr, "triclinic1M")
     # sampled pairs of the full frame, one by one: binary64 scaled distances
     # equal to the oracle's, binary32 within the edge window
     import torch
@@ -90,21 +94,7 @@ def test_triclinic1m_full(ctx):
 def test_image_search_full(ctx):
     import torch
     fr = workloads.image_search()
-    print("\n[case] image search 200k gpu", flush=True)
-    pairs = fr.hist_pairs()
-    h64, oor64 = run_gpu(ctx, fr, 1)
-    assert list(h64.sum(axis=1).astype(np.int64) + oor64.astype(np.int64)) == pairs
-    h32, oor32 = run_gpu(ctx, fr, 0)
-    assert list(h32.sum(axis=1).astype(np.int64) + oor32.astype(np.int64)) == pairs
-    # a 15,000-point subset in the same cell, r_max and bins, against the oracle
-    sub = fr.subset([9_000, 6_000])
-    print("[case] image search subset oracle", flush=True)
-    w = oracle.edge_window(sub.coords, sub.box, sub.r_max)
-    ref = oracle.frame_histogram(sub, edge_window=w)
-    s64, so64 = run_gpu(ctx, sub, 1)
-    assert np.array_equal(s64, ref.hist) and np.array_equal(so64, ref.out_of_range)
-    s32, _ = run_gpu(ctx, sub, 0)
-    assert not fp32_bound_violations(s32, ref.hist, ref.edges)
+    _against_golden(ctx, fr, "image_search200k")
     # sampled pairs of the full frame (searched images included), one by one
     print("[case] image search sampled pairs", flush=True)
     rng = np.random.Generator(np.random.PCG64(43))

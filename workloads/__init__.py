@@ -111,14 +111,31 @@ def ortho_box(lx: float, ly: float, lz: float) -> np.ndarray:
     return np.array([[lx, 0.0, 0.0], [0.0, ly, 0.0], [0.0, 0.0, lz]], np.float64)
 
 
+def rows_combine(u: np.ndarray, rows: np.ndarray) -> np.ndarray:
+    """u @ rows for (n, 3) @ (3, 3), written as elementwise products and sums
+    (u0*r0 + u1*r1) + u2*r2 so that the bytes do not depend on which BLAS
+    kernel the host CPU selects: stored expected values made on one machine
+    must be reproducible on another."""
+    u = np.asarray(u, np.float64)
+    r = np.asarray(rows, np.float64)
+    return (u[:, 0:1] * r[0] + u[:, 1:2] * r[1]) + u[:, 2:3] * r[2]
+
+
 def min_width(box: np.ndarray) -> float:
     """Smallest distance between opposite faces of the cell (geometry of the
-    input, used to pick workload cut-offs)."""
-    a, b, c = (np.asarray(v, np.float64) for v in box)
-    vol = abs(float(np.dot(a, np.cross(b, c))))
-    return min(vol / float(np.linalg.norm(np.cross(b, c))),
-               vol / float(np.linalg.norm(np.cross(c, a))),
-               vol / float(np.linalg.norm(np.cross(a, b))))
+    input, used to pick workload cut-offs). Written with scalar arithmetic,
+    not BLAS, so it is the same on every host."""
+    a, b, c = ([float(t) for t in v] for v in np.asarray(box, np.float64))
+
+    def cross(u, v):
+        return (u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0])
+
+    def norm(u):
+        return math.sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2])
+
+    bc, ca, ab = cross(b, c), cross(c, a), cross(a, b)
+    vol = abs(a[0] * bc[0] + a[1] * bc[1] + a[2] * bc[2])
+    return min(vol / norm(bc), vol / norm(ca), vol / norm(ab))
 
 
 # --------------------------------------------------------------------------- #
@@ -157,17 +174,22 @@ def triclinic(seed: int = 3, n: int = 1_000_000, n_centres: int = 64, sigma: flo
     Species are drawn by a seeded permutation (50/30/20 %) and stably sorted
     into blocks. r_max = 22 < w_min/2 = 22.5; 20,000 bins. Seed 3."""
     rng = _rng(seed)
-    hmat = TRICLINIC_BOX.T                     # columns a, b, c
-    hinv = np.linalg.inv(hmat)
+    rows = TRICLINIC_BOX                       # rows a, b, c (lower triangular)
+    # inverse of the lower-triangular row matrix, written out: x = u @ rows
+    # gives u = x @ inv
+    (ax, _, _), (bx, by, _), (cx, cy, cz) = rows
+    inv = np.array([[1.0 / ax, 0.0, 0.0],
+                    [-bx / (ax * by), 1.0 / by, 0.0],
+                    [(bx * cy - by * cx) / (ax * by * cz), -cy / (by * cz), 1.0 / cz]])
     n_bg = int(round(n * frac_background))
     n_cl = n - n_bg
-    centres = rng.uniform(0.0, 1.0, size=(n_centres, 3)) @ hmat.T
+    centres = rows_combine(rng.uniform(0.0, 1.0, size=(n_centres, 3)), rows)
     which = rng.integers(0, n_centres, size=n_cl)
     pts = centres[which] + rng.normal(0.0, sigma, size=(n_cl, 3))
-    frac = (pts @ hinv.T) % 1.0
+    frac = rows_combine(pts, inv) % 1.0
     frac = np.concatenate([frac, rng.uniform(0.0, 1.0, size=(n_bg, 3))])
     frac = frac[rng.permutation(n)]
-    x = frac @ hmat.T
+    x = rows_combine(frac, rows)
     counts = [int(round(n * f)) for f in species[:-1]]
     counts.append(n - sum(counts))
     labels = rng.permutation(np.repeat(np.arange(len(counts)), counts))
@@ -239,8 +261,9 @@ def image_search(n: int = 200_000, seed: int = 31) -> Frame:
     cell width (so the 27-image search runs), 4,000 bins."""
     rng = _rng(seed)
     shape = np.array([[10.0, 0, 0], [3.0, 9.5, 0], [-2.0, 3.5, 9.0]])
-    box = shape * (n / DENSITY / abs(np.linalg.det(shape))) ** (1.0 / 3.0)
-    x = rng.uniform(0.0, 1.0, size=(n, 3)) @ box
+    # lower triangular: the determinant is the product of the diagonal
+    box = shape * (n / DENSITY / (shape[0, 0] * shape[1, 1] * shape[2, 2])) ** (1.0 / 3.0)
+    x = rows_combine(rng.uniform(0.0, 1.0, size=(n, 3)), box)
     na = (n * 3) // 5
     return Frame(np.ascontiguousarray(x), _offsets([na, n - na]), BOX_TRICLINIC, box,
                  0.8 * min_width(box), 4000, f"image-search-{n}")
@@ -266,7 +289,7 @@ def serving_job(rng: np.random.Generator, job_id: int, arrival: float,
         box, r_max = ortho_box(*edge), 0.5 * float(edge.min())
     else:
         box = random_triclinic_cell(rng, vol)
-        x = rng.uniform(0.0, 1.0, size=(n, 3)) @ box
+        x = rows_combine(rng.uniform(0.0, 1.0, size=(n, 3)), box)
         r_max = 0.49 * min_width(box)
     fr = Frame(np.ascontiguousarray(x), _offsets(sizes), box_type, box, float(r_max),
                n_bins, f"job{job_id}")
@@ -305,7 +328,7 @@ def random_frame(seed: int, sizes, box_type: int, r_max: Optional[float] = None,
                 box = np.array([[extent, 0, 0], [0.3 * extent, 0.95 * extent, 0],
                                 [-0.2 * extent, 0.35 * extent, 0.9 * extent]], np.float64)
         bx = np.asarray(box, np.float64)
-        x = rng.uniform(0.0, 1.0, size=(n, 3)) @ bx
+        x = rows_combine(rng.uniform(0.0, 1.0, size=(n, 3)), bx)
         rm = 0.45 * min_width(bx) if r_max is None else r_max
     return Frame(np.ascontiguousarray(x), _offsets(sizes), box_type, bx, float(rm),
                  int(n_bins), f"rand{seed}")
