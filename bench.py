@@ -4,12 +4,13 @@
 One step is one full pass of the hot path over one frame already resident in
 HBM: stage the binary64 coordinates (convert / wrap / pad), zero the output,
 run the pair kernel (distances, minimum image, binning into LDS
-sub-histograms, flush to uint64), and derive the out-of-range counts.
+sub-histograms, flush to uint64, out-of-range counts).
 
-Default workload: N = 100,000 uniform points in a periodic 40^3 cube, species
-60,000 / 40,000 (histograms AA, BB, AB), r_max = 20, 10,000 bins,
-4,999,950,000 pairs per step. The headline value is binary32; the binary64
-rate is reported beside it.
+Default workload (the largest single-frame one): N = 1,000,000 clustered
+points in the triclinic cell a=(50,0,0), b=(15,48,0), c=(10,12,45), species
+50/30/20 % (6 histograms), r_max = 22, 20,000 bins, 499,999,500,000 pairs per
+step. The headline value is binary32; the binary64 rate is reported beside
+it, and the 100,000-point orthorhombic frame as a sub-object.
 
 Prints ONE JSON line. Usage: python bench.py [--steps K] [--warmup W]
 """
@@ -32,21 +33,33 @@ import workloads  # noqa: E402
 # algorithmic FLOPs per pair of the canonical op sequence (add, sub, mul,
 # sqrt, rint, min: 1; fma: 2)
 FLOPS_PER_PAIR = {0: 10, 1: 22, 2: 34, 3: 268}
+# a searched pair adds 26 images (3 adds, mul + 2 fma: 8 FLOPs each) and 26
+# minima to the 34 FLOPs of the reduced pair
+SEARCH_FLOPS = 26 * 9
 PEAK_TFLOPS = {0: 157.3, 1: 78.6}        # MI355X vector FP32 / FP64
 KERNEL_NAME = "pairs_kernel"
 
 
+DESCRIPTIONS = {
+    "ortho100k": "ortho100k: N=100,000 uniform, species 60,000/40,000, periodic cube L=40, "
+                 "r_max=20, 10,000 bins",
+    "tiny": "tiny: N=5,000 uniform in [0,10)^3, 1 species, no box, r_max=10*sqrt(3), 1,000 bins",
+    "triclinic1M": "triclinic1M: N=1,000,000 clustered, species 50/30/20 %, cell a=(50,0,0) "
+                   "b=(15,48,0) c=(10,12,45), r_max=22, 20,000 bins",
+}
+
+
+def workload_desc(name: str) -> str:
+    return DESCRIPTIONS[name]
+
+
 def workload(name: str):
     if name == "ortho100k":
-        return workloads.ortho(), "ortho100k: N=100,000 uniform, species 60,000/40,000, " \
-                                  "periodic cube L=40, r_max=20, 10,000 bins"
+        return workloads.ortho(), DESCRIPTIONS[name]
     if name == "tiny":
-        return workloads.tiny(), "tiny: N=5,000 uniform in [0,10)^3, 1 species, no box, " \
-                                 "r_max=10*sqrt(3), 1,000 bins"
+        return workloads.tiny(), DESCRIPTIONS[name]
     if name == "triclinic1M":
-        return workloads.triclinic(), "triclinic1M: N=1,000,000 clustered, species " \
-                                      "50/30/20 %, cell a=(50,0,0) b=(15,48,0) c=(10,12,45), " \
-                                      "r_max=22, 20,000 bins"
+        return workloads.triclinic(), DESCRIPTIONS[name]
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -122,9 +135,9 @@ def time_path(ctx, frame, precision, steps, warmup):
     step_ms = sorted(s.elapsed_time(e) for s, e in zip(start, end))
     counts = out.cpu().numpy().view(np.uint64)
     oor_h = oor.cpu().numpy().view(np.uint64)
-    assert list(counts.sum(axis=1).astype(np.int64) + oor_h.astype(np.int64)) == \
-        frame.hist_pairs(), "pair-count identity failed"
     return {
+        "hist": counts,
+        "oor": oor_h,
         "wall_s": t1 - t0,
         "kernel_ms_avg": kern_ms / max(1, launches),
         "launches": launches,
@@ -196,7 +209,10 @@ def bench_image_search(steps=3):
     pairs = n * (n - 1) // 2
     out = {"workload": "image search: 200,000 uniform points in a skewed triclinic cell, "
                        "species 120,000/80,000, r_max = 0.8 of the smallest width, 4,000 bins",
-           "flops_per_pair": FLOPS_PER_PAIR[3]}
+           "pairs": pairs,
+           "flops": f"{FLOPS_PER_PAIR[2]} per pair (Eq. 5 reduction, root, scale) plus "
+                    f"{SEARCH_FLOPS} per searched pair (26 more images and the minimum); "
+                    "the pair kernel counts the searched pairs"}
     xt = torch.from_numpy(x).cuda()
     h = torch.empty((3, 4000), dtype=torch.int64, device="cuda")
     with dh.Context(0) as c:
@@ -208,9 +224,13 @@ def bench_image_search(steps=3):
                 c.histo_async(xt, offs, dh.BOX_TRICLINIC, box, r_max, 4000, prec, h)
             ms, k = c.profile_read()
             c.profile(False)
+            torch.cuda.synchronize()
+            searched = c.searched_pairs()
             ms /= k
-            ach = pairs * FLOPS_PER_PAIR[3] / (ms * 1e-3) / 1e12
+            flops = pairs * FLOPS_PER_PAIR[2] + searched * SEARCH_FLOPS
+            ach = flops / (ms * 1e-3) / 1e12
             out[name] = {"kernel_ms": ms, "pairs_per_s": pairs / (ms * 1e-3),
+                         "searched_pairs": searched, "searched_frac": searched / pairs,
                          "achieved_tflops": ach, "roofline_frac": ach / PEAK_TFLOPS[prec]}
     return out
 
@@ -275,7 +295,7 @@ def bench_trajectory(ctx, n_frames: int, steps: int):
         batch.launch()
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / steps
-    snap = [b["d_out"].clone() for b in bufs[:8]]
+    snap = [b["d_out"].clone() for b in bufs]
 
     def per_frame():
         for f, b in zip(frames, bufs):
@@ -288,7 +308,7 @@ def bench_trajectory(ctx, n_frames: int, steps: int):
         per_frame()
     torch.cuda.synchronize()
     t_frames = (time.perf_counter() - t0) / steps
-    same = all(torch.equal(a, b["d_out"]) for a, b in zip(snap, bufs[:8]))
+    same = all(torch.equal(a, b["d_out"]) for a, b in zip(snap, bufs))
     info = batch.info()
     batch.close()
     return {
@@ -301,6 +321,7 @@ def bench_trajectory(ctx, n_frames: int, steps: int):
                                "ms_per_run": t_frames * 1e3, "launches": n_frames},
         "speedup": t_frames / t_batch,
         "identical_results": bool(same),
+        "identical_results_frames": len(bufs),
     }
 
 
@@ -352,100 +373,185 @@ def run_trace(server_args, frames, gaps, progress: str = ""):
     return np.array(lat), end, st
 
 
-def bench_triclinic(ctx, steps: int):
-    """The clustered 1M-point triclinic frame (6 histograms, 5.0e11 pairs,
-    r_max below half the smallest width, so no image search) in binary32 and
-    binary64: pairs/s, kernel time and FLOP roofline fraction."""
-    import paper_1808_01478_amd as dh
-    frame, desc = workload("triclinic1M")
-    kind = box_kind(frame)
-    pairs = frame.total_pairs()
-    out = {"workload": desc, "pairs_per_step": pairs, "flops_per_pair": FLOPS_PER_PAIR[kind]}
-    for prec, name in ((dh.FP32, "fp32"), (dh.FP64, "fp64")):
-        r = time_path(ctx, frame, prec, steps, 1)
-        ach = pairs * FLOPS_PER_PAIR[kind] / (r["kernel_ms_avg"] * 1e-3) / 1e12
-        out[name] = {"value": pairs * steps / r["wall_s"], "unit": "pairs/s", "steps": steps,
-                     "kernel_ms_avg": r["kernel_ms_avg"], "achieved_tflops": ach,
-                     "roofline_frac": ach / PEAK_TFLOPS[prec], "launch_shape": ctx.last_config()}
+GOLDEN = {"triclinic1M": os.path.join(ROOT, "tests", "golden", "triclinic1M.npz")}
+
+
+def check_against_golden(name, frame, r32, r64):
+    """The step's histograms against the oracle's stored full-size result
+    (written by tests/golden/make_golden.py from the oracle alone): binary64
+    bit for bit, binary32 within the per-edge bound. None when no stored
+    result exists for the workload or it was made from other input bytes."""
+    path = GOLDEN.get(name)
+    if path is None or not os.path.exists(path):
+        return None
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from golden.make_golden import input_hash
+    with np.load(path, allow_pickle=False) as z:
+        g = {k: z[k] for k in z.files}
+    if str(g["input_sha256"][0]) != input_hash(frame):
+        return {"against": os.path.relpath(path, ROOT), "input_matches": False}
+    out = {"against": os.path.relpath(path, ROOT), "input_matches": True}
+    if r64 is not None:
+        out["fp64_bit_exact"] = bool(np.array_equal(r64["hist"], g["hist"]) and
+                                     np.array_equal(r64["oor"], g["oor"]))
+    worst, ok = 0, True
+    for h in range(frame.n_hist):
+        d = np.abs(np.cumsum(r32["hist"][h].astype(np.int64)) -
+                   np.cumsum(g["hist"][h].astype(np.int64)))
+        e = g["edges"][h].astype(np.int64)
+        ok &= bool((d <= e).all())
+        worst = max(worst, int(d.max()))
+        ok &= abs(int(r32["oor"][h]) - int(g["oor"][h])) <= int(e[-1])
+    out["fp32_within_edge_bound"] = ok
+    out["fp32_max_cumulative_difference"] = worst
+    out["edge_pairs"] = int(g["edges"].sum())
     return out
 
 
-def bench_serving(n_jobs: int, seed: int = 5):
+def bench_frame(ctx, name: str, steps: int, fp64_steps: int, warmup: int, frame=None):
+    """One single-frame workload in binary32 and binary64: pairs/s over the
+    timed steps' wall clock, the pair kernel's HIP-event average and its FLOP
+    roofline fraction."""
+    import paper_1808_01478_amd as dh
+    fr, desc = workload(name) if frame is None else (frame, workload_desc(name))
+    frame = fr
+    kind = box_kind(frame)
+    pairs = frame.total_pairs()
+    out = {"workload": desc, "pairs_per_step": pairs, "flops_per_pair": FLOPS_PER_PAIR[kind]}
+    res = {}
+    for prec, key, k in ((dh.FP32, "fp32", steps), (dh.FP64, "fp64", fp64_steps)):
+        if k <= 0:
+            continue
+        progress(f"{name} {key}, {k} steps")
+        r = time_path(ctx, frame, prec, k, warmup if prec == dh.FP32 else 1)
+        res[key] = r
+        ach = pairs * FLOPS_PER_PAIR[kind] / (r["kernel_ms_avg"] * 1e-3) / 1e12
+        out[key] = {"value": pairs * k / r["wall_s"], "unit": "pairs/s", "steps": k,
+                    "ms_per_step": r["wall_s"] * 1e3 / k, "kernel_ms_avg": r["kernel_ms_avg"],
+                    "achieved_tflops": ach, "roofline_frac": ach / PEAK_TFLOPS[prec],
+                    "launch_shape": ctx.last_config(),
+                    "latency_ms": {"p50": r["step_ms_p50"], "p99": r["step_ms_p99"]}}
+    return frame, out, res
+
+
+def serving_frames(n_jobs: int, n_warm: int, seed: int = 5):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    frames = [workloads.serving_job(rng, j, 0.0).frame for j in range(n_warm + n_jobs)]
+    return frames[:n_warm], frames[n_warm:]
+
+
+def batched_rate(frames):
+    """The batched path (dh_batch: all frames planned once, one persistent
+    launch per class of frames) on the same frames, binary32: pairs/s and
+    jobs/s of one run, frames already resident."""
+    import torch
+    import paper_1808_01478_amd as dh
+    dev = torch.device("cuda")
+    bufs = [{"d_coords": torch.from_numpy(f.coords).to(dev), "offsets": f.offsets,
+             "box_type": f.box_type, "box": f.box, "r_max": f.r_max, "n_bins": f.n_bins,
+             "d_out": torch.empty((f.n_hist, f.n_bins), dtype=torch.int64, device=dev)}
+            for f in frames]
+    with dh.Context(0) as ctx:
+        batch = dh.Batch(ctx, bufs, dh.FP32, graph=False)
+        batch.launch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        batch.launch()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        batch.close()
+    pairs = sum(f.total_pairs() for f in frames)
+    del bufs
+    torch.cuda.empty_cache()
+    return {"pairs_per_s": pairs / dt, "jobs_per_s": len(frames) / dt, "seconds": dt}
+
+
+def bench_serving(n_jobs: int, n_warm: int = 50, n_capacity: int = 200, seed: int = 5,
+                  load: float = 0.75, slots: int = 8):
     """Histogram jobs with N log-uniform in [1e3, 2e6], box none/orthorhombic/
     triclinic, 1-3 species, 1k/10k/50k bins, binary32, Poisson arrivals at
-    0.75 of the saturated job rate, 8 GiB HBM budget: the server's default
-    (4 slots, least remaining work first at launch boundaries) against the
-    same slots in arrival order and against one job at a time in arrival
-    order (FIFO), on the same arrivals."""
-    rng = np.random.Generator(np.random.PCG64(seed))
-    frames = [workloads.serving_job(rng, j, 0.0).frame for j in range(n_jobs)]
-    pairs = sum(f.total_pairs() for f in frames)
+    `load` times the saturated job rate C of the batched path on the same
+    mix (measured on the first n_capacity jobs, which also run saturated
+    through the server), n_jobs measured jobs after n_warm warm-up jobs:
+    the server's default (continuous batching, `slots` resident jobs, least
+    remaining work first) with an 8 GiB and a 256 MiB HBM budget, against
+    one job at a time in arrival order (FIFO), on the same arrivals."""
     import paper_1808_01478_amd as dh
-    cont = {"hbm_budget_bytes": 8 << 30, "max_inflight": 4}
-    arrival = {"hbm_budget_bytes": 8 << 30, "max_inflight": 4, "policy": dh.SCHED_ARRIVAL}
+    warm, frames = serving_frames(n_jobs, n_warm, seed)
+    pairs = sum(f.total_pairs() for f in frames)
+    cont = {"hbm_budget_bytes": 8 << 30, "max_inflight": slots}
     fifo = {"hbm_budget_bytes": 8 << 30, "max_inflight": 1, "policy": dh.SCHED_ARRIVAL}
-    # warm-up: load every kernel variant the trace uses (small copies of the
-    # first jobs of each box kind and bin count)
-    seen, warm = set(), []
-    for f in frames:
-        key = (f.box_type, f.n_bins, f.n_species)
-        if key not in seen:
-            seen.add(key)
-            warm.append(f.subset([min(s, 500) for s in f.species_sizes()]))
     run_trace(cont, warm, [0.0] * len(warm))
-    # saturated capacity: everything submitted at once, one at a time
-    _, sat_end, _ = run_trace(fifo, frames, [0.0] * n_jobs)
-    capacity = n_jobs / sat_end
-    lam = 0.75 * capacity
-    gaps = rng.exponential(1.0 / lam, size=n_jobs)
-    out = {"workload": f"serving: {n_jobs} jobs, N log-uniform [1e3, 2e6], box none/ortho/"
-                       "triclinic, 1-3 species, bins 1k/10k/50k, binary32, Poisson arrivals",
-           "pairs": pairs, "saturated_jobs_per_s": capacity, "arrival_rate_per_s": lam}
-    for name, args in (("shortest_remaining_work", cont), ("arrival_order", arrival),
-                       ("fifo_one_at_a_time", fifo)):
-        lat, end, st = run_trace(args, frames, gaps)
+    cap_frames = frames[:n_capacity]
+    batched = batched_rate(cap_frames)
+    progress(f"serving: batched path {batched['jobs_per_s']:.1f} jobs/s")
+    cap_pairs = sum(f.total_pairs() for f in cap_frames)
+    _, sat_end, sat_st = run_trace(cont, cap_frames, [0.0] * len(cap_frames))
+    capacity = batched["jobs_per_s"]
+    lam = load * capacity
+    gaps = np.random.Generator(np.random.PCG64(seed * 100)).exponential(1.0 / lam, size=n_jobs)
+    out = {"workload": f"serving: {n_jobs} jobs after {n_warm} warm-up jobs, N log-uniform "
+                       "[1e3, 2e6], box none/ortho/triclinic, 1-3 species, bins 1k/10k/50k, "
+                       f"binary32, Poisson arrivals at {load} of the batched path's job rate",
+           "pairs": pairs, "load": load, "arrival_rate_per_s": lam,
+           "saturated": {"jobs": len(cap_frames),
+                         "batched_path": batched,
+                         "server": {"pairs_per_s": cap_pairs / sat_end,
+                                    "jobs_per_s": len(cap_frames) / sat_end,
+                                    "launches": sat_st["launches"],
+                                    "shared_launches": sat_st["shared_launches"]},
+                         "server_vs_batched": (cap_pairs / sat_end) / batched["pairs_per_s"]}}
+    runs = (("continuous_batching", cont), ("continuous_batching_256MiB",
+                                            dict(cont, hbm_budget_bytes=256 << 20)),
+            ("fifo_one_at_a_time", fifo))
+    for name, args in runs:
+        progress(f"serving: {name}, {n_jobs} jobs")
+        lat, end, st = run_trace(args, frames, gaps, progress=name)
         out[name] = {"p50_ms": float(np.percentile(lat, 50) * 1e3),
+                     "p90_ms": float(np.percentile(lat, 90) * 1e3),
                      "p99_ms": float(np.percentile(lat, 99) * 1e3),
                      "throughput_pairs_per_s": pairs / end, "jobs_per_s": n_jobs / end,
-                     "max_running": st["max_running"], "peak_bytes": st["peak_bytes"]}
+                     "budget_bytes": args["hbm_budget_bytes"], "slots": args["max_inflight"],
+                     "max_running": st["max_running"], "peak_bytes": st["peak_bytes"],
+                     "launches": st["launches"], "shared_launches": st["shared_launches"],
+                     "max_jobs_per_launch": st["max_jobs_per_launch"]}
     return out
 
 
 def bench_serving_sweep(policy: str, n_jobs: int = 1000, n_warm: int = 50, seed: int = 5,
-                        loads=(0.25, 0.5, 0.75, 0.9)):
+                        loads=(0.25, 0.5, 0.75, 0.9), n_capacity: int = 200, slots: int = 8):
     """The full serving protocol for one policy: n_warm warm-up jobs, then
     n_jobs measured jobs (N log-uniform in [1e3, 2e6], box none/orthorhombic/
     triclinic, 1-3 species, 1k/10k/50k bins, binary32) at Poisson arrival
-    rates of each load times the saturated capacity, with an 8 GiB budget;
-    for the default policy also one run at 0.75 with a 256 MiB budget
-    (admission back-pressure). policy: "shortest" (the server's default,
-    4 slots) or "fifo" (arrival order, one slot). Prints one progress line
-    per run to stderr."""
+    rates of each load times the saturated job rate C of the batched path
+    (measured on the first n_capacity jobs), with an 8 GiB budget; for the
+    default policy also one run at 0.75 with a 256 MiB budget (admission
+    back-pressure). policy: "shortest" (the server's default: continuous
+    batching, `slots` resident jobs, least remaining work first) or "fifo"
+    (arrival order, one job at a time). The arrivals of a load are the same
+    for both policies. Prints one progress line per run to stderr."""
     import paper_1808_01478_amd as dh
-    rng = np.random.Generator(np.random.PCG64(seed))
-    frames = [workloads.serving_job(rng, j, 0.0).frame for j in range(n_warm + n_jobs)]
-    warm, frames = frames[:n_warm], frames[n_warm:]
+    warm, frames = serving_frames(n_jobs, n_warm, seed)
     pairs = sum(f.total_pairs() for f in frames)
     fifo = {"hbm_budget_bytes": 8 << 30, "max_inflight": 1, "policy": dh.SCHED_ARRIVAL}
     if policy == "fifo":
         args = fifo
     elif policy == "shortest":
-        args = {"hbm_budget_bytes": 8 << 30, "max_inflight": 4, "policy": dh.SCHED_SHORTEST}
+        args = {"hbm_budget_bytes": 8 << 30, "max_inflight": slots, "policy": dh.SCHED_SHORTEST}
     else:
         raise ValueError(policy)
     t0 = time.perf_counter()
     run_trace(args, warm, [0.0] * len(warm))
-    # capacity: the measured jobs all submitted at once, one at a time
-    _, sat_end, _ = run_trace(fifo, frames, [0.0] * n_jobs, progress="capacity")
-    capacity = n_jobs / sat_end
-    print(f"[serving] {policy}: capacity {capacity:.2f} jobs/s "
+    capacity = batched_rate(frames[:n_capacity])["jobs_per_s"]
+    print(f"[serving] {policy}: batched-path capacity {capacity:.2f} jobs/s "
           f"({time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
-    runs = [(lam, args) for lam in loads]
+    runs = [(k, lam, args) for k, lam in enumerate(loads)]
     if policy == "shortest":
-        runs.append((0.75, dict(args, hbm_budget_bytes=256 << 20)))
+        runs.append((loads.index(0.75) if 0.75 in loads else len(loads), 0.75,
+                     dict(args, hbm_budget_bytes=256 << 20)))
     out = {"policy": policy, "jobs": n_jobs, "warmup_jobs": n_warm, "pairs": pairs,
-           "saturated_jobs_per_s": capacity, "runs": []}
-    for k, (lam, a) in enumerate(runs):
+           "batched_jobs_per_s": capacity, "runs": []}
+    for k, lam, a in runs:
         gaps = np.random.Generator(np.random.PCG64(seed * 100 + k)).exponential(
             1.0 / (lam * capacity), size=n_jobs)
         lat, end, st = run_trace(a, frames, gaps, progress=f"load {lam}")
@@ -454,7 +560,8 @@ def bench_serving_sweep(policy: str, n_jobs: int = 1000, n_warm: int = 50, seed:
                "p90_ms": float(np.percentile(lat, 90) * 1e3),
                "p99_ms": float(np.percentile(lat, 99) * 1e3),
                "jobs_per_s": n_jobs / end, "throughput_pairs_per_s": pairs / end,
-               "max_running": st["max_running"], "peak_bytes": st["peak_bytes"]}
+               "max_running": st["max_running"], "peak_bytes": st["peak_bytes"],
+               "launches": st["launches"], "shared_launches": st["shared_launches"]}
         out["runs"].append(row)
         print(f"[serving] {policy} load {lam} budget {a['hbm_budget_bytes'] >> 20} MiB: "
               f"p50 {row['p50_ms']:.1f} ms p99 {row['p99_ms']:.1f} ms "
@@ -464,8 +571,9 @@ def bench_serving_sweep(policy: str, n_jobs: int = 1000, n_warm: int = 50, seed:
 
 def cpu_tuned(frame):
     """The library's cache-blocked, vectorized CPU kernel (dh_cpu_histo) on
-    the whole bench frame, binary32 and binary64, the same host threads as
-    the oracle: context for the oracle baseline, not the target."""
+    the whole 100,000-point orthorhombic frame, binary32 and binary64, the
+    same host threads as the oracle: context for the oracle baseline, not the
+    target."""
     import paper_1808_01478_amd as dh
     # the library's default: the affinity mask, at most OMP_NUM_THREADS
     threads = len(os.sched_getaffinity(0))
@@ -480,9 +588,33 @@ def cpu_tuned(frame):
     return out
 
 
-def cpu_baseline(frame, target_s: float = 12.0):
+def host_cores():
+    """Physical cores and logical CPUs from lscpu, and the CPUs this process
+    may run on."""
+    import subprocess
+    info = {"lscpu_physical_cores": None, "lscpu_cpus": None,
+            "affinity_cpus": len(os.sched_getaffinity(0))}
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        kv = {}
+        for line in txt.splitlines():
+            if ":" in line:
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        if "Core(s) per socket" in kv and "Socket(s)" in kv:
+            info["lscpu_physical_cores"] = int(kv["Core(s) per socket"]) * int(kv["Socket(s)"])
+        if "CPU(s)" in kv:
+            info["lscpu_cpus"] = int(kv["CPU(s)"])
+        info["model"] = kv.get("Model name")
+    except Exception:
+        pass
+    return info
+
+
+def cpu_baseline(frame, target_s: float = 12.0, target_1t_s: float = 5.0):
     """The oracle (plain FP64 double loop, OpenMP) on the first M points of
-    every species of the same frame, M sized for about target_s seconds."""
+    every species of the same frame, M sized for about target_s seconds on
+    all the threads it gets, and again on one thread (about target_1t_s)."""
     import oracle
     oracle.build(force=False)
     frac = np.array(frame.species_sizes(), np.float64) / frame.n
@@ -490,50 +622,62 @@ def cpu_baseline(frame, target_s: float = 12.0):
     def sample(m_total):
         return frame.subset([max(1, int(m_total * f)) for f in frac])
 
-    cal = sample(6000)
-    t0 = time.perf_counter()
-    oracle.frame_histogram(cal)
-    dt = max(time.perf_counter() - t0, 1e-3)
-    rate = cal.total_pairs() / dt
-    m = int(np.sqrt(2.0 * rate * target_s))
-    m = max(6000, min(m, frame.n))
-    sub = sample(m)
-    reps, done = 0, 0.0
-    t0 = time.perf_counter()
-    while reps == 0 or done < 0.5 * target_s:
-        oracle.frame_histogram(sub)
-        reps += 1
-        done = time.perf_counter() - t0
-    what = "the whole frame" if sub.n == frame.n else \
-        f"the first {sub.n} points of the frame (species kept in proportion)"
+    def timed(target, n_threads):
+        cal = sample(4000 if n_threads == 1 else 6000)
+        t0 = time.perf_counter()
+        oracle.frame_histogram(cal, n_threads=n_threads)
+        rate = cal.total_pairs() / max(time.perf_counter() - t0, 1e-3)
+        m = max(4000, min(int(np.sqrt(2.0 * rate * target)), frame.n))
+        sub = sample(m)
+        reps, done = 0, 0.0
+        t0 = time.perf_counter()
+        while reps == 0 or done < 0.5 * target:
+            oracle.frame_histogram(sub, n_threads=n_threads)
+            reps += 1
+            done = time.perf_counter() - t0
+        return sub, reps, done
+
+    sub, reps, done = timed(target_s, 0)
+    sub1, reps1, done1 = timed(target_1t_s, 1)
+    cores = host_cores()
+
+    def what(f, r, d):
+        w = "the whole frame" if f.n == frame.n else \
+            f"the first {f.n} points of the frame (species kept in proportion)"
+        return f"{w}, {r} run(s), {f.total_pairs() * r} pairs in {d:.1f} s, binary64"
+
     return {
         "value": sub.total_pairs() * reps / done,
         "unit": "pairs/s",
         "cores": oracle.max_threads(),
         "kind": "oracle",
-        "sample": f"{what}, {reps} run(s), {sub.total_pairs() * reps} pairs in {done:.1f} s, "
-                  "binary64",
+        "sample": what(sub, reps, done),
+        "one_thread": {"value": sub1.total_pairs() * reps1 / done1, "unit": "pairs/s",
+                       "sample": what(sub1, reps1, done1)},
+        "host": cores,
     }
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="ortho100k")
+    ap.add_argument("--workload", default="triclinic1M",
+                    choices=("triclinic1M", "ortho100k", "tiny"))
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serving-jobs", type=int, default=120,
-                    help="jobs of the serving comparison (0 = skip)")
+    ap.add_argument("--serving-jobs", type=int, default=1000,
+                    help="measured jobs of the serving comparison (0 = skip)")
     ap.add_argument("--no-tune", action="store_true",
                     help="built-in launch shape instead of tuning on the first warm-up call")
     ap.add_argument("--trajectory-frames", type=int, default=512,
                     help="frames of the batched trajectory comparison (0 = skip)")
     ap.add_argument("--no-wide", dest="wide", action="store_false",
                     help="skip the wide-histogram comparison")
-    ap.add_argument("--triclinic-steps", type=int, default=3,
-                    help="timed steps per precision on the 1M-point triclinic frame (0 = skip)")
+    ap.add_argument("--ortho-steps", type=int, default=20,
+                    help="binary32 steps on the 100,000-point orthorhombic frame, reported as "
+                         "a sub-object (half as many binary64 steps; 0 = skip)")
     ap.add_argument("--serving-sweep", choices=("shortest", "fifo"), default=None,
                     help="run only the full serving protocol for one policy (1000 jobs at "
                          "each of four loads, several minutes) and print its JSON line")
@@ -564,18 +708,15 @@ def main():
         if os.path.exists(DEFAULT_CACHE):
             os.environ.setdefault("DH_TUNE", str(dh.TUNE_CACHED))
             os.environ.setdefault("DH_TUNE_CACHE", DEFAULT_CACHE)
-    progress(f"{args.workload} binary32, {args.steps} steps")
-    r32 = time_path(ctx, frame, dh.FP32, args.steps, max(1, args.warmup))
-    shape32 = ctx.last_config()
     fp64_steps = args.fp64_steps if args.fp64_steps is not None else max(1, args.steps // 2)
-    progress(f"{args.workload} binary64, {fp64_steps} steps")
-    r64 = time_path(ctx, frame, dh.FP64, fp64_steps, 1)
-    shape64 = ctx.last_config()
+    _, head, res = bench_frame(ctx, args.workload, args.steps, fp64_steps, max(1, args.warmup),
+                               frame)
+    r32, r64 = res["fp32"], res.get("fp64")
+    progress("checking the step's histograms against the stored oracle result")
+    parity = check_against_golden(args.workload, frame, r32, r64)
 
     value = pairs * args.steps / r32["wall_s"]
-    flops = pairs * FLOPS_PER_PAIR[kind]
-    ach32 = flops / (r32["kernel_ms_avg"] * 1e-3) / 1e12
-    ach64 = flops / (r64["kernel_ms_avg"] * 1e-3) / 1e12
+    ach32 = head["fp32"]["achieved_tflops"]
     traffic = traffic_for(args.workload, 0, None)
     line = {
         "metric": "pair-distances binned/sec (1 MI355X, FP32 vs FP64) + p50/p99 job latency",
@@ -598,20 +739,12 @@ def main():
             "r_max": frame.r_max,
             "pairs_per_step": pairs,
             "flops_per_pair": FLOPS_PER_PAIR[kind],
-            "launch_shape": shape32,
+            "launch_shape": head["fp32"]["launch_shape"],
             "tuned": not args.no_tune,
         },
         "latency_ms": {"p50": r32["step_ms_p50"], "p99": r32["step_ms_p99"]},
-        "fp64": {
-            "value": pairs * fp64_steps / r64["wall_s"],
-            "unit": "pairs/s",
-            "steps": fp64_steps,
-            "ms_per_step": r64["wall_s"] * 1e3 / fp64_steps,
-            "kernel_ms_avg": r64["kernel_ms_avg"],
-            "roofline_frac": ach64 / PEAK_TFLOPS[1],
-            "launch_shape": shape64,
-            "latency_ms": {"p50": r64["step_ms_p50"], "p99": r64["step_ms_p99"]},
-        },
+        "fp64": head.get("fp64"),
+        "parity": parity,
         "roofline": {
             "bound": "alu",
             "kernel": KERNEL_NAME,
@@ -621,23 +754,25 @@ def main():
             "frac": ach32 / PEAK_TFLOPS[0],
             "traffic": traffic,
             "kernel_ms_avg": r32["kernel_ms_avg"],
+            "flops_per_launch": pairs * FLOPS_PER_PAIR[kind],
         },
         "cpu_baseline": None,
     }
+    if args.ortho_steps > 0 and args.workload != "ortho100k":
+        _, sub, _ = bench_frame(ctx, "ortho100k", args.ortho_steps, max(1, args.ortho_steps // 2),
+                                3)
+        line["ortho100k"] = sub
     # PCIe-inclusive rate of the synchronous host-buffer entry point
     progress("host buffers")
     line["host_buffers"] = time_host_buffers(frame, dh.FP32, max(1, args.steps // 4))
     if args.serving_jobs > 0:
         progress(f"serving, {args.serving_jobs} jobs")
         line["serving"] = bench_serving(args.serving_jobs)
-        line["latency_ms"]["serving_p50"] = line["serving"]["shortest_remaining_work"]["p50_ms"]
-        line["latency_ms"]["serving_p99"] = line["serving"]["shortest_remaining_work"]["p99_ms"]
-    if args.triclinic_steps > 0 and args.workload != "triclinic1M":
-        progress("triclinic1M")
-        line["triclinic1M"] = bench_triclinic(ctx, args.triclinic_steps)
+        line["latency_ms"]["serving_p50"] = line["serving"]["continuous_batching"]["p50_ms"]
+        line["latency_ms"]["serving_p99"] = line["serving"]["continuous_batching"]["p99_ms"]
     if args.wide:
         progress("wide histograms")
-        line["wide"] = bench_wide(frame)
+        line["wide"] = bench_wide(workloads.ortho())
         progress("image search")
         line["image_search"] = bench_image_search()
     if args.trajectory_frames > 0:
@@ -649,7 +784,7 @@ def main():
         progress("CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(frame)
         progress("tuned CPU kernel")
-        line["cpu_tuned"] = cpu_tuned(frame)
+        line["cpu_tuned"] = cpu_tuned(workloads.ortho())
     ctx.close()
     del torch
     print(json.dumps(line), flush=True)

@@ -244,19 +244,24 @@ void dh_batch_destroy(dh_batch *batch);
 
 /* ---------------------------------------------------------------------------
  * Serving: a request loop that runs histogram jobs of mixed sizes, boxes and
- * bin counts on one GPU (continuous batching). A scheduler thread admits
- * queued jobs while a slot (a context with its own stream) is free and the
- * job's device footprint fits the HBM budget (see dh_sched_select for the
- * order), copies the admitted job's frame to the device and stages it. The
- * job's pair kernel is cut into launches of a bounded pair count, and the
- * same thread paces them onto the device one at a time, each from the
- * admitted job with the least work left (shortest remaining work first),
- * so a small job that
- * arrives while a huge one runs is computed at the huge job's next launch
- * boundary instead of after it. DH_SCHED_ARRIVAL selects arrival order for
- * both admission and launches instead. Completion is detected with events.
- * The paper's counterpart is its producer/consumer engine that feeds frames
- * to GPU workers through queues (Sec. 3.3).
+ * bin counts on one GPU with continuous batching. A scheduler thread admits
+ * queued jobs while a slot is free and the job's device footprint fits the
+ * HBM budget (see dh_sched_select for the order); an admitted job's frame is
+ * copied to the device, staged and zeroed on a setup stream while other
+ * jobs compute, and stays resident in its slot. Every pair-kernel launch is
+ * then built from the work items of all ready jobs that share a kernel
+ * variant (precision, minimum-image kind, accumulation mode, launch shape),
+ * taken in policy order up to a bounded amount of work per launch (about 10
+ * ms), with at most two launches on the device: a job admitted while others
+ * run joins the next launch, its items computed in the same launch as pieces
+ * of the running jobs. The default policy takes the job with the least work
+ * left first (shortest remaining work); DH_SCHED_ARRIVAL uses arrival order
+ * for admission and launches (with one slot: one job at a time, FIFO). When
+ * a launch carries a job's last items, its results are copied out after
+ * that launch; completion is detected with events. The paper's counterpart
+ * is its producer/consumer engine that feeds frames to GPU workers through
+ * queues (Sec. 3.3); here the unit handed to the device is a work item, so
+ * one launch computes several frames.
  */
 typedef struct dh_server dh_server;
 
@@ -265,9 +270,10 @@ typedef struct dh_server dh_server;
 #define DH_JOB_RUNNING 2
 
 /*
- * Creates a server on `device` with `max_inflight` (1..16) slots and an HBM
- * budget in bytes for the footprints of running jobs (coordinates, staged
- * copy, histograms, work list). head_wait_limit_s < 0 selects 1 second.
+ * Creates a server on `device` with `max_inflight` (1..64) slots (jobs
+ * resident at once) and an HBM budget in bytes for the footprints of
+ * resident jobs (coordinates, staged copy, histograms, out-of-range and
+ * pair counts). head_wait_limit_s < 0 selects 1 second.
  */
 int dh_server_create(int32_t device, int64_t hbm_budget_bytes, int32_t max_inflight,
                      double head_wait_limit_s, dh_server **server);
@@ -308,6 +314,13 @@ int dh_server_wait(dh_server *server, int64_t job_id, uint64_t *out, uint64_t *o
  * budget (bytes).
  */
 int dh_server_stats(const dh_server *server, int64_t *stats);
+
+/*
+ * Pair-kernel launches issued so far, how many of them carried the work
+ * items of more than one job, and the most jobs one launch carried.
+ */
+int dh_server_launch_stats(const dh_server *server, int64_t *launches,
+                           int64_t *shared_launches, int64_t *max_jobs_per_launch);
 
 /* Finishes running jobs, drops queued ones, releases the server. */
 void dh_server_destroy(dh_server *server);
@@ -457,6 +470,19 @@ int dh_ctx_set_launch_pairs(dh_ctx *ctx, int64_t max_pairs);
  */
 int dh_ctx_profile(dh_ctx *ctx, int32_t enable);
 int dh_ctx_profile_read(dh_ctx *ctx, double *kernel_ms, int64_t *launches);
+
+/*
+ * Pairs that went through the 27-image search (Sec. 2.3, the neighbouring
+ * cells beyond half the smallest width; Sec. 4.1, the three-fold loop over
+ * neighbouring boxes) in the last single-frame histogram on ctx
+ * (dh_histo_async or dh_histo through ctx): the pairs whose Eq. 5 reduced
+ * vector is at least half the shortest lattice vector long, counted by the
+ * pair kernel. 0 when that call ran no search (r_max below half the smallest
+ * width, or no triclinic cell) or the frame was added into an accumulating
+ * sum. The caller must have waited for that call's stream; this reads the
+ * device counter with a blocking copy. DH_EINVAL for a null argument.
+ */
+int dh_ctx_searched_pairs(dh_ctx *ctx, uint64_t *searched);
 
 #ifdef __cplusplus
 }

@@ -26,6 +26,8 @@ struct dh_ctx {
   hipStream_t own_stream = nullptr;
   void *d_staged = nullptr;
   size_t staged_cap = 0;
+  void *d_keys = nullptr;  // sort keys of spatially sorted frames
+  size_t keys_cap = 0;
   void *d_blob = nullptr;
   size_t blob_cap = 0;
   void *h_blob = nullptr;
@@ -74,6 +76,9 @@ struct dh_ctx {
   bool profile = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
   size_t prof_used = 0;
+  // image-search pair counter of the last single-frame call (in the work
+  // blob), null when that call ran no image search
+  unsigned long long *searched_dev = nullptr;
 };
 
 struct dh_batch {
@@ -95,6 +100,17 @@ struct dh_batch {
   void *d_blob = nullptr;
   size_t off_frames = 0, off_items = 0, off_counters = 0;
   std::vector<Group> groups;
+  // spatially sorted frames (staged by their own sort, not the batched
+  // staging kernel): frame index, input, staged copy, species offsets
+  struct Sorted {
+    int32_t frame;
+    const double *d_in;
+    void *staged;
+    std::vector<int64_t> offsets;
+    FrameParams fp;
+  };
+  std::vector<Sorted> sorted;
+  void *d_keys = nullptr;
   int64_t n_items = 0;
   double total_pairs = 0;
   hipGraph_t graph = nullptr;
@@ -180,6 +196,7 @@ int frame_consts(int32_t box_type, const double *box, double r_max, int32_t n_bi
   std::memset(&fp, 0, sizeof fp);
   fp.n_bins = n_bins;
   fp.s = static_cast<double>(n_bins) / r_max;
+  fp.s32 = static_cast<float>(fp.s);
   int kind = kBoxNone;
   if (box_type != DH_BOX_NONE) {
     fp.ax = box[0]; fp.bx = box[3]; fp.by = box[4];
@@ -214,6 +231,7 @@ int frame_consts(int32_t box_type, const double *box, double r_max, int32_t n_bi
         fp.ryz32[c] = static_cast<float>((fp.L[c + 1] / fp.L[0]) * (fp.L[c + 1] / fp.L[0]));
     const double B[6] = {fp.ax, fp.bx, fp.by, fp.cx, fp.cy, fp.cz};
     for (int c = 0; c < 6; ++c) fp.Bk[c] = static_cast<float>(B[c] * fp.s / kTwo32);
+    for (int c = 0; c < 6; ++c) fp.cell32[c] = static_cast<float>(B[c]);
     if (fp.ax > 0)
       for (int c = 0; c < 5; ++c) fp.Bn[c] = static_cast<float>(B[c + 1] / fp.ax);
     for (int q = 0; q < kShifts; ++q)
@@ -346,7 +364,8 @@ BaseConfig base_config(size_t lds_per_block, int precision, const Knobs &k, int 
   c.jchunk = c.tj;
   // two j-tiles, plus one entry of pad: the look-ahead read of j may touch
   // the entry just past the second tile
-  b.tile_bytes = (2 * static_cast<size_t>(c.tj) + 1) * coord_bytes(precision);
+  b.tile_bytes = (2 * static_cast<size_t>(c.tj) + 1) * staged_point_bytes(precision, kind);
+  if (kind == kBoxTricSorted) b.tile_bytes += kSortedBoxBytes;
   // the search kernels keep their queues after the histogram; counting them
   // with the tiles leaves the histogram budget below them
   if (kind == kBoxTricSearch) b.tile_bytes += search_queue_bytes(precision, c.threads, c.r);
@@ -630,6 +649,22 @@ struct FrameJob {
   bool accumulate = false;  // add into d_out instead of overwriting it
 };
 
+// Stages a frame's coordinates into the context's scratch (spatially sorted
+// frames: the sort keys in the context's key buffer).
+int stage_job(dh_ctx *ctx, hipStream_t st, const FrameJob &job, const FrameParams &fp) {
+  const int64_t n = job.offsets[job.n_species];
+  if (job.kind == kBoxTricSorted) {
+    int rc = ensure_device(ctx, &ctx->d_keys, &ctx->keys_cap,
+                           static_cast<size_t>(sort_keys_count(n)) * sizeof(uint64_t));
+    if (rc) return rc;
+    DH_HIP(ctx, launch_stage_sorted(job.d_coords, ctx->d_staged, n, job.offsets, job.n_species,
+                                    fp, static_cast<uint64_t *>(ctx->d_keys), st));
+    return DH_OK;
+  }
+  DH_HIP(ctx, launch_stage(job.precision, job.kind, job.d_coords, ctx->d_staged, n, fp, st));
+  return DH_OK;
+}
+
 // Plans and enqueues one frame with the given knobs: stage (optional), zero,
 // pair kernel (between e0 and e1 when given), out-of-range counts.
 int run_frame(dh_ctx *ctx, hipStream_t st, const FrameJob &job, const Knobs &k, bool stage,
@@ -690,17 +725,38 @@ int run_frame(dh_ctx *ctx, hipStream_t st, const FrameJob &job, const Knobs &k, 
   const bool oor_flush = job.d_oor && L.mode != kModeGlobal;
   fp.oor = oor_flush ? job.d_oor : nullptr;
   fp.oor_by_flush = oor_flush ? 1 : 0;
-  const BlobLayout lay = blob_layout(1, items.size(), pairs.size(), n_launches);
+  // counters: one work counter per launch, then (8-byte aligned) the count
+  // of image-searched pairs; the upload or the zero kernel clears them all
+  const size_t n_work_counters = (n_launches + 1) / 2 * 2;
+  const size_t n_counters = n_work_counters + 2;
+  const BlobLayout lay = blob_layout(1, items.size(), pairs.size(), n_counters);
+  // the counter's device address goes into the frame constants, so the blob
+  // is allocated before they are uploaded (a new allocation is never taken
+  // for an unchanged plan)
+  if (lay.total > ctx->blob_cap) ctx->blob_last.clear();
+  {
+    int rc0 = ensure_device(ctx, &ctx->d_blob, &ctx->blob_cap, lay.total);
+    if (rc0) return rc0;
+  }
+  fp.searched = job.kind == kBoxTricSearch && !job.accumulate
+                    ? reinterpret_cast<unsigned long long *>(
+                          static_cast<char *>(ctx->d_blob) + lay.counter +
+                          n_work_counters * sizeof(int32_t))
+                    : nullptr;
+  ctx->searched_dev = fp.searched;
   std::vector<FrameParams> frames(1, fp);
   // an unchanged plan is reused when the zero kernel below resets the counters
   int rc = upload_blob(ctx, st, lay, frames, items, pairs, !job.accumulate);
   if (rc) return rc;
   char *db = static_cast<char *>(ctx->d_blob);
-  if (stage) DH_HIP(ctx, launch_stage(job.precision, job.kind, job.d_coords, ctx->d_staged, n, fp, st));
+  if (stage) {
+    const int rc_stage = stage_job(ctx, st, job, fp);
+    if (rc_stage) return rc_stage;
+  }
   if (!job.accumulate)
     DH_HIP(ctx, launch_zero(job.d_out, static_cast<int64_t>(n_hist) * fp.n_bins,
                             reinterpret_cast<int32_t *>(db + lay.counter),
-                            static_cast<int32_t>(n_launches), fp.oor,
+                            static_cast<int32_t>(n_counters), fp.oor,
                             reinterpret_cast<const uint64_t *>(db + lay.pairs), n_hist, st));
   const int grid = std::max(1, std::min<int>(L.grid, static_cast<int>(items.size())));
   if (ctx->hold) {
@@ -841,7 +897,11 @@ int tune_frame(dh_ctx *ctx, hipStream_t st, const FrameJob &job, const std::stri
   const int64_t n = job.offsets[job.n_species];
   FrameParams fp = job.fp;
   fp.coords = ctx->d_staged;
-  DH_HIP(ctx, launch_stage(job.precision, job.kind, job.d_coords, ctx->d_staged, n, fp, st));
+  (void)n;
+  {
+    const int rc_stage = stage_job(ctx, st, job, fp);
+    if (rc_stage) return rc_stage;
+  }
   hipEvent_t e0, e1;
   DH_HIP(ctx, hipEventCreate(&e0));
   DH_HIP(ctx, hipEventCreate(&e1));
@@ -954,6 +1014,23 @@ LaunchPlan default_launch(int n_cu, size_t lds_per_block, int precision, const F
   return p;
 }
 
+LaunchPlan serve_launch(int n_cu, size_t lds_per_block, int precision, const FrameParams &fp,
+                        uint64_t total_pairs, int threads) {
+  Knobs k = default_knobs(precision);
+  k.threads = threads;
+  const Launch L = choose_launch(n_cu, lds_per_block, precision, fp, total_pairs, k);
+  LaunchPlan p;
+  p.cfg = L.cfg;
+  p.mode = L.mode;
+  p.win = L.win;
+  p.n_sweeps = L.n_sweeps;
+  p.stride = L.stride;
+  p.grid = L.grid;
+  p.noclamp = L.noclamp;
+  p.lds = L.lds;
+  return p;
+}
+
 int thread_fail(int code, const char *fmt, ...) {
   va_list ap;
   va_start(ap, fmt);
@@ -973,15 +1050,16 @@ int zero_u64(uint64_t *p, int64_t n, hipStream_t st) {
 }
 
 size_t ctx_device_bytes(const dh_ctx *ctx) {
-  return ctx->staged_cap + ctx->blob_cap + ctx->in_cap + ctx->out_cap;
+  return ctx->staged_cap + ctx->blob_cap + ctx->in_cap + ctx->out_cap + ctx->keys_cap;
 }
 
 void ctx_release_scratch(dh_ctx *ctx) {
   if (hipSetDevice(ctx->device) != hipSuccess) return;
-  void **bufs[4] = {&ctx->d_staged, &ctx->d_blob, reinterpret_cast<void **>(&ctx->d_in),
-                    reinterpret_cast<void **>(&ctx->d_out)};
-  size_t *caps[4] = {&ctx->staged_cap, &ctx->blob_cap, &ctx->in_cap, &ctx->out_cap};
-  for (int k = 0; k < 4; ++k) {
+  void **bufs[5] = {&ctx->d_staged, &ctx->d_blob, reinterpret_cast<void **>(&ctx->d_in),
+                    reinterpret_cast<void **>(&ctx->d_out), &ctx->d_keys};
+  size_t *caps[5] = {&ctx->staged_cap, &ctx->blob_cap, &ctx->in_cap, &ctx->out_cap,
+                     &ctx->keys_cap};
+  for (int k = 0; k < 5; ++k) {
     if (*bufs[k]) (void)hipFree(*bufs[k]);
     *bufs[k] = nullptr;
     *caps[k] = 0;
@@ -1019,6 +1097,11 @@ static int dh_batch_launch_direct(dh_batch *b, hipStream_t st) {
   const FrameParams *d_frames = reinterpret_cast<const FrameParams *>(db + b->off_frames);
   int32_t *counters = reinterpret_cast<int32_t *>(db + b->off_counters);
   DH_HIP(ctx, launch_stage_batch(b->precision, d_frames, b->n_frames, b->max_points, st));
+  // spatially sorted frames one after the other (one key buffer)
+  for (const dh_batch::Sorted &q : b->sorted)
+    DH_HIP(ctx, launch_stage_sorted(q.d_in, q.staged, q.fp.n_points, q.offsets.data(),
+                                    static_cast<int32_t>(q.offsets.size() - 1), q.fp,
+                                    static_cast<uint64_t *>(b->d_keys), st));
   DH_HIP(ctx, launch_zero_batch(d_frames, b->n_frames, b->max_words, counters,
                                 static_cast<int32_t>(b->groups.size()), st));
   for (size_t k = 0; k < b->groups.size(); ++k) {
@@ -1080,6 +1163,7 @@ void dh_ctx_destroy(dh_ctx *ctx) {
   if (hipSetDevice(ctx->device) == hipSuccess) {
     (void)hipDeviceSynchronize();
     if (ctx->d_staged) (void)hipFree(ctx->d_staged);
+    if (ctx->d_keys) (void)hipFree(ctx->d_keys);
     if (ctx->d_blob) (void)hipFree(ctx->d_blob);
     if (ctx->d_in) (void)hipFree(ctx->d_in);
     if (ctx->d_out) (void)hipFree(ctx->d_out);
@@ -1131,10 +1215,9 @@ int histo_job(dh_ctx *ctx, hipStream_t stream, const double *d_coords, const int
   job.d_out = d_out;
   job.d_oor = accumulate ? nullptr : d_out_of_range;
   job.accumulate = accumulate;
-  job.kind = frame_consts(box_type, box, r_max, n_bins, job.fp);
-  if (precision == DH_FP32 && job.kind == kBoxOrtho && job.fp.L[0] == job.fp.L[1] &&
-      job.fp.L[1] == job.fp.L[2])
-    job.fp.box = job.kind = kBoxCube;
+  job.kind = staged_kind(frame_consts(box_type, box, r_max, n_bins, job.fp), precision,
+                         job.fp.L, n);
+  job.fp.box = job.kind;
   for (int s = 0; s < n_species; ++s) {
     const uint64_t a = static_cast<uint64_t>(offsets[s + 1] - offsets[s]);
     job.total += a * (a > 0 ? a - 1 : 0) / 2;
@@ -1142,7 +1225,8 @@ int histo_job(dh_ctx *ctx, hipStream_t stream, const double *d_coords, const int
       job.total += a * static_cast<uint64_t>(offsets[t + 1] - offsets[t]);
   }
   rc = ensure_device(ctx, &ctx->d_staged, &ctx->staged_cap,
-                     std::max<size_t>(1, static_cast<size_t>(n)) * coord_bytes(precision));
+                     std::max<size_t>(1, static_cast<size_t>(n)) *
+                         staged_point_bytes(precision, job.kind));
   if (rc) return rc;
 
   Knobs k = default_knobs(precision);
@@ -1314,16 +1398,18 @@ int dh_batch_create(dh_ctx *ctx, const dh_frame_desc *frames, int32_t n_frames, 
     const int64_t n = d.offsets[d.n_species];
     if (!d.d_out || (n > 0 && !d.d_coords)) return fail(ctx, DH_EINVAL, "frame %d: null pointer", f);
     FrameInfo &fi = info[f];
-    int kind = frame_consts(d.box_type, d.box, d.r_max, d.n_bins, fi.fp);
-    if (precision == DH_FP32 && kind == kBoxOrtho && fi.fp.L[0] == fi.fp.L[1] &&
-        fi.fp.L[1] == fi.fp.L[2])
-      fi.fp.box = kind = kBoxCube;
+    const int kind =
+        staged_kind(frame_consts(d.box_type, d.box, d.r_max, d.n_bins, fi.fp), precision,
+                    fi.fp.L, n);
+    fi.fp.box = kind;
     fi.offsets.assign(d.offsets, d.offsets + d.n_species + 1);
-    if (d.n_bins <= base.win_max) {
+    // the bin window that fits beside this kind's j-tiles
+    const BaseConfig fbase = base_config(ctx->lds_per_block, precision, bk, kind);
+    if (d.n_bins <= fbase.win_max) {
       fi.fp.win = d.n_bins;
       fi.fp.n_sweeps = 1;
     } else {
-      fi.fp.n_sweeps = static_cast<int32_t>((d.n_bins + base.win_max - 1) / base.win_max);
+      fi.fp.n_sweeps = static_cast<int32_t>((d.n_bins + fbase.win_max - 1) / fbase.win_max);
       fi.fp.win = (d.n_bins + fi.fp.n_sweeps - 1) / fi.fp.n_sweeps;
       fi.mode = kModeSweep;
     }
@@ -1333,9 +1419,9 @@ int dh_batch_create(dh_ctx *ctx, const dh_frame_desc *frames, int32_t n_frames, 
       fi.fp.n_sweeps = 1;
     }
     const double tb = t_bound(fi.fp);
-    if (base.noclamp && fi.mode == kModeLds && tb > 0) {
+    if (fbase.noclamp && fi.mode == kModeLds && tb > 0) {
       fi.slots = static_cast<int64_t>(tb * (1.0 + 1e-4)) + 2;
-      fi.noclamp_ok = fi.slots <= base.win_max + kDump;
+      fi.noclamp_ok = fi.slots <= fbase.win_max + kDump;
     }
     fi.fp.n_points = n;
     fi.fp.n_hist = d.n_species * (d.n_species + 1) / 2;
@@ -1415,7 +1501,9 @@ int dh_batch_create(dh_ctx *ctx, const dh_frame_desc *frames, int32_t n_frames, 
   size_t staged_bytes = 0;
   for (int32_t f = 0; f < n_frames; ++f) {
     staged_off[f] = staged_bytes;
-    staged_bytes += align_up(std::max<int64_t>(1, info[f].fp.n_points) * coord_bytes(precision), 256);
+    staged_bytes += align_up(std::max<int64_t>(1, info[f].fp.n_points) *
+                                 staged_point_bytes(precision, info[f].fp.box),
+                             256);
     b->max_points = std::max(b->max_points, info[f].fp.n_points);
     b->max_words = std::max(b->max_words, static_cast<int64_t>(info[f].fp.n_hist) * frames[f].n_bins);
     b->max_hist = std::max(b->max_hist, info[f].fp.n_hist);
@@ -1439,11 +1527,24 @@ int dh_batch_create(dh_ctx *ctx, const dh_frame_desc *frames, int32_t n_frames, 
   }
   char *db = static_cast<char *>(b->d_blob);
   std::vector<char> host(blob_bytes, 0);
+  int64_t max_sorted = 0;
   for (int32_t f = 0; f < n_frames; ++f) {
     FrameParams fp = info[f].fp;
     fp.coords = static_cast<char *>(b->d_staged) + staged_off[f];
     fp.pairs = reinterpret_cast<const uint64_t *>(db + off_pairs) + pairs_base[f];
     std::memcpy(host.data() + b->off_frames + f * sizeof(FrameParams), &fp, sizeof fp);
+    if (fp.box == kBoxTricSorted) {
+      b->sorted.push_back({f, frames[f].d_coords, const_cast<void *>(fp.coords),
+                           info[f].offsets, fp});
+      max_sorted = std::max(max_sorted, fp.n_points);
+    }
+  }
+  if (max_sorted > 0 &&
+      hipMalloc(&b->d_keys, static_cast<size_t>(sort_keys_count(max_sorted)) * 8) !=
+          hipSuccess) {
+    (void)hipGetLastError();
+    b->d_keys = nullptr;
+    return bail(fail(ctx, DH_ENOMEM, "hipMalloc of the sort keys failed"));
   }
   if (!items.empty())
     std::memcpy(host.data() + b->off_items, items.data(), items.size() * sizeof(WorkItem));
@@ -1505,6 +1606,7 @@ void dh_batch_destroy(dh_batch *b) {
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->d_staged) (void)hipFree(b->d_staged);
     if (b->d_blob) (void)hipFree(b->d_blob);
+    if (b->d_keys) (void)hipFree(b->d_keys);
   }
   (void)hipGetLastError();
   delete b;
@@ -1545,6 +1647,17 @@ int dh_ctx_set_launch_pairs(dh_ctx *ctx, int64_t max_pairs) {
   if (max_pairs > 0 && max_pairs < (int64_t{1} << 24))
     return fail(ctx, DH_EINVAL, "max_pairs must be 0 or at least 2^24");
   ctx->launch_pairs = static_cast<uint64_t>(max_pairs);
+  return DH_OK;
+}
+
+int dh_ctx_searched_pairs(dh_ctx *ctx, uint64_t *searched) {
+  if (!ctx || !searched) return DH_EINVAL;
+  *searched = 0;
+  if (!ctx->searched_dev) return DH_OK;
+  DH_HIP(ctx, hipSetDevice(ctx->device));
+  unsigned long long v = 0;
+  DH_HIP(ctx, hipMemcpy(&v, ctx->searched_dev, sizeof v, hipMemcpyDeviceToHost));
+  *searched = v;
   return DH_OK;
 }
 

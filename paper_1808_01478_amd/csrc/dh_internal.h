@@ -13,7 +13,38 @@ enum BoxKind : int32_t {
   kBoxTric = 2,        // Eq. 5 reduction only (r_max below half the smallest width)
   kBoxTricSearch = 3,  // Eq. 5 reduction, then the 27 neighbouring images
   kBoxCube = 4,        // binary32 only: orthorhombic cell with equal edges
+  // binary32 only: triclinic cell without image search, points spatially
+  // sorted within each species at staging (frames of at least kSortMinPoints)
+  kBoxTricSorted = 5,
 };
+
+// Largest species count of a frame (the staging kernels take the offsets by
+// value).
+constexpr int kMaxSpeciesStage = 64;
+// binary32 triclinic frames (no image search) with at least this many points
+// are staged in spatial order (kBoxTricSorted)
+constexpr int64_t kSortMinPoints = int64_t{1} << 16;
+
+// The minimum-image kind the kernels use for a frame: the geometric kind of
+// frame_constants, with the binary32 special cases (equal orthorhombic
+// edges; large triclinic frames staged in spatial order).
+inline int staged_kind(int kind, int precision, const double L[3], int64_t n_points) {
+  if (precision != 0) return kind;
+  if (kind == kBoxOrtho && L[0] == L[1] && L[1] == L[2]) return kBoxCube;
+  if (kind == kBoxTric && n_points >= kSortMinPoints) return kBoxTricSorted;
+  return kind;
+}
+
+// Bytes per staged point (binary64 double4; binary32 float4, two of them
+// for spatially sorted frames) and the sort workspace of a frame.
+inline size_t staged_point_bytes(int precision, int kind) {
+  return precision != 0 ? 32 : (kind == kBoxTricSorted ? 32 : 16);
+}
+inline int64_t sort_keys_count(int64_t n) {
+  int64_t p = 2048;
+  while (p < n) p <<= 1;
+  return p;
+}
 
 // How a pair kernel accumulates its counts.
 enum HistMode : int32_t {
@@ -72,7 +103,19 @@ struct FrameParams {
   int32_t noclamp;     // 1: every t of a full block fits below `stride` slots
   float qskip32;       // binary32 q (t units) below which no image is nearer
   double qskip64;      // binary64 q below which the reduced vector is nearest
+  // image search: pairs that went through the 27-image search are added here
+  // (device, 8-byte aligned) unless null
+  unsigned long long *searched;
+  // spatially sorted binary32 frames: the cell rows (ax bx by cx cy cz) and
+  // s = n_bins / r_max, rounded to binary32
+  float cell32[6];
+  float s32;
 };
+
+// LDS of a spatially sorted frame's pair kernel besides its two j-tiles:
+// the bounding boxes of the tiles' groups of 64 points (two tiles, at most
+// four groups each, eight words per box)
+constexpr size_t kSortedBoxBytes = 2 * 4 * 8 * sizeof(uint32_t);
 
 // One unit of work: particles [i0, i1) of the frame against [j0, j1), for
 // histogram `hist`, bin window `sweep`; flags: kItemDiag, kItemFull.
@@ -188,6 +231,12 @@ __host__ __device__ inline int64_t emit_row(const HistRows &r, int32_t h, int32_
 }
 
 // host-side launchers (dh_kernels.hip)
+// binary32 staging of a kBoxTricSorted frame: the points of every species
+// in Morton order of their wrapped fractional coordinates (keys: a workspace
+// of sort_keys_count(n) words), two float4 per point in `out`.
+hipError_t launch_stage_sorted(const double *in, void *out, int64_t n, const int64_t *offsets,
+                               int32_t n_species, const FrameParams &fp, uint64_t *keys,
+                               hipStream_t st);
 hipError_t launch_stage(int precision, int box_kind, const double *in, void *out, int64_t n,
                         const FrameParams &fp, hipStream_t st);
 // zeroes out[n_words] and counters[n_counters]; with oor, sets oor[h] =
@@ -241,6 +290,10 @@ struct LaunchPlan {
 };
 LaunchPlan default_launch(int n_cu, size_t lds_per_block, int precision, const FrameParams &fp,
                           uint64_t total_pairs);
+// The same with a given workgroup size (0 = automatic): launches that mix
+// frames need one shape for all of them.
+LaunchPlan serve_launch(int n_cu, size_t lds_per_block, int precision, const FrameParams &fp,
+                        uint64_t total_pairs, int threads);
 // Records the message of a failure that has no context (read back by
 // dh_ctx_last_error(NULL); a fixed thread-local buffer, so it allocates
 // nothing) and returns code.

@@ -291,6 +291,34 @@ __device__ __forceinline__ uint32_t med3_u32(uint32_t x, uint32_t lo, uint32_t h
   return r;
 }
 
+// Minimum and maximum over the 64 lanes of a wave, as a wave-uniform value.
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, static_cast<uint32_t>(__shfl_xor(v, o)));
+  return static_cast<uint32_t>(uni(static_cast<int>(v)));
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, static_cast<uint32_t>(__shfl_xor(v, o)));
+  return static_cast<uint32_t>(uni(static_cast<int>(v)));
+}
+
+// Lattice shift n (in cell vectors, one axis) shared by every pair of a
+// group of i-points with fixed-point fractions in [ilo, ihi] and a group of
+// j-points in [jlo, jhi]: the Eq. 5 wrap of u_j - u_i is the n with
+// u_j - u_i - n 2^32 in [-2^31, 2^31), i.e. floor((u_j - u_i + 2^31) / 2^32),
+// the same for the whole interval [jlo - ihi, jhi - ilo] iff both ends give
+// the same n. Returns false when they differ (or a group is empty).
+__device__ __forceinline__ bool group_shift(uint32_t ilo, uint32_t ihi, uint32_t jlo,
+                                            uint32_t jhi, int &n) {
+  if (ilo > ihi || jlo > jhi) return false;
+  const int64_t dlo = static_cast<int64_t>(jlo) - static_cast<int64_t>(ihi) + (int64_t{1} << 31);
+  const int64_t dhi = static_cast<int64_t>(jhi) - static_cast<int64_t>(ilo) + (int64_t{1} << 31);
+  const int64_t nlo = dlo >> 32, nhi = dhi >> 32;  // arithmetic shifts: floor
+  n = static_cast<int>(nlo);
+  return nlo == nhi;
+}
+
 // Triclinic reduced vector (t units) from packed fractional words.
 __device__ __forceinline__ void tric_vec32(uint64_t ab_j, uint64_t neg_ab_i, float zi, float zj,
                                            const Geo32 &g, float &dx, float &dy, float &dz) {
@@ -502,10 +530,142 @@ __global__ void stage32_kernel(const double *__restrict__ in, float4 *__restrict
     out[i] = stage_point32<BOX>(in[3 * i], in[3 * i + 1], in[3 * i + 2], p);
 }
 
+// --------------------------------------------------------------------------
+// Spatially sorted binary32 staging (triclinic cells without image search)
+// --------------------------------------------------------------------------
+//
+// The points of every species are put in the order of a Morton curve over
+// their wrapped fractional coordinates (9 bits per axis), ties by input
+// index, so that 64 consecutive points are close together in the cell. The
+// pair kernel then finds, for most pairs of such groups, one lattice shift
+// that is the Eq. 5 wrap of every pair of the two groups (see run_item).
+// The order is a permutation within each species, so the histograms are
+// those of the input; the sort is a bitonic network on 64-bit keys
+// (species : Morton code : input index), which makes the order unique.
+
+struct SpeciesOffsets {
+  int64_t v[kMaxSpeciesStage + 1];
+};
+
+// Morton code of three 9-bit integers: bit b of axis a goes to bit 3b + a.
+__device__ __forceinline__ uint64_t morton9(uint32_t a, uint32_t b, uint32_t c) {
+  uint64_t m = 0;
+#pragma unroll
+  for (int bit = 0; bit < 9; ++bit)
+    m |= (static_cast<uint64_t>((a >> bit) & 1u) << (3 * bit)) |
+         (static_cast<uint64_t>((b >> bit) & 1u) << (3 * bit + 1)) |
+         (static_cast<uint64_t>((c >> bit) & 1u) << (3 * bit + 2));
+  return m;
+}
+
+// wrapped fractional coordinate as 32-bit fixed point (as fixfrac)
+__device__ __forceinline__ uint32_t fix32(double f) {
+  const double w = f - floor(f);
+  return static_cast<uint32_t>(static_cast<uint64_t>(w * 4294967296.0));
+}
+
+__global__ void sort_keys_kernel(const double *__restrict__ in, int64_t n, int64_t npad,
+                                 SpeciesOffsets off, int32_t k, FrameParams p,
+                                 uint64_t *__restrict__ keys) {
+  const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < npad;
+       i += step) {
+    if (i >= n) {
+      keys[i] = ~0ull;
+      continue;
+    }
+    int s = 0;
+    while (s + 1 < k && off.v[s + 1] <= i) ++s;
+    const double x = in[3 * i], y = in[3 * i + 1], z = in[3 * i + 2];
+    const uint32_t ua = fix32(fma(z, p.h13, fma(y, p.h12, x * p.h11)));
+    const uint32_t ub = fix32(fma(z, p.h23, y * p.h22));
+    const uint32_t uc = fix32(z * p.h33);
+    const uint64_t m = morton9(ua >> 23, ub >> 23, uc >> 23);
+    keys[i] = (static_cast<uint64_t>(s) << 58) | (m << 31) | static_cast<uint64_t>(i);
+  }
+}
+
+constexpr int kBitonicBlock = 2048;  // keys sorted in LDS by one workgroup of 1024
+
+__device__ __forceinline__ void bitonic_cas(uint64_t &a, uint64_t &b, bool ascending) {
+  if ((a > b) == ascending) {
+    const uint64_t t = a;
+    a = b;
+    b = t;
+  }
+}
+
+// All stages k <= kBitonicBlock of each block (first == true), or the steps
+// j < kBitonicBlock of stage k (first == false), in LDS.
+__global__ __launch_bounds__(1024) void bitonic_local_kernel(uint64_t *__restrict__ keys,
+                                                             int64_t k_stage, int first) {
+  __shared__ uint64_t sk[kBitonicBlock];
+  const int t = threadIdx.x;
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kBitonicBlock;
+  sk[t] = keys[base + t];
+  sk[t + 1024] = keys[base + t + 1024];
+  const int64_t k_lo = first ? 2 : k_stage, k_hi = first ? kBitonicBlock : k_stage;
+  for (int64_t kk = k_lo; kk <= k_hi; kk <<= 1) {
+    for (int j = kk / 2 < kBitonicBlock / 2 ? static_cast<int>(kk / 2) : kBitonicBlock / 2;
+         j > 0; j >>= 1) {
+      __syncthreads();
+      const int lo = 2 * j * (t / j) + (t % j);
+      const bool asc = ((base + lo) & kk) == 0;
+      bitonic_cas(sk[lo], sk[lo + j], asc);
+    }
+  }
+  __syncthreads();
+  keys[base + t] = sk[t];
+  keys[base + t + 1024] = sk[t + 1024];
+}
+
+// One step j >= kBitonicBlock of stage k over the whole array.
+__global__ void bitonic_global_kernel(uint64_t *__restrict__ keys, int64_t npad, int64_t j,
+                                      int64_t k_stage) {
+  const int64_t half = npad / 2;
+  const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < half;
+       t += step) {
+    const int64_t lo = 2 * j * (t / j) + (t % j);
+    uint64_t a = keys[lo], b = keys[lo + j];
+    bitonic_cas(a, b, (lo & k_stage) == 0);
+    keys[lo] = a;
+    keys[lo + j] = b;
+  }
+}
+
+// Staged entry of the sorted position p: the fixed-point fractional words
+// (a, b, c, c) as for the unsorted binary32 triclinic staging, then the
+// Cartesian position of the same wrapped point relative to the cell centre,
+// B (u - 1/2) with u the fixed-point fraction read back exactly, so the two
+// formats describe one point.
+__global__ void stage_sorted_kernel(const double *__restrict__ in,
+                                    const uint64_t *__restrict__ keys, int64_t n, FrameParams p,
+                                    float4 *__restrict__ out) {
+  const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t q = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; q < n;
+       q += step) {
+    const int64_t i = static_cast<int64_t>(keys[q] & 0x7FFFFFFFull);
+    const double x = in[3 * i], y = in[3 * i + 1], z = in[3 * i + 2];
+    const uint32_t ua = fix32(fma(z, p.h13, fma(y, p.h12, x * p.h11)));
+    const uint32_t ub = fix32(fma(z, p.h23, y * p.h22));
+    const uint32_t uc = fix32(z * p.h33);
+    const double va = ua * 0x1p-32 - 0.5, vb = ub * 0x1p-32 - 0.5, vc = uc * 0x1p-32 - 0.5;
+    const float cx = static_cast<float>(fma(p.cx, vc, fma(p.bx, vb, p.ax * va)));
+    const float cy = static_cast<float>(fma(p.cy, vc, p.by * vb));
+    const float cz = static_cast<float>(p.cz * vc);
+    out[2 * q] = make_float4(__uint_as_float(ua), __uint_as_float(ub), __uint_as_float(uc),
+                             __uint_as_float(uc));
+    out[2 * q + 1] = make_float4(cx, cy, cz, 0.f);
+  }
+}
+
 // Batched staging: blockIdx.y selects the frame.
 template <int PREC>
 __global__ void stage_batch_kernel(const FrameParams *__restrict__ frames) {
   const FrameParams &p = frames[blockIdx.y];
+  // spatially sorted frames are staged by their own sort
+  if (PREC == 0 && p.box == kBoxTricSorted) return;
   const int64_t n = p.n_points;
   const double *__restrict__ in = p.in;
   const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
@@ -597,6 +757,105 @@ __device__ __forceinline__ void flush_hist(uint32_t *hist, const PairKernelArgs 
   }
 }
 
+// One j-tile of a spatially sorted frame for one wave. For every group of 64
+// j-points of the tile and every slice r of the wave's i-points, the two
+// groups' bounding boxes (fixed-point fractions) decide whether one lattice
+// shift n is the Eq. 5 wrap of all their pairs (group_shift on each axis).
+// If it is, the pairs take the short path: the Cartesian difference to the
+// i-point shifted by B n, with no conversion and no cell matrix per pair
+// (3 subtractions, q, root, bin). Otherwise they take the fixed-point path
+// of unsorted triclinic frames. The choice depends only on the two groups
+// (species-aligned blocks of 64 points), not on the launch shape, so every
+// launch shape, batch and server path gives the same counts.
+template <int R, int MODE, bool DIAG, bool CLAMP, typename CountT>
+__device__ __forceinline__ void sorted_tile(
+    const float4 *__restrict__ tb, const uint32_t *__restrict__ boxes, int jt, int js,
+    int jcount, int wbase, int lane, const FrameParams *F, const Geo32 &g, const float (&xi)[R],
+    const float (&zi)[R], const float (&cxi)[R], const float (&cyi)[R], const float (&czi)[R],
+    const uint32_t (&ibox)[R][6], const uint64_t (&nab)[R], const uint64_t (&nzz)[R / 2],
+    const uint32_t (&lo)[R], const uint32_t (&lob)[R], uint32_t hi, uint32_t hib,
+    CountT &count_t) {
+  (void)xi;
+  (void)zi;
+  const float ax = uni(F->cell32[0]), bx = uni(F->cell32[1]), by = uni(F->cell32[2]);
+  const float cx = uni(F->cell32[3]), cy = uni(F->cell32[4]), cz = uni(F->cell32[5]);
+  const float s32 = uni(F->s32);
+  const uint64_t *__restrict__ tb64 = reinterpret_cast<const uint64_t *>(tb);
+  constexpr uint32_t kAll = (1u << R) - 1u;
+  for (int g0 = js & ~63; g0 < jcount; g0 += 64) {
+    const int j_begin = max(js, g0), j_end = min(jcount, g0 + 64);
+    const uint32_t *gb = boxes + (g0 >> 6) * 8;
+    uint32_t jb[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) jb[q] = static_cast<uint32_t>(uni(static_cast<int>(gb[q])));
+    uint32_t fast = 0;
+    float sx[R], sy[R], sz[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      int na = 0, nb = 0, nc = 0;
+      const bool f = group_shift(ibox[r][0], ibox[r][3], jb[0], jb[3], na) &&
+                     group_shift(ibox[r][1], ibox[r][4], jb[1], jb[4], nb) &&
+                     group_shift(ibox[r][2], ibox[r][5], jb[2], jb[5], nc);
+      if (f) {
+        fast |= 1u << r;
+        const float fa = static_cast<float>(na), fb = static_cast<float>(nb),
+                    fc = static_cast<float>(nc);
+        sx[r] = cxi[r] + (fa * ax + fb * bx + fc * cx);
+        sy[r] = cyi[r] + (fb * by + fc * cy);
+        sz[r] = czi[r] + fc * cz;
+      } else {
+        sx[r] = sy[r] = sz[r] = 0.f;
+      }
+    }
+    auto mask = [&](int r, int j, uint32_t &l, uint32_t &lb) {
+      l = lo[r];
+      lb = lob[r];
+      if constexpr (DIAG) {
+        const bool up = jt + j > wbase + r * 64 + lane;
+        l = up ? l : hi;
+        lb = up ? lb : hib;
+      }
+    };
+    auto fast_pair = [&](int r, const float4 &C, int j) {
+      uint32_t l, lb;
+      mask(r, j, l, lb);
+      const float dx = C.x - sx[r], dy = C.y - sy[r], dz = C.z - sz[r];
+      const float q = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+      count_t(__float_as_uint(fmaf(__builtin_amdgcn_sqrtf(q), s32, kMagic32)), l, lb);
+    };
+    auto slow_pair = [&](int r, uint64_t ab, uint64_t cc, int j) {
+      uint32_t l, lb;
+      mask(r, j, l, lb);
+      const uint64_t dcc = cc + nzz[r / 2];
+      const float fcd = static_cast<float>(
+          static_cast<int32_t>(static_cast<uint32_t>(r % 2 == 0 ? dcc : dcc >> 32)));
+      count_t(bits32_packed_c<kBoxTric>(ab, nab[r], fcd, g), l, lb);
+    };
+    if (fast == kAll) {
+      for (int j = j_begin; j < j_end; ++j) {
+        const float4 C = tb[2 * j + 1];
+#pragma unroll
+        for (int r = 0; r < R; ++r) fast_pair(r, C, j);
+      }
+    } else if (fast == 0) {
+      for (int j = j_begin; j < j_end; ++j) {
+        const uint64_t ab = tb64[4 * j], cc = tb64[4 * j + 1];
+#pragma unroll
+        for (int r = 0; r < R; ++r) slow_pair(r, ab, cc, j);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (fast & (1u << r)) {
+          for (int j = j_begin; j < j_end; ++j) fast_pair(r, tb[2 * j + 1], j);
+        } else {
+          for (int j = j_begin; j < j_end; ++j) slow_pair(r, tb64[4 * j], tb64[4 * j + 1], j);
+        }
+      }
+    }
+  }
+}
+
 // CLAMP = false: the host proved that every t of this frame is below the LDS
 // stride and the block has no invalid lanes, so the bin index needs no clamp
 // (out-of-range pairs land in slots [n_bins, stride) that are never flushed).
@@ -618,6 +877,10 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
   constexpr bool SWEEP = MODE == kModeSweep;
   constexpr bool GLOBAL = MODE == kModeGlobal;
   constexpr bool SEARCH = BOX == kBoxTricSearch;
+  // spatially sorted frames: two float4 per point (fixed-point words, then
+  // the Cartesian position relative to the cell centre)
+  constexpr bool SORTED = BOX == kBoxTricSorted;
+  constexpr int EPJ = SORTED ? 2 : 1;
   const V *__restrict__ X = static_cast<const V *>(F->coords);
   const G g = Geo<T>::load(F);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -652,13 +915,28 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
   T xi[R], yi[R], zi[R];
   const uint32_t hi = static_cast<uint32_t>(win + lane);  // discard slot of this lane
   uint32_t lo[R];
+  // sorted frames: Cartesian i-positions, and the fixed-point bounding box of
+  // each 64-particle slice r of the wave (its valid lanes): lo a, b, c, hi a,
+  // b, c; an empty slice has lo > hi
+  [[maybe_unused]] float cxi[R], cyi[R], czi[R];
+  [[maybe_unused]] uint32_t ibox[R][6];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int i = wbase + r * 64 + lane;
     const bool ok = i < w.i1;
-    const V p = X[ok ? i : w.i0];
+    const V p = X[EPJ * (ok ? i : w.i0)];
     xi[r] = p.x; yi[r] = p.y; zi[r] = p.z;
     lo[r] = ok ? 0u : hi;
+    if constexpr (SORTED) {
+      const V c = X[EPJ * (ok ? i : w.i0) + 1];
+      cxi[r] = c.x; cyi[r] = c.y; czi[r] = c.z;
+      const uint32_t u[3] = {__float_as_uint(p.x), __float_as_uint(p.y), __float_as_uint(p.z)};
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        ibox[r][ax] = wave_min_u32(ok ? u[ax] : 0xFFFFFFFFu);
+        ibox[r][3 + ax] = wave_max_u32(ok ? u[ax] : 0u);
+      }
+    }
   }
   // binary32 clamp bounds in bin bits: the guard word below bin 0 for a
   // lane that counts, its discard slot for one that must not
@@ -792,6 +1070,10 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
         count_t(bin_bits32(__builtin_amdgcn_sqrtf(q)), v ? 0u : hi, v ? kMagicBits - 1u : hib);
       else
         count_t(t_guarded64(q, g.s, big_bins), v ? 0u : hi, 0u);
+      // one atomic per 64 searched pairs at most (cnt is wave-uniform)
+      unsigned long long *const searched = F->searched;
+      if (searched != nullptr && lane == 0)
+        atomicAdd(searched, static_cast<unsigned long long>(cnt));
       head += cnt;
       if (head >= cap) head -= cap;
       qn -= cnt;
@@ -805,18 +1087,57 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
   __builtin_amdgcn_s_waitcnt(kWaitVm0);
 
   V pre = {};
-  if (tid < tj && w.j0 + tid < w.j1) pre = X[w.j0 + tid];
+  [[maybe_unused]] V preC = {};
+  // sorted frames: bounding boxes of the tiles' groups of 64 j-points, after
+  // the two tiles (eight words per group)
+  [[maybe_unused]] uint32_t *const tboxes = reinterpret_cast<uint32_t *>(tile + 2 * tj * EPJ);
+  if (tid < tj && w.j0 + tid < w.j1) {
+    pre = X[EPJ * (w.j0 + tid)];
+    if constexpr (SORTED) preC = X[EPJ * (w.j0 + tid) + 1];
+  }
   int buf = 0;
   for (int jt = w.j0; jt < w.j1; jt += tj, buf ^= 1) {
-    if (tid < tj) tile[buf * tj + tid] = pre;
+    if (tid < tj) {
+      tile[(buf * tj + tid) * EPJ] = pre;
+      if constexpr (SORTED) {
+        tile[(buf * tj + tid) * EPJ + 1] = preC;
+        // the box of this wave's 64 j (tiles start on group boundaries of
+        // the species, so the group is the same whatever the launch shape)
+        const bool ok = jt + tid < w.j1;
+        const uint32_t u[3] = {__float_as_uint(pre.x), __float_as_uint(pre.y),
+                               __float_as_uint(pre.z)};
+        uint32_t b6[6];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          b6[ax] = wave_min_u32(ok ? u[ax] : 0xFFFFFFFFu);
+          b6[3 + ax] = wave_max_u32(ok ? u[ax] : 0u);
+        }
+        if (lane < 6) {
+          uint32_t v = b6[0];
+#pragma unroll
+          for (int q = 1; q < 6; ++q) v = lane == q ? b6[q] : v;
+          tboxes[(buf * 4 + (tid >> 6)) * 8 + lane] = v;
+        }
+      }
+    }
     __syncthreads();
     {
       const int jn = jt + tj + tid;
-      if (tid < tj && jn < w.j1) pre = X[jn];
+      if (tid < tj && jn < w.j1) {
+        pre = X[EPJ * jn];
+        if constexpr (SORTED) preC = X[EPJ * jn + 1];
+      }
     }
     const int jcount = min(tj, w.j1 - jt);
     int js = 0;
     if constexpr (DIAG) js = max(0, min(jcount, wbase + 1 - jt));
+    if constexpr (SORTED) {
+      if (wave_active && js < jcount)
+        sorted_tile<R, MODE, DIAG, CLAMP>(tile + buf * tj * EPJ, tboxes + buf * 32, jt, js,
+                                          jcount, wbase, lane, F, g, xi, zi, cxi, cyi, czi,
+                                          ibox, nab, nzz, lo, lob, hi, hib, count_t);
+      continue;
+    }
     if (wave_active && js < jcount) {
       const V *__restrict__ tb = tile + buf * tj;
       // periodic binary32: j as its packed (b:a) and (c:c) words, one
@@ -972,7 +1293,11 @@ __global__ __launch_bounds__(max_threads<BOX>()) void pairs_kernel(PairKernelArg
   // the histogram follows the two j-tiles and a guard of kGuardBytes: one
   // word per copy for binary32 bin -1 (t < 1/4), added to bin 0 on flush.
   // The host's allocation has one spare coordinate entry there.
-  uint32_t *hist = reinterpret_cast<uint32_t *>(smem + 2 * a.tj * sizeof(V) + kGuardBytes);
+  // (sorted frames: two entries per j, then the tiles' group boxes)
+  constexpr int EPJ = BOX == kBoxTricSorted ? 2 : 1;
+  const size_t tiles_bytes = 2 * static_cast<size_t>(a.tj) * EPJ * sizeof(V) +
+                             (BOX == kBoxTricSorted ? kSortedBoxBytes : 0);
+  uint32_t *hist = reinterpret_cast<uint32_t *>(smem + tiles_bytes + kGuardBytes);
   const int tid = threadIdx.x;
   // lane-interleaved sub-histogram copies: lanes of one instruction that
   // hit the same bin use different words (and banks) when copies > 1
@@ -1092,6 +1417,9 @@ PairFn pick_box(int box) {
     case kBoxCube:
       if constexpr (sizeof(T) == 4) return pairs_kernel<T, R, kBoxCube, SW>;
       return pairs_kernel<T, R, kBoxOrtho, SW>;
+    case kBoxTricSorted:
+      if constexpr (sizeof(T) == 4) return pairs_kernel<T, R, kBoxTricSorted, SW>;
+      return pairs_kernel<T, R, kBoxTric, SW>;
     default: return pairs_kernel<T, R, kBoxTricSearch, SW>;
   }
 }
@@ -1123,6 +1451,30 @@ int grid_for(int64_t n, int threads) {
 
 }  // namespace
 
+hipError_t launch_stage_sorted(const double *in, void *out, int64_t n, const int64_t *offsets,
+                               int32_t n_species, const FrameParams &fp, uint64_t *keys,
+                               hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  if (n_species < 1 || n_species > kMaxSpeciesStage || n > 0x7FFFFFFFll)
+    return hipErrorInvalidValue;
+  const int64_t npad = sort_keys_count(n);
+  SpeciesOffsets off;
+  for (int s = 0; s <= kMaxSpeciesStage; ++s) off.v[s] = offsets[s < n_species ? s : n_species];
+  const int threads = 256;
+  sort_keys_kernel<<<grid_for(npad, threads), threads, 0, st>>>(in, n, npad, off, n_species, fp,
+                                                                keys);
+  const int blocks = static_cast<int>(npad / kBitonicBlock);
+  bitonic_local_kernel<<<blocks, 1024, 0, st>>>(keys, 0, 1);
+  for (int64_t kk = 2 * kBitonicBlock; kk <= npad; kk <<= 1) {
+    for (int64_t j = kk / 2; j >= kBitonicBlock; j >>= 1)
+      bitonic_global_kernel<<<grid_for(npad / 2, threads), threads, 0, st>>>(keys, npad, j, kk);
+    bitonic_local_kernel<<<blocks, 1024, 0, st>>>(keys, kk, 0);
+  }
+  stage_sorted_kernel<<<grid_for(n, threads), threads, 0, st>>>(in, keys, n, fp,
+                                                                static_cast<float4 *>(out));
+  return hipGetLastError();
+}
+
 hipError_t launch_stage(int precision, int box_kind, const double *in, void *out, int64_t n,
                         const FrameParams &fp, hipStream_t st) {
   if (n <= 0) return hipSuccess;
@@ -1136,6 +1488,7 @@ hipError_t launch_stage(int precision, int box_kind, const double *in, void *out
       case kBoxNone: stage32_kernel<kBoxNone><<<grid, threads, 0, st>>>(in, o, n, fp); break;
       case kBoxOrtho:
       case kBoxCube: stage32_kernel<kBoxOrtho><<<grid, threads, 0, st>>>(in, o, n, fp); break;
+      case kBoxTricSorted: return hipErrorInvalidValue;  // launch_stage_sorted stages these
       default: stage32_kernel<kBoxTric><<<grid, threads, 0, st>>>(in, o, n, fp); break;
     }
   }

@@ -45,6 +45,8 @@ SIGNATURES = {
     "dh_server_set_policy": ([_vp, _i32], ctypes.c_int),
     "dh_server_wait": ([_vp, _i64, _vp, _vp, _vp], ctypes.c_int),
     "dh_server_stats": ([_vp, _vp], ctypes.c_int),
+    "dh_server_launch_stats": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+                                ctypes.POINTER(_i64)], ctypes.c_int),
     "dh_server_destroy": ([_vp], None),
     "dh_sched_select": ([_vp, _vp, _vp, _i32, _i64, _i32, _f64, _vp], ctypes.c_int32),
     "dh_cpu_histo": ([_vp, _vp, _i32, _i32, _vp, _f64, _i32, _i32, _i32, _vp, _vp], ctypes.c_int),
@@ -60,6 +62,7 @@ SIGNATURES = {
     "dh_ctx_set_launch_pairs": ([_vp, _i64], ctypes.c_int),
     "dh_ctx_profile": ([_vp, _i32], ctypes.c_int),
     "dh_ctx_profile_read": ([_vp, ctypes.POINTER(_f64), ctypes.POINTER(_i64)], ctypes.c_int),
+    "dh_ctx_searched_pairs": ([_vp, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
 }
 
 
@@ -269,6 +272,13 @@ class Context:
                self.handle)
         return float(ms.value), int(n.value)
 
+    def searched_pairs(self) -> int:
+        """dh_ctx_searched_pairs: pairs of the last single-frame call that went
+        through the 27-image search (wait for its stream first)."""
+        v = ctypes.c_uint64()
+        _check(LIB.dh_ctx_searched_pairs(self.handle, ctypes.byref(v)), self.handle)
+        return int(v.value)
+
     def pair_t_async(self, d_coords, box_type: int, box, r_max: float, n_bins: int,
                      precision: int, d_pi, d_pj, d_t, stream=None) -> None:
         """dh_pair_t_async on torch device tensors (int32 indices, float64 output)."""
@@ -397,8 +407,14 @@ class Server:
     def stats(self) -> dict:
         st = np.zeros(6, np.int64)
         _check(LIB.dh_server_stats(self.handle, _np_ptr(st)))
-        return dict(zip(("submitted", "completed", "failed", "max_running", "peak_bytes",
-                         "budget_bytes"), (int(v) for v in st)))
+        out = dict(zip(("submitted", "completed", "failed", "max_running", "peak_bytes",
+                        "budget_bytes"), (int(v) for v in st)))
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(LIB.dh_server_launch_stats(self.handle, ctypes.byref(a), ctypes.byref(b),
+                                          ctypes.byref(c)))
+        out.update(launches=int(a.value), shared_launches=int(b.value),
+                   max_jobs_per_launch=int(c.value))
+        return out
 
     def close(self):
         if getattr(self, "handle", None):

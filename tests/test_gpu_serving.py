@@ -1,7 +1,9 @@
 """The serving loop on the GPU: every job's result in a concurrent mix is
-bit-identical to the same job run alone (same kernels, integer sums), binary64
-jobs equal the oracle, the budget bounds the admitted footprints, and bad
-jobs fail alone."""
+bit-identical to the same job run alone (same kernels, integer sums), also
+when the jobs' work items share pair-kernel launches (continuous batching),
+binary64 jobs equal the oracle, jobs of the serving workload's full sizes
+are exact, the budget bounds the admitted footprints, and bad jobs fail
+alone."""
 import math
 import time
 
@@ -30,6 +32,14 @@ def alone(frame, prec):
                     frame.n_bins, prec)
 
 
+def alone_with_oor(frame, prec):
+    """(histograms, out-of-range counts) of one dh_histo_async call."""
+    import paper_1808_01478_amd as dh
+    from gpu_util import run_gpu
+    with dh.Context(0) as ctx:
+        return run_gpu(ctx, frame, prec)
+
+
 def test_mix_equals_alone_and_oracle():
     import paper_1808_01478_amd as dh
     jobs = job_mix()
@@ -42,9 +52,9 @@ def test_mix_equals_alone_and_oracle():
     assert st["completed"] == len(jobs) and st["failed"] == 0
     assert st["max_running"] >= 2, st          # jobs did overlap
     for (f, p), (h, oor, times) in zip(jobs, results):
-        ref = alone(f, p)
+        ref, ref_oor = alone_with_oor(f, p)
         assert np.array_equal(h, ref), f"{f.name} prec={p}: mix differs from alone"
-        assert list(h.sum(axis=1).astype(np.int64) + oor.astype(np.int64)) == f.hist_pairs()
+        assert np.array_equal(oor, ref_oor), f"{f.name} prec={p}: out-of-range differs"
         assert times[2] >= times[1] >= 0 and times[0] >= 0
     for (f, p), (h, _, _) in list(zip(jobs, results))[:6]:
         if p == 1:
@@ -61,11 +71,8 @@ def test_budget_back_pressure():
             probe.append(s1.wait(s1.submit(f.coords, f.offsets, f.box_type, f.box, f.r_max,
                                            f.n_bins, p))[0])
     def footprint(f, p):
-        windows = min(64, (f.n_bins + 8999) // 9000)
-        work = f.n * (f.n - 1) // 2 * windows
-        launches = work // (3 << 33) + 1
-        return (f.n * 24 + f.n_hist * f.n_bins * 8 + f.n * (32 if p else 16) + (4 << 20)
-                + f.n_hist * 8 + ((work >> 21) + launches * 3 * 2048) * 32)
+        # coordinates, staged copy, histograms, out-of-range and pair counts
+        return f.n * 24 + f.n * (32 if p else 16) + f.n_hist * f.n_bins * 8 + 2 * f.n_hist * 8
     sizes = [footprint(f, p) for f, p in jobs]
     budget = int(max(sizes) * 1.2)
     with dh.Server(0, hbm_budget_bytes=budget, max_inflight=4, head_wait_limit_s=0.05) as srv:
@@ -81,8 +88,8 @@ def test_budget_back_pressure():
 def test_bad_jobs_fail_alone():
     import paper_1808_01478_amd as dh
     f = workloads.random_frame(601, [500, 300], workloads.BOX_ORTHO, n_bins=100)
-    # the small job needs about 4 MB (mostly work-list slack), the big one
-    # about 16 MB: an 8 MB budget admits one and refuses the other
+    # the small job needs about 40 kB, the big one about 11.6 MB (coordinates,
+    # staged copy, histogram): an 8 MB budget admits one and refuses the other
     with dh.Server(0, hbm_budget_bytes=8 << 20, max_inflight=2) as srv:
         good = srv.submit(f.coords, f.offsets, f.box_type, f.box, f.r_max, f.n_bins, 0)
         with pytest.raises(dh.DisthistError) as e:
@@ -180,3 +187,78 @@ def test_launch_order_policy(policy):
     else:
         # (the small kernel may run beside the huge job's last launch)
         assert end_small >= 0.8 * end_big
+
+
+def test_job_admitted_mid_run_shares_a_launch():
+    """A small job submitted while a large one of the same kind runs joins
+    the next launch (continuous batching: the launch carries work items of
+    both frames), and both results equal their runs alone, out-of-range
+    counts included."""
+    import paper_1808_01478_amd as dh
+    big = workloads.random_frame(631, [600_000, 300_000], workloads.BOX_ORTHO,
+                                 box=workloads.ortho_box(80.0, 84.0, 88.0), r_max=30.0,
+                                 n_bins=4000)
+    small = workloads.random_frame(632, [3000, 1500], workloads.BOX_ORTHO,
+                                   box=workloads.ortho_box(12.0, 13.0, 14.0), r_max=6.0,
+                                   n_bins=1000)
+    with dh.Server(0, hbm_budget_bytes=8 << 30, max_inflight=4) as srv:
+        b = srv.submit(big.coords, big.offsets, big.box_type, big.box, big.r_max, big.n_bins, 0)
+        t0 = time.perf_counter()
+        while srv.status(b) == dh.JOB_QUEUED and time.perf_counter() - t0 < 5.0:
+            time.sleep(0.001)
+        time.sleep(0.03)
+        sid = srv.submit(small.coords, small.offsets, small.box_type, small.box, small.r_max,
+                         small.n_bins, 0)
+        hs, os_, _ = srv.wait(sid)
+        still_running = srv.status(b) == dh.JOB_RUNNING
+        hb, ob, _ = srv.wait(b)
+        st = srv.stats()
+    print(f"\n[case] launches {st['launches']}, shared {st['shared_launches']}, "
+          f"most jobs in one launch {st['max_jobs_per_launch']}", flush=True)
+    assert still_running, "the small job waited for the whole large job"
+    assert st["shared_launches"] >= 1 and st["max_jobs_per_launch"] >= 2, st
+    ref_s, ref_so = alone_with_oor(small, 0)
+    ref_b, ref_bo = alone_with_oor(big, 0)
+    assert np.array_equal(hs, ref_s) and np.array_equal(os_, ref_so)
+    assert np.array_equal(hb, ref_b) and np.array_equal(ob, ref_bo)
+
+
+def test_serving_workload_sizes():
+    """Jobs of the serving workload's sizes in one server: a 2,000,000-point
+    triclinic job with 50,000 bins (two bin windows), a 1,000,000-point job
+    without a box, an orthorhombic job, and small ones, submitted at once and
+    sharing launches; each equals its run alone (histograms and out-of-range
+    counts), and the binary64 job of 150,000 points equals the oracle."""
+    import paper_1808_01478_amd as dh
+    rng = np.random.Generator(np.random.PCG64(641))
+    vol = 2_000_000 / workloads.DENSITY
+    tric_box = workloads.random_triclinic_cell(rng, vol)
+    jobs = [
+        (workloads.random_frame(642, [1_000_000, 600_000, 400_000], workloads.BOX_TRICLINIC,
+                                box=tric_box, r_max=0.49 * workloads.min_width(tric_box),
+                                n_bins=50_000), 0),
+        (workloads.random_frame(643, [1_000_000], workloads.BOX_NONE,
+                                extent=(1_000_000 / workloads.DENSITY) ** (1 / 3),
+                                n_bins=10_000), 0),
+        (workloads.random_frame(644, [90_000, 60_000], workloads.BOX_ORTHO,
+                                box=workloads.ortho_box(40.0, 44.0, 48.0), r_max=20.0,
+                                n_bins=1000), 1),
+    ]
+    jobs += [(f, int(p)) for f, p in job_mix(seed=645, n_jobs=6, n_hi=50_000)]
+    print(f"\n[case] serving sizes: {[f.n for f, _ in jobs]}", flush=True)
+    with dh.Server(0, hbm_budget_bytes=8 << 30, max_inflight=8) as srv:
+        ids = [srv.submit(f.coords, f.offsets, f.box_type, f.box, f.r_max, f.n_bins, p)
+               for f, p in jobs]
+        res = [srv.wait(i) for i in ids]
+        st = srv.stats()
+    assert st["completed"] == len(jobs) and st["failed"] == 0
+    print(f"[case] launches {st['launches']}, shared {st['shared_launches']}", flush=True)
+    for (f, p), (h, o, _) in zip(jobs, res):
+        print(f"[case] alone {f.name} N={f.n} bins={f.n_bins} prec={p}", flush=True)
+        ref_h, ref_o = alone_with_oor(f, p)
+        assert np.array_equal(h, ref_h), f"{f.name}: served differs from alone"
+        assert np.array_equal(o, ref_o), f"{f.name}: out-of-range differs from alone"
+    f, p = jobs[2]
+    print(f"[case] oracle {f.name} N={f.n}", flush=True)
+    ref = oracle.frame_histogram(f)
+    assert np.array_equal(res[2][0], ref.hist) and np.array_equal(res[2][1], ref.out_of_range)
