@@ -172,6 +172,29 @@ int dh_histo_async(dh_ctx *ctx, dh_stream stream, const double *d_coords,
                    uint64_t *d_out, uint64_t *d_out_of_range);
 
 /*
+ * dh_histo_async without any allocation, for callers that cannot allocate
+ * device or pinned memory: work under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc. No context: the call runs on the
+ * current HIP device, enqueues its kernels on `stream` and returns without
+ * waiting. Arguments, layouts and validation as for dh_histo_async; the
+ * counts are the same as dh_histo_async's (built-in launch shape, no tuning).
+ * Scratch: one fixed device array per device, 48 MiB, held by every device
+ * the library runs on until the process ends (frame constants, work list,
+ * counters and the staged coordinates, 16 bytes per point in binary32 and 32
+ * in binary64: about 1.4 million binary64 or 2.9 million binary32 points;
+ * binary32 triclinic frames of at least 65,536 points are staged in spatial
+ * order with 32 bytes per point and sort keys: about 1.0 million points).
+ * A frame that does not fit gets DH_EINVAL before anything is enqueued.
+ * Calls share that array: calls that overlap on one device (several streams
+ * or host threads) race and must be serialised by the caller. Failures
+ * without a context: message via dh_ctx_last_error(NULL).
+ */
+int dh_histo_noalloc(dh_stream stream, const double *d_coords, const int64_t *offsets,
+                     int32_t n_species, int32_t box_type, const double *box, double r_max,
+                     int32_t n_bins, int32_t precision, uint64_t *d_out,
+                     uint64_t *d_out_of_range);
+
+/*
  * Scaled distances t = r * n_bins / r_max of explicit particle pairs,
  * evaluated with the device arithmetic that the histogram kernels use for
  * the given precision and box (Algorithm 1 without the increment): exactly

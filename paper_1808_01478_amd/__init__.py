@@ -11,7 +11,7 @@ _EXPORTS = (
     "LIB_PATH", "KNOB_NAMES", "Server", "sched_select", "TUNE_CACHED", "TUNE_OFF", "TUNE_ON", "check_args",
     "exported_symbols", "histo", "n_hist", "version", "MODE_LDS", "MODE_SWEEP", "MODE_GLOBAL",
     "JOB_DONE", "JOB_QUEUED", "JOB_RUNNING", "SCHED_SHORTEST", "SCHED_ARRIVAL", "Trajectory",
-    "cpu_histo",
+    "cpu_histo", "histo_noalloc",
 )
 __all__ = list(_EXPORTS)
 

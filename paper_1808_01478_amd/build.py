@@ -20,7 +20,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libdisthist.so")
-SOURCES = ["dh_api.hip", "dh_kernels.hip", "dh_server.hip", "dh_traj.hip"]
+SOURCES = ["dh_api.hip", "dh_kernels.hip", "dh_server.hip", "dh_traj.hip", "dh_noalloc.hip"]
 ARCH = os.environ.get("DH_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -33,6 +33,8 @@ SIGNATURES = {
                        ctypes.c_int),
     "dh_pair_t_async": ([_vp, _vp, _vp, _i64, _i32, _vp, _f64, _i32, _i32, _vp, _vp, _i64, _vp],
                         ctypes.c_int),
+    "dh_histo_noalloc": ([_vp, _vp, _vp, _i32, _i32, _vp, _f64, _i32, _i32, _vp, _vp],
+                         ctypes.c_int),
     "dh_batch_create": ([_vp, _vp, _i32, _i32, _i32, ctypes.POINTER(_vp)], ctypes.c_int),
     "dh_batch_launch": ([_vp, _vp], ctypes.c_int),
     "dh_batch_info": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32), ctypes.POINTER(_f64)],
@@ -147,6 +149,20 @@ def check_args(coords, offsets, box_type: int, box, r_max: float, n_bins: int,
     b = _host_box(box)
     return int(LIB.dh_check_args(_np_ptr(c), _np_ptr(o), len(o) - 1, int(box_type), _np_ptr(b),
                                  float(r_max), int(n_bins), int(precision)))
+
+
+def histo_noalloc(d_coords, offsets, box_type: int, box, r_max: float, n_bins: int,
+                  precision: int, d_out, d_out_of_range=None, stream=None) -> None:
+    """dh_histo_noalloc on torch device tensors (the current device): the
+    allocation-free variant of Context.histo_async."""
+    o = _offsets(offsets)
+    b = _host_box(box)
+    _check(LIB.dh_histo_noalloc(_stream_handle(stream), ctypes.c_void_p(d_coords.data_ptr()),
+                                _np_ptr(o), len(o) - 1, int(box_type), _np_ptr(b),
+                                float(r_max), int(n_bins), int(precision),
+                                ctypes.c_void_p(d_out.data_ptr()),
+                                None if d_out_of_range is None
+                                else ctypes.c_void_p(d_out_of_range.data_ptr())))
 
 
 def histo(coords, offsets, box_type: int, box, r_max: float, n_bins: int,
