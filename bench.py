@@ -257,6 +257,7 @@ def bench_trajectory_file(ctx, n_frames: int = 48, interval: int = 8):
     del xs
     offs = [0, 60_000, n]
     pairs = n * (n - 1) // 2 * n_frames
+    threads = len(os.sched_getaffinity(0))
     with dh.Trajectory(path) as t:
         # warm-up on the first interval (kernel loading), then the timed run
         t.histo(ctx, offs, 20.0, 10_000, dh.FP32, res + ".warm", interval=interval,
@@ -264,13 +265,21 @@ def bench_trajectory_file(ctx, n_frames: int = 48, interval: int = 8):
         t0 = time.perf_counter()
         done = t.histo(ctx, offs, 20.0, 10_000, dh.FP32, res, interval=interval)
         wall = time.perf_counter() - t0
-    for q in (path, res, res + ".warm"):
+        # the same with a CPU worker on the host's threads beside the GPU
+        t0 = time.perf_counter()
+        done_h, cpu_frames = t.histo_hybrid(ctx, offs, 20.0, 10_000, dh.FP32, res + ".hyb",
+                                            threads - 1 if threads > 1 else 1, interval=interval)
+        wall_h = time.perf_counter() - t0
+    for q in (path, res, res + ".warm", res + ".hyb"):
         os.remove(q)
     os.rmdir(d)
     return {"workload": f"trajectory file: {n_frames} frames of 100,000 points in breathing "
                         f"orthorhombic cells, r_max 20, 10,000 bins, binary32, sums over "
                         f"{interval}-frame intervals", "intervals": done,
-            "value": pairs / wall, "unit": "pairs/s", "ms_per_frame": wall * 1e3 / n_frames}
+            "value": pairs / wall, "unit": "pairs/s", "ms_per_frame": wall * 1e3 / n_frames,
+            "hybrid_cpu_worker": {"value": pairs / wall_h, "unit": "pairs/s",
+                                  "intervals": done_h, "frames_on_cpu": cpu_frames,
+                                  "cpu_threads": threads - 1 if threads > 1 else 1}}
 
 
 def bench_trajectory(ctx, n_frames: int, steps: int):

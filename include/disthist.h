@@ -428,6 +428,28 @@ int dh_traj_histo(dh_ctx *ctx, dh_traj *t, const int64_t *species_offsets, int32
                   int64_t frame_end, int64_t interval, const char *results_path,
                   int64_t max_intervals, int64_t *intervals_done);
 
+/*
+ * dh_traj_histo with a CPU worker beside the GPU (the paper's hybrid of CPU
+ * and GPU workers, Sec. 3.3 and Table 4): a host thread runs dh_cpu_histo on
+ * `cpu_threads` threads over whole frames taken from the end of each
+ * interval while the GPU takes them from the start, and the interval's
+ * record adds both (binary64 counts are the same either way; binary32 frames
+ * computed on the CPU follow the canonical sequence in binary32 and stay
+ * within the binary32 tolerance). The CPU takes a frame only when its
+ * measured time per frame (before the first one: 2e8 pairs per second per
+ * thread) is below the GPU's measured time for the other unclaimed frames of
+ * the interval, so it cannot hold an interval back by much more than one GPU
+ * frame; flags = DH_HYBRID_GREEDY lifts that rule (every frame the CPU
+ * worker can claim, for tests). cpu_threads = 0 is dh_traj_histo.
+ * *cpu_frames (may be NULL) receives the number of frames the CPU computed.
+ */
+#define DH_HYBRID_GREEDY 1
+int dh_traj_histo_hybrid(dh_ctx *ctx, dh_traj *t, const int64_t *species_offsets,
+                         int32_t n_species, double r_max, int32_t n_bins, int32_t precision,
+                         int64_t frame_begin, int64_t frame_end, int64_t interval,
+                         const char *results_path, int64_t max_intervals, int32_t cpu_threads,
+                         int32_t flags, int64_t *intervals_done, int64_t *cpu_frames);
+
 /* ---------------------------------------------------------------------------
  * Launch tuning. The launch shape of a frame (i-particles per lane, LDS
  * sub-histogram copies, j-tile length, unclamped interior blocks, workgroups

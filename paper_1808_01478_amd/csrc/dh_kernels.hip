@@ -780,7 +780,6 @@ __device__ __forceinline__ void sorted_tile(
   const float ax = uni(F->cell32[0]), bx = uni(F->cell32[1]), by = uni(F->cell32[2]);
   const float cx = uni(F->cell32[3]), cy = uni(F->cell32[4]), cz = uni(F->cell32[5]);
   const float s32 = uni(F->s32);
-  const uint64_t *__restrict__ tb64 = reinterpret_cast<const uint64_t *>(tb);
   constexpr uint32_t kAll = (1u << R) - 1u;
   for (int g0 = js & ~63; g0 < jcount; g0 += 64) {
     const int j_begin = max(js, g0), j_end = min(jcount, g0 + 64);
@@ -831,25 +830,56 @@ __device__ __forceinline__ void sorted_tile(
           static_cast<int32_t>(static_cast<uint32_t>(r % 2 == 0 ? dcc : dcc >> 32)));
       count_t(bits32_packed_c<kBoxTric>(ab, nab[r], fcd, g), l, lb);
     };
+    // Every loop reads the next j before the current j's atomics: LDS
+    // operations complete in order, so a read issued after the atomics would
+    // wait for all of them. At the end of the tile the look-ahead read
+    // touches the entry just past it (the next tile or the box area), never
+    // used. The entry pointer lives in a VGPR so both reads use immediate
+    // offsets (the zero is opaque to the compiler on purpose).
+    int vzero;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(vzero));
+    auto run_j = [&](auto &&body, int part) {
+      // part 1: the Cartesian float4 of each j; part 0: its fixed-point words
+      const float4 *cp = tb + 2 * j_begin + part + vzero;
+      float4 pa = cp[0];
+      int j = j_begin;
+      for (; j + 1 < j_end; j += 2, cp += 4) {
+        const float4 pb = cp[2];
+        __builtin_amdgcn_sched_barrier(0);
+        body(pa, j);
+        pa = cp[4];
+        __builtin_amdgcn_sched_barrier(0);
+        body(pb, j + 1);
+      }
+      if (j < j_end) body(pa, j);
+    };
+    auto words = [](const float4 &e, uint64_t &ab, uint64_t &cc) {
+      ab = (static_cast<uint64_t>(__float_as_uint(e.y)) << 32) | __float_as_uint(e.x);
+      cc = (static_cast<uint64_t>(__float_as_uint(e.w)) << 32) | __float_as_uint(e.z);
+    };
     if (fast == kAll) {
-      for (int j = j_begin; j < j_end; ++j) {
-        const float4 C = tb[2 * j + 1];
+      run_j([&](const float4 &C, int j) {
 #pragma unroll
         for (int r = 0; r < R; ++r) fast_pair(r, C, j);
-      }
+      }, 1);
     } else if (fast == 0) {
-      for (int j = j_begin; j < j_end; ++j) {
-        const uint64_t ab = tb64[4 * j], cc = tb64[4 * j + 1];
+      run_j([&](const float4 &A, int j) {
+        uint64_t ab, cc;
+        words(A, ab, cc);
 #pragma unroll
         for (int r = 0; r < R; ++r) slow_pair(r, ab, cc, j);
-      }
+      }, 0);
     } else {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if (fast & (1u << r)) {
-          for (int j = j_begin; j < j_end; ++j) fast_pair(r, tb[2 * j + 1], j);
+          run_j([&](const float4 &C, int j) { fast_pair(r, C, j); }, 1);
         } else {
-          for (int j = j_begin; j < j_end; ++j) slow_pair(r, tb64[4 * j], tb64[4 * j + 1], j);
+          run_j([&](const float4 &A, int j) {
+            uint64_t ab, cc;
+            words(A, ab, cc);
+            slow_pair(r, ab, cc, j);
+          }, 0);
         }
       }
     }
@@ -1038,6 +1068,7 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
   constexpr int cap = queue_cap(R);
   V *const wq = queue + wave * cap;
   int head = 0, qn = 0;
+  [[maybe_unused]] uint64_t n_searched = 0;  // pairs this wave searched in this item
   [[maybe_unused]] T qskip;
   if constexpr (sizeof(T) == 4)
     qskip = uni(F->qskip32);
@@ -1070,10 +1101,7 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
         count_t(bin_bits32(__builtin_amdgcn_sqrtf(q)), v ? 0u : hi, v ? kMagicBits - 1u : hib);
       else
         count_t(t_guarded64(q, g.s, big_bins), v ? 0u : hi, 0u);
-      // one atomic per 64 searched pairs at most (cnt is wave-uniform)
-      unsigned long long *const searched = F->searched;
-      if (searched != nullptr && lane == 0)
-        atomicAdd(searched, static_cast<unsigned long long>(cnt));
+      n_searched += cnt;  // wave-uniform; added to the frame's count once per item
       head += cnt;
       if (head >= cap) head -= cap;
       qn -= cnt;
@@ -1272,8 +1300,13 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
       }
     }
   }
-  if constexpr (SEARCH)
+  if constexpr (SEARCH) {
     if (qn > 0) drain(qn);
+    // one atomic per wave and item (one address for the whole frame)
+    unsigned long long *const searched = F->searched;
+    if (searched != nullptr && n_searched != 0 && lane == 0)
+      atomicAdd(searched, static_cast<unsigned long long>(n_searched));
+  }
 }
 
 // Workgroups of up to 1024 threads share one LDS histogram (more waves per

@@ -5,6 +5,14 @@
 // over frame intervals in its writer, Sec. 3.3 and Sec. 4.4). Every finished
 // interval is appended to a results file, which is also the checkpoint: a
 // later call with the same parameters skips the intervals already there.
+//
+// Hybrid mode (the paper's CPU and GPU workers side by side, Sec. 3.3 and
+// Table 4): a CPU worker thread runs the library's CPU kernel on whole
+// frames taken from the end of the current interval, while the GPU takes
+// them from the start; the interval's record adds both. The CPU takes a
+// frame only if its measured time per frame is below the GPU's time for the
+// frames still unclaimed besides it, so it never holds an interval back by
+// more than about one GPU frame (DH_HYBRID_GREEDY lifts that rule).
 #include "disthist.h"
 #include "dh_internal.h"
 
@@ -13,6 +21,7 @@
 #include <unistd.h>
 
 #include <algorithm>
+#include <chrono>
 #include <condition_variable>
 #include <cstring>
 #include <mutex>
@@ -69,6 +78,34 @@ struct ResHeader {
   char pad[kResHeader - 8 - 8 - 24 - 16 - 8 - 16];
 };
 static_assert(sizeof(ResHeader) == kResHeader, "results header size");
+
+// Claims of the current interval's frames: the GPU takes [lo, ...) from the
+// start, the CPU worker (lo, hi] from the end.
+struct Hybrid {
+  std::mutex mu;
+  std::condition_variable cv;
+  int64_t lo = 0, hi = 0;  // unclaimed frames [lo, hi)
+  bool open = false;       // the current interval takes claims
+  bool busy = false;       // the CPU worker is computing a frame
+  bool quit = false;
+  bool greedy = false;
+  std::vector<uint64_t> sum;  // CPU frames' histograms of the interval
+  std::vector<uint64_t> pairs;  // and their pair counts per histogram
+  int64_t frames = 0, total_frames = 0;
+  double gpu_s = 0.0, cpu_s = 0.0;  // seconds per frame (running estimates)
+  int rc = DH_OK;
+  // worth a CPU frame: the GPU stays busy longer with the other frames
+  bool cpu_takes() const {
+    if (hi <= lo) return false;
+    if (greedy) return true;
+    return cpu_s > 0.0 && gpu_s > 0.0 && cpu_s < static_cast<double>(hi - lo - 1) * gpu_s;
+  }
+};
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
 
 }  // namespace
 
@@ -136,8 +173,20 @@ int dh_traj_histo(dh_ctx *ctx, dh_traj *t, const int64_t *offsets, int32_t n_spe
                   double r_max, int32_t n_bins, int32_t precision, int64_t frame_begin,
                   int64_t frame_end, int64_t interval, const char *results_path,
                   int64_t max_intervals, int64_t *intervals_done) {
+  return dh_traj_histo_hybrid(ctx, t, offsets, n_species, r_max, n_bins, precision, frame_begin,
+                              frame_end, interval, results_path, max_intervals, 0, 0,
+                              intervals_done, nullptr);
+}
+
+int dh_traj_histo_hybrid(dh_ctx *ctx, dh_traj *t, const int64_t *offsets, int32_t n_species,
+                         double r_max, int32_t n_bins, int32_t precision, int64_t frame_begin,
+                         int64_t frame_end, int64_t interval, const char *results_path,
+                         int64_t max_intervals, int32_t cpu_threads, int32_t flags,
+                         int64_t *intervals_done, int64_t *cpu_frames) {
+  if (cpu_frames) *cpu_frames = 0;
   if (!ctx || !t || !offsets || !results_path || interval < 1 || max_intervals < 0 ||
-      frame_begin < 0 || frame_end < frame_begin || frame_end > t->n_frames)
+      frame_begin < 0 || frame_end < frame_begin || frame_end > t->n_frames || cpu_threads < 0 ||
+      (flags & ~DH_HYBRID_GREEDY) != 0)
     return DH_EINVAL;
   if (n_species < 1 || n_species > 64 || offsets[0] != 0 || offsets[n_species] != t->n_points)
     return DH_EINVAL;
@@ -267,13 +316,84 @@ int dh_traj_histo(dh_ctx *ctx, dh_traj *t, const int64_t *offsets, int32_t n_spe
     });
   }
 
+  // CPU worker: whole frames from the end of the open interval
+  Hybrid hy;
+  hy.greedy = (flags & DH_HYBRID_GREEDY) != 0;
+  hy.sum.assign(hist_words, 0);
+  hy.pairs.assign(n_hist, 0);
+  std::thread cpu;
+  if (!rc && cpu_threads > 0) {
+    cpu = std::thread([&] {
+      std::vector<double> frame(static_cast<size_t>(t->frame_bytes / 8));
+      std::vector<uint64_t> out(hist_words), oor(n_hist);
+      while (true) {
+        int64_t f;
+        {
+          std::unique_lock<std::mutex> lk(hy.mu);
+          hy.cv.wait(lk, [&] { return hy.quit || (hy.open && hy.cpu_takes()); });
+          if (hy.quit) return;
+          f = --hy.hi;
+          hy.busy = true;
+        }
+        const double t0 = now_s();
+        int frc = read_all(t->fd, frame.data(), fbytes, kTrajHeader + f * t->frame_bytes)
+                      ? DH_OK
+                      : DH_EINVAL;
+        if (!frc)
+          frc = dh_cpu_histo(frame.data() + 9, offsets, n_species, t->box_type,
+                             t->box_type == DH_BOX_NONE ? nullptr : frame.data(), r_max, n_bins,
+                             precision, cpu_threads, out.data(), oor.data());
+        const double dt = now_s() - t0;
+        {
+          std::lock_guard<std::mutex> lk(hy.mu);
+          if (frc) {
+            hy.rc = frc;
+          } else {
+            for (size_t q = 0; q < hist_words; ++q) hy.sum[q] += out[q];
+            for (int hh = 0; hh < n_hist; ++hh) {
+              uint64_t in_range = 0;
+              for (int32_t b = 0; b < n_bins; ++b) in_range += out[static_cast<size_t>(hh) * n_bins + b];
+              hy.pairs[hh] += in_range + oor[hh];
+            }
+            ++hy.frames;
+            ++hy.total_frames;
+          }
+          hy.cpu_s = hy.cpu_s > 0.0 ? 0.5 * (hy.cpu_s + dt) : dt;
+          hy.busy = false;
+        }
+        hy.cv.notify_all();
+      }
+    });
+  }
+  // before the first CPU frame its time per frame is unknown: assume 2e8
+  // pairs per second per thread, a low rate for the CPU kernel
+  {
+    uint64_t fp_pairs = 0;
+    for (int32_t hh = 0; hh < n_hist; ++hh) fp_pairs += dh::hist_rows(offsets, n_species, hh).pairs;
+    hy.cpu_s = cpu_threads > 0 ? static_cast<double>(fp_pairs) / (2e8 * cpu_threads) : 0.0;
+  }
+
   std::vector<uint64_t> rec(hist_words + n_hist + 1);
   std::vector<uint64_t> pairs(n_hist);
   int64_t cur_interval = done;
   int64_t frames_in = 0;
   std::vector<uint64_t> hist_pairs(n_hist, 0);
+  double t_prev = 0.0;  // when the GPU took its previous frame
   for (int64_t f = f0; f < f1 && !rc; ++f) {
     const int k = static_cast<int>((f - f0) % kSlots);
+    const int64_t int_begin = frame_begin + cur_interval * interval;
+    const int64_t int_end = std::min(frame_end, int_begin + interval);
+    if (f == int_begin) {
+      // open the interval for claims
+      std::lock_guard<std::mutex> lk(hy.mu);
+      hy.lo = int_begin;
+      hy.hi = int_end;
+      hy.open = cpu_threads > 0;
+      hy.frames = 0;
+      std::fill(hy.sum.begin(), hy.sum.end(), 0);
+      std::fill(hy.pairs.begin(), hy.pairs.end(), 0);
+    }
+    if (cpu_threads > 0) hy.cv.notify_all();
     {
       std::unique_lock<std::mutex> lk(mu);
       cv.wait(lk, [&] { return filled[k] == static_cast<int>(f - f0) || reader_failed; });
@@ -282,8 +402,29 @@ int dh_traj_histo(dh_ctx *ctx, dh_traj *t, const int64_t *offsets, int32_t n_spe
         break;
       }
     }
-    // the device slot must be free: the compute of frame f - 2 is done
-    if (f - f0 >= kSlots && hipStreamWaitEvent(s_copy, consumed[k], 0) != hipSuccess) {
+    bool cpu_frame = false;
+    {
+      std::lock_guard<std::mutex> lk(hy.mu);
+      if (f >= hy.hi) {
+        cpu_frame = true;  // taken by the CPU worker
+      } else {
+        hy.lo = f + 1;
+        const double now = now_s();
+        if (t_prev > 0.0 && f > int_begin)
+          hy.gpu_s = hy.gpu_s > 0.0 ? 0.5 * (hy.gpu_s + (now - t_prev)) : now - t_prev;
+        t_prev = now;
+      }
+    }
+    if (cpu_frame) {
+      // the reader's copy of this frame is not needed
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        free_slot[k] = true;
+      }
+      cv.notify_all();
+    } else {
+    // the device slot must be free: the compute of its previous frame is done
+    if (hipStreamWaitEvent(s_copy, consumed[k], 0) != hipSuccess) {
       rc = DH_EDEVICE;
       break;
     }
@@ -333,9 +474,26 @@ int dh_traj_histo(dh_ctx *ctx, dh_traj *t, const int64_t *offsets, int32_t n_spe
         hist_pairs[hh] += static_cast<uint64_t>(offsets[s + 1] - offsets[s]) *
                           static_cast<uint64_t>(offsets[u + 1] - offsets[u]);
     ++frames_in;
-    const int64_t int_end = std::min(frame_end, frame_begin + (cur_interval + 1) * interval);
+    }  // GPU frame
     if (f + 1 == int_end) {
-      // interval finished: copy its sums out and append the record
+      // interval finished: close it to claims, wait for the CPU worker's
+      // frame, copy the GPU sums out, add the CPU sums, append the record
+      int64_t cpu_n = 0;
+      {
+        std::unique_lock<std::mutex> lk(hy.mu);
+        hy.open = false;
+        hy.cv.wait(lk, [&] { return !hy.busy; });
+        if (hy.rc) rc = hy.rc;
+        cpu_n = hy.frames;
+        for (int hh = 0; hh < n_hist; ++hh) hist_pairs[hh] += hy.pairs[hh];
+      }
+      if (rc) break;
+      if (frames_in == 0) {
+        // every frame of the interval ran on the CPU: the device sums were
+        // never zeroed for it
+        rc = dh::zero_u64(d_out, static_cast<int64_t>(hist_words), s_comp);
+        if (rc) break;
+      }
       if (hipMemcpyAsync(h_out, d_out, hist_words * 8, hipMemcpyDeviceToHost, s_comp) !=
               hipSuccess ||
           hipEventRecord(out_ready, s_comp) != hipSuccess ||
@@ -343,6 +501,8 @@ int dh_traj_histo(dh_ctx *ctx, dh_traj *t, const int64_t *offsets, int32_t n_spe
         rc = DH_EDEVICE;
         break;
       }
+      for (size_t q = 0; q < hist_words; ++q) h_out[q] += hy.sum[q];
+      frames_in += cpu_n;
       std::memcpy(rec.data(), h_out, hist_words * 8);
       for (int hh = 0; hh < n_hist; ++hh) {
         uint64_t in_range = 0;
@@ -367,6 +527,15 @@ int dh_traj_histo(dh_ctx *ctx, dh_traj *t, const int64_t *offsets, int32_t n_spe
     cv.notify_all();
     reader.join();
   }
+  if (cpu.joinable()) {
+    {
+      std::lock_guard<std::mutex> lk(hy.mu);
+      hy.quit = true;
+    }
+    hy.cv.notify_all();
+    cpu.join();
+  }
+  if (cpu_frames) *cpu_frames = hy.total_frames;
   if (s_comp) (void)hipStreamSynchronize(s_comp);
   if (s_copy) (void)hipStreamSynchronize(s_copy);
   for (int k = 0; k < kSlots; ++k) {

@@ -58,6 +58,9 @@ SIGNATURES = {
     "dh_traj_close": ([_vp], None),
     "dh_traj_histo": ([_vp, _vp, _vp, _i32, _f64, _i32, _i32, _i64, _i64, _i64, ctypes.c_char_p,
                        _i64, ctypes.POINTER(_i64)], ctypes.c_int),
+    "dh_traj_histo_hybrid": ([_vp, _vp, _vp, _i32, _f64, _i32, _i32, _i64, _i64, _i64,
+                              ctypes.c_char_p, _i64, _i32, _i32, ctypes.POINTER(_i64),
+                              ctypes.POINTER(_i64)], ctypes.c_int),
     "dh_ctx_set_tuning": ([_vp, _i32, ctypes.c_char_p], ctypes.c_int),
     "dh_ctx_set_config": ([_vp, _vp], ctypes.c_int),
     "dh_ctx_last_config": ([_vp, _vp], ctypes.c_int),
@@ -479,6 +482,25 @@ class Trajectory:
                                  int(interval), os.fsencode(results_path), int(max_intervals),
                                  ctypes.byref(done)), ctx.handle)
         return done.value
+
+    def histo_hybrid(self, ctx: "Context", offsets, r_max: float, n_bins: int, precision: int,
+                     results_path: str, cpu_threads: int, interval: int = 1,
+                     frame_begin: int = 0, frame_end: Optional[int] = None,
+                     max_intervals: int = 0, greedy: bool = False):
+        """dh_traj_histo_hybrid: as histo, with a CPU worker of cpu_threads
+        threads beside the GPU; returns (intervals recorded, frames the CPU
+        computed)."""
+        o = _offsets(offsets)
+        if frame_end is None:
+            frame_end = self.info()["n_frames"]
+        done, cpu = ctypes.c_int64(), ctypes.c_int64()
+        _check(LIB.dh_traj_histo_hybrid(ctx.handle, self.handle, _np_ptr(o), len(o) - 1,
+                                        float(r_max), int(n_bins), int(precision),
+                                        int(frame_begin), int(frame_end), int(interval),
+                                        os.fsencode(results_path), int(max_intervals),
+                                        int(cpu_threads), 1 if greedy else 0,
+                                        ctypes.byref(done), ctypes.byref(cpu)), ctx.handle)
+        return done.value, cpu.value
 
     def close(self) -> None:
         if self.handle:

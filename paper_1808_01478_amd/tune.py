@@ -26,10 +26,10 @@ def main(argv=None) -> int:
 
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_CACHE)
-    ap.add_argument("--workloads", default="ortho100k,tiny,triclinic1M")
+    ap.add_argument("--workloads", default="ortho100k,tiny,triclinic1M,image_search")
     args = ap.parse_args(argv)
     makers = {"ortho100k": workloads.ortho, "tiny": workloads.tiny,
-              "triclinic1M": workloads.triclinic}
+              "triclinic1M": workloads.triclinic, "image_search": workloads.image_search}
     # tune into a fresh file so that every listed workload is measured again,
     # then merge its entries over the existing cache
     fresh = args.out + ".new"

@@ -132,3 +132,44 @@ def test_invalid_frame_stops_before_its_interval(ctx, tmp_path):
     frames = [workloads.Frame(np.ascontiguousarray(x), offs, 2, good, 4.0, 100, "f") for x in xs[:4]]
     want = sum(oracle.frame_histogram(f).hist for f in frames[:2])
     assert np.array_equal(hist[0], want)
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+def test_hybrid_cpu_worker(ctx, tmp_path, kind):
+    """The CPU worker beside the GPU (the paper's hybrid workers): with the
+    greedy rule the CPU takes frames from the end of every interval, and the
+    binary64 records are byte-identical to the GPU-only run's (the CPU kernel
+    follows the same canonical arithmetic); binary32 records stay within the
+    edge-pair bound of the oracle's interval sums. With the default rule the
+    records are the same too, however many frames the CPU took."""
+    import paper_1808_01478_amd as dh
+    from gpu_util import fp32_bound_violations
+    p = str(tmp_path / "t.dhtraj")
+    frames = make_traj(p, kind, n_frames=12, sizes=(1500, 900))
+    f0 = frames[0]
+    print(f"\n[case] hybrid box={kind}", flush=True)
+    with dh.Trajectory(p) as t:
+        t.histo(ctx, f0.offsets, f0.r_max, f0.n_bins, 1, str(tmp_path / "gpu.dhres"), interval=4)
+        done, cpu = t.histo_hybrid(ctx, f0.offsets, f0.r_max, f0.n_bins, 1,
+                                   str(tmp_path / "hyb.dhres"), 2, interval=4, greedy=True)
+        assert done == 3 and cpu >= 1, (done, cpu)
+        done2, cpu2 = t.histo_hybrid(ctx, f0.offsets, f0.r_max, f0.n_bins, 1,
+                                     str(tmp_path / "auto.dhres"), 2, interval=4)
+        assert done2 == 3
+        done32, cpu32 = t.histo_hybrid(ctx, f0.offsets, f0.r_max, f0.n_bins, 0,
+                                       str(tmp_path / "hyb32.dhres"), 2, interval=4,
+                                       greedy=True)
+        assert done32 == 3 and cpu32 >= 1
+    gpu = open(tmp_path / "gpu.dhres", "rb").read()
+    assert open(tmp_path / "hyb.dhres", "rb").read() == gpu
+    assert open(tmp_path / "auto.dhres", "rb").read() == gpu
+    from paper_1808_01478_amd import trajfile
+    _, h32, oor32, nfr = trajfile.read_results(str(tmp_path / "hyb32.dhres"), f0.n_hist)
+    assert list(nfr) == [4, 4, 4]
+    for k in range(3):
+        refs = [oracle.frame_histogram(fr, edge_window=oracle.edge_window(
+            fr.coords, fr.box, fr.r_max)) for fr in frames[4 * k:4 * k + 4]]
+        hist = sum(r.hist.astype(np.int64) for r in refs)
+        edges = sum(r.edges.astype(np.int64) for r in refs)
+        bad = fp32_bound_violations(h32[k], hist, edges)
+        assert not bad, "; ".join(bad[:5])
