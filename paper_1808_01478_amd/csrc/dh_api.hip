@@ -657,7 +657,7 @@ int stage_job(dh_ctx *ctx, hipStream_t st, const FrameJob &job, const FrameParam
     int rc = ensure_device(ctx, &ctx->d_keys, &ctx->keys_cap,
                            static_cast<size_t>(sort_keys_count(n)) * sizeof(uint64_t));
     if (rc) return rc;
-    DH_HIP(ctx, launch_stage_sorted(job.d_coords, ctx->d_staged, n, job.offsets, job.n_species,
+    DH_HIP(ctx, launch_stage_sorted(job.precision, job.d_coords, ctx->d_staged, n, job.offsets, job.n_species,
                                     fp, static_cast<uint64_t *>(ctx->d_keys), st));
     return DH_OK;
   }
@@ -1099,7 +1099,7 @@ static int dh_batch_launch_direct(dh_batch *b, hipStream_t st) {
   DH_HIP(ctx, launch_stage_batch(b->precision, d_frames, b->n_frames, b->max_points, st));
   // spatially sorted frames one after the other (one key buffer)
   for (const dh_batch::Sorted &q : b->sorted)
-    DH_HIP(ctx, launch_stage_sorted(q.d_in, q.staged, q.fp.n_points, q.offsets.data(),
+    DH_HIP(ctx, launch_stage_sorted(b->precision, q.d_in, q.staged, q.fp.n_points, q.offsets.data(),
                                     static_cast<int32_t>(q.offsets.size() - 1), q.fp,
                                     static_cast<uint64_t *>(b->d_keys), st));
   DH_HIP(ctx, launch_zero_batch(d_frames, b->n_frames, b->max_words, counters,

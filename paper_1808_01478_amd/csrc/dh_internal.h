@@ -13,25 +13,25 @@ enum BoxKind : int32_t {
   kBoxTric = 2,        // Eq. 5 reduction only (r_max below half the smallest width)
   kBoxTricSearch = 3,  // Eq. 5 reduction, then the 27 neighbouring images
   kBoxCube = 4,        // binary32 only: orthorhombic cell with equal edges
-  // binary32 only: triclinic cell without image search, points spatially
-  // sorted within each species at staging (frames of at least kSortMinPoints)
+  // triclinic cell without image search, points spatially sorted within each
+  // species at staging (frames of at least kSortMinPoints)
   kBoxTricSorted = 5,
 };
 
 // Largest species count of a frame (the staging kernels take the offsets by
 // value).
 constexpr int kMaxSpeciesStage = 64;
-// binary32 triclinic frames (no image search) with at least this many points
-// are staged in spatial order (kBoxTricSorted)
+// triclinic frames (no image search) with at least this many points are
+// staged in spatial order (kBoxTricSorted)
 constexpr int64_t kSortMinPoints = int64_t{1} << 16;
 
 // The minimum-image kind the kernels use for a frame: the geometric kind of
-// frame_constants, with the binary32 special cases (equal orthorhombic
-// edges; large triclinic frames staged in spatial order).
+// frame_constants, with large triclinic frames staged in spatial order (both
+// precisions) and the binary32 special case of equal orthorhombic edges.
 inline int staged_kind(int kind, int precision, const double L[3], int64_t n_points) {
+  if (kind == kBoxTric && n_points >= kSortMinPoints) return kBoxTricSorted;
   if (precision != 0) return kind;
   if (kind == kBoxOrtho && L[0] == L[1] && L[1] == L[2]) return kBoxCube;
-  if (kind == kBoxTric && n_points >= kSortMinPoints) return kBoxTricSorted;
   return kind;
 }
 
@@ -114,8 +114,9 @@ struct FrameParams {
 
 // LDS of a spatially sorted frame's pair kernel besides its two j-tiles:
 // the bounding boxes of the tiles' groups of 64 points (two tiles, at most
-// four groups each, eight words per box)
-constexpr size_t kSortedBoxBytes = 2 * 4 * 8 * sizeof(uint32_t);
+// four groups each, eight words per box: 32-bit fixed-point fractions in
+// binary32, binary64 fractions in binary64)
+constexpr size_t kSortedBoxBytes = 2 * 4 * 8 * sizeof(double);
 
 // One unit of work: particles [i0, i1) of the frame against [j0, j1), for
 // histogram `hist`, bin window `sweep`; flags: kItemDiag, kItemFull.
@@ -231,12 +232,13 @@ __host__ __device__ inline int64_t emit_row(const HistRows &r, int32_t h, int32_
 }
 
 // host-side launchers (dh_kernels.hip)
-// binary32 staging of a kBoxTricSorted frame: the points of every species
-// in Morton order of their wrapped fractional coordinates (keys: a workspace
-// of sort_keys_count(n) words), two float4 per point in `out`.
-hipError_t launch_stage_sorted(const double *in, void *out, int64_t n, const int64_t *offsets,
-                               int32_t n_species, const FrameParams &fp, uint64_t *keys,
-                               hipStream_t st);
+// Staging of a kBoxTricSorted frame: the points of every species in Morton
+// order of their wrapped fractional coordinates (keys: a workspace of
+// sort_keys_count(n) words); binary32: two float4 per point in `out`,
+// binary64: the input coordinates as one double4 per point.
+hipError_t launch_stage_sorted(int precision, const double *in, void *out, int64_t n,
+                               const int64_t *offsets, int32_t n_species, const FrameParams &fp,
+                               uint64_t *keys, hipStream_t st);
 hipError_t launch_stage(int precision, int box_kind, const double *in, void *out, int64_t n,
                         const FrameParams &fp, hipStream_t st);
 // zeroes out[n_words] and counters[n_counters]; with oor, sets oor[h] =

@@ -80,6 +80,15 @@ __device__ __forceinline__ Geo64 load_geo64(const FrameParams *F) {
   return g;
 }
 
+// Fractional coordinates B^-1 x of a point (the rows of Eq. 5's reduction
+// applied to a position instead of a difference).
+__device__ __forceinline__ void frac64(double x, double y, double z, const Geo64 &g,
+                                       double (&sg)[3]) {
+  sg[0] = fma(z, g.h13, fma(y, g.h12, x * g.h11));
+  sg[1] = fma(z, g.h23, y * g.h22);
+  sg[2] = z * g.h33;
+}
+
 // Correctly rounded binary64 square root (IEEE-754 sqrt) for every
 // argument. The candidate y comes from v_rsq_f64 refined by one Goldschmidt
 // step and two Newton corrections with fused residuals, which leaves y within
@@ -301,6 +310,17 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = max(v, static_cast<uint32_t>(__shfl_xor(v, o)));
   return static_cast<uint32_t>(uni(static_cast<int>(v)));
+}
+
+__device__ __forceinline__ double wave_min_f64(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  return uni(v);
+}
+__device__ __forceinline__ double wave_max_f64(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return uni(v);
 }
 
 // Lattice shift n (in cell vectors, one axis) shared by every pair of a
@@ -660,12 +680,24 @@ __global__ void stage_sorted_kernel(const double *__restrict__ in,
   }
 }
 
+// binary64: the input point of the sorted position q, unchanged.
+__global__ void stage_sorted64_kernel(const double *__restrict__ in,
+                                      const uint64_t *__restrict__ keys, int64_t n,
+                                      double4 *__restrict__ out) {
+  const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t q = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; q < n;
+       q += step) {
+    const int64_t i = static_cast<int64_t>(keys[q] & 0x7FFFFFFFull);
+    out[q] = make_double4(in[3 * i], in[3 * i + 1], in[3 * i + 2], 0.0);
+  }
+}
+
 // Batched staging: blockIdx.y selects the frame.
 template <int PREC>
 __global__ void stage_batch_kernel(const FrameParams *__restrict__ frames) {
   const FrameParams &p = frames[blockIdx.y];
   // spatially sorted frames are staged by their own sort
-  if (PREC == 0 && p.box == kBoxTricSorted) return;
+  if (p.box == kBoxTricSorted) return;
   const int64_t n = p.n_points;
   const double *__restrict__ in = p.in;
   const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
@@ -886,6 +918,164 @@ __device__ __forceinline__ void sorted_tile(
   }
 }
 
+// Lattice shift along one axis shared by every pair of two groups of a
+// binary64 sorted frame. The fractional difference s of a pair (the first
+// step of Eq. 5, with its rounding) lies in [jlo - ihi, jhi - ilo] (the
+// groups' boxes of B^-1 x) widened by the margin m, which bounds the
+// rounding of s, of the boxes and of this test. When both ends of the
+// widened interval round to the same n, every s lies strictly inside
+// (n - 1/2, n + 1/2), so rint(s) = n for every pair, ties included. False
+// when the ends differ or a group is empty (an empty box has lo = +inf,
+// hi = -inf) or holds a non-finite value.
+__device__ __forceinline__ bool group_shift64(double ilo, double ihi, double jlo, double jhi,
+                                              double m, double &n) {
+  const double a = floor(((jlo - ihi) - m) + 0.5);
+  const double b = floor(((jhi - ilo) + m) + 0.5);
+  n = a;
+  return a == b;
+}
+
+// One j-tile of a spatially sorted binary64 frame for one wave. For every
+// group of 64 j-points and every slice r of the wave's i-points, each axis
+// whose Eq. 5 shift n is shared by all their pairs (group_shift64) and whose
+// terms B n are exact binary64 numbers skips that axis's fractional
+// coordinate and rounding: each fused step of Eq. 5 with that n, d - B_k n
+// rounded once, equals the plain sum d + P_k with the exact term
+// P_k = -B_k n. The other axes take Eq. 5's own steps. A pass over the
+// group's j serves all R slices with one kind of reduction (the axes that
+// need the rounding for any slice take it for all of them: for a shared
+// axis it yields the same n), so every reduced vector, q and t is
+// bit-identical to the canonical sequence. Passes whose shifts are all zero
+// skip the sums (they would change only the sign of a zero component).
+//
+// Box slot 6 of a group holds the largest |x| + |y| + |z| of its points,
+// which bounds the magnitudes, and with them the rounding, that the margin
+// of group_shift64 must cover: with u = 2^-53 and h the largest entry of
+// B^-1, every rounding error of the fractional difference, of the boxes and
+// of the test is below 12 u h (A_i + A_j), well inside 2^-48 h (A_i + A_j).
+template <int R, bool DIAG, typename CountT>
+__device__ __forceinline__ void sorted_tile64(
+    const double4 *__restrict__ tb, const double *__restrict__ boxes, int jt, int js,
+    int jcount, int wbase, int lane, const Geo64 &g, bool big_bins, const double (&xi)[R],
+    const double (&yi)[R], const double (&zi)[R], const double (&ibox)[R][7],
+    const uint32_t (&lo)[R], uint32_t hi, CountT &count_t) {
+  const double hmax = fmax(fmax(fabs(g.h11), fabs(g.h12)),
+                           fmax(fmax(fabs(g.h13), fabs(g.h22)), fmax(fabs(g.h23), fabs(g.h33))));
+  for (int g0 = js & ~63; g0 < jcount; g0 += 64) {
+    const int j_begin = max(js, g0), j_end = min(jcount, g0 + 64);
+    const double *gb = boxes + (g0 >> 6) * 8;
+    double jb[7];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) jb[q] = uni(gb[q]);
+    // amb: bit k when axis k (a, b, c) needs the rounding for some slice;
+    // nonzero: some slice has a shared non-zero shift
+    uint32_t amb = 0;
+    bool nonzero = false;
+    // exact terms, in the order of the canonical steps: x of a, b, c; y of
+    // b, c; z of c (zero where the axis takes the rounding)
+    double P[R][6];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      double n[3] = {0.0, 0.0, 0.0};
+      uint32_t amb_r = 0;
+      // an empty slice (all lanes past the end: lo > hi) counts nothing
+      if (ibox[r][0] <= ibox[r][3]) {
+        const double m = fma(hmax * (ibox[r][6] + jb[6]), 0x1p-48, 0x1p-40);
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          if (!group_shift64(ibox[r][k], ibox[r][3 + k], jb[k], jb[3 + k], m, n[k]))
+            amb_r |= 1u << k;
+      }
+      const double c[6] = {g.ax, g.bx, g.cx, g.by, g.cy, g.cz};
+      constexpr int axis[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        const double nk = amb_r & (1u << axis[k]) ? 0.0 : n[axis[k]];
+        const double t = -c[k] * nk;
+        if (fma(-c[k], nk, -t) != 0.0) amb_r |= 1u << axis[k];  // not exact
+        P[r][k] = uni(t);
+      }
+      amb |= amb_r;
+      nonzero = nonzero || n[0] != 0.0 || n[1] != 0.0 || n[2] != 0.0;
+    }
+    amb = static_cast<uint32_t>(uni(static_cast<int>(amb)));
+    const bool zero = uni(static_cast<int>(nonzero)) == 0;
+
+    // The pairs of all slices with one j, reduced as AMB says: short roots,
+    // one ballot, the correctly rounded root for all of them when any lane
+    // needs it (see t_fast64), then the counts.
+    auto pairs_of = [&](auto amb_c, auto zero_c, const double4 &pj, int j) {
+      constexpr uint32_t AMB = decltype(amb_c)::value;
+      constexpr bool ZERO = decltype(zero_c)::value;
+      double q[R], t[R];
+      uint64_t near = big_bins ? ~0ull : 0ull;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        double dx = pj.x - xi[r], dy = pj.y - yi[r], dz = pj.z - zi[r];
+        if constexpr (!ZERO) {
+          // Eq. 5's n of the axes that need it, from the unreduced d
+          double na = 0.0, nb = 0.0, nc = 0.0;
+          if constexpr (AMB & 1u) na = rint(fma(dz, g.h13, fma(dy, g.h12, dx * g.h11)));
+          if constexpr (AMB & 2u) nb = rint(fma(dz, g.h23, dy * g.h22));
+          if constexpr (AMB & 4u) nc = rint(dz * g.h33);
+          if constexpr (AMB & 4u) dz = fma(-g.cz, nc, dz); else dz = dz + P[r][5];
+          if constexpr (AMB & 2u) dy = fma(-g.by, nb, dy); else dy = dy + P[r][3];
+          if constexpr (AMB & 4u) dy = fma(-g.cy, nc, dy); else dy = dy + P[r][4];
+          if constexpr (AMB & 1u) dx = fma(-g.ax, na, dx); else dx = dx + P[r][0];
+          if constexpr (AMB & 2u) dx = fma(-g.bx, nb, dx); else dx = dx + P[r][1];
+          if constexpr (AMB & 4u) dx = fma(-g.cx, nc, dx); else dx = dx + P[r][2];
+        }
+        q[r] = fma(dz, dz, fma(dy, dy, dx * dx));
+        t[r] = t_fast64(q[r], g.s, near);
+      }
+      if (__builtin_expect(near != 0, 0))
+#pragma unroll
+        for (int r = 0; r < R; ++r) t[r] = sqrt_cr(q[r]) * g.s;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        uint32_t l = lo[r];
+        if constexpr (DIAG) l = jt + j > wbase + r * 64 + lane ? l : hi;
+        count_t(t[r], l, 0u);
+      }
+    };
+    // One pass over the group's j: the next j is read before the current
+    // j's atomics (see sorted_tile); at the end of the group the look-ahead
+    // read touches the entry after it (the next group, the other tile or the
+    // box area), never used.
+    auto run_j = [&](auto amb_c, auto zero_c) {
+      int vzero;
+      asm volatile("v_mov_b32 %0, 0" : "=v"(vzero));
+      const double4 *cp = tb + j_begin + vzero;
+      double4 pa = cp[0];
+      int j = j_begin;
+      for (; j + 1 < j_end; j += 2, cp += 2) {
+        const double4 pb = cp[1];
+        pairs_of(amb_c, zero_c, pa, j);
+        pa = cp[2];
+        pairs_of(amb_c, zero_c, pb, j + 1);
+      }
+      if (j < j_end) pairs_of(amb_c, zero_c, pa, j);
+    };
+    using No = std::integral_constant<bool, false>;
+    using Yes = std::integral_constant<bool, true>;
+    switch (amb) {
+      case 0:
+        if (zero)
+          run_j(std::integral_constant<uint32_t, 0>{}, Yes{});
+        else
+          run_j(std::integral_constant<uint32_t, 0>{}, No{});
+        break;
+      case 1: run_j(std::integral_constant<uint32_t, 1>{}, No{}); break;
+      case 2: run_j(std::integral_constant<uint32_t, 2>{}, No{}); break;
+      case 3: run_j(std::integral_constant<uint32_t, 3>{}, No{}); break;
+      case 4: run_j(std::integral_constant<uint32_t, 4>{}, No{}); break;
+      case 5: run_j(std::integral_constant<uint32_t, 5>{}, No{}); break;
+      case 6: run_j(std::integral_constant<uint32_t, 6>{}, No{}); break;
+      default: run_j(std::integral_constant<uint32_t, 7>{}, No{}); break;
+    }
+  }
+}
+
 // CLAMP = false: the host proved that every t of this frame is below the LDS
 // stride and the block has no invalid lanes, so the bin index needs no clamp
 // (out-of-range pairs land in slots [n_bins, stride) that are never flushed).
@@ -910,7 +1100,7 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
   // spatially sorted frames: two float4 per point (fixed-point words, then
   // the Cartesian position relative to the cell centre)
   constexpr bool SORTED = BOX == kBoxTricSorted;
-  constexpr int EPJ = SORTED ? 2 : 1;
+  constexpr int EPJ = SORTED && sizeof(T) == 4 ? 2 : 1;
   const V *__restrict__ X = static_cast<const V *>(F->coords);
   const G g = Geo<T>::load(F);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -950,6 +1140,9 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
   // b, c; an empty slice has lo > hi
   [[maybe_unused]] float cxi[R], cyi[R], czi[R];
   [[maybe_unused]] uint32_t ibox[R][6];
+  // binary64 sorted frames: boxes of the fractional coordinates B^-1 x
+  // (slot 6: the largest |x| + |y| + |z| of the slice)
+  [[maybe_unused]] double ibox64[R][7];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int i = wbase + r * 64 + lane;
@@ -957,7 +1150,17 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
     const V p = X[EPJ * (ok ? i : w.i0)];
     xi[r] = p.x; yi[r] = p.y; zi[r] = p.z;
     lo[r] = ok ? 0u : hi;
-    if constexpr (SORTED) {
+    if constexpr (SORTED && sizeof(T) == 8) {
+      double sg[3];
+      frac64(p.x, p.y, p.z, g, sg);
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        ibox64[r][ax] = wave_min_f64(ok ? sg[ax] : __builtin_inf());
+        ibox64[r][3 + ax] = wave_max_f64(ok ? sg[ax] : -__builtin_inf());
+      }
+      ibox64[r][6] = wave_max_f64(ok ? fabs(p.x) + fabs(p.y) + fabs(p.z) : 0.0);
+    }
+    if constexpr (SORTED && sizeof(T) == 4) {
       const V c = X[EPJ * (ok ? i : w.i0) + 1];
       cxi[r] = c.x; cyi[r] = c.y; czi[r] = c.z;
       const uint32_t u[3] = {__float_as_uint(p.x), __float_as_uint(p.y), __float_as_uint(p.z)};
@@ -1121,13 +1324,32 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
   [[maybe_unused]] uint32_t *const tboxes = reinterpret_cast<uint32_t *>(tile + 2 * tj * EPJ);
   if (tid < tj && w.j0 + tid < w.j1) {
     pre = X[EPJ * (w.j0 + tid)];
-    if constexpr (SORTED) preC = X[EPJ * (w.j0 + tid) + 1];
+    if constexpr (SORTED && sizeof(T) == 4) preC = X[EPJ * (w.j0 + tid) + 1];
   }
   int buf = 0;
   for (int jt = w.j0; jt < w.j1; jt += tj, buf ^= 1) {
     if (tid < tj) {
       tile[(buf * tj + tid) * EPJ] = pre;
-      if constexpr (SORTED) {
+      if constexpr (SORTED && sizeof(T) == 8) {
+        // the box of this wave's 64 j in fractional coordinates
+        const bool ok = jt + tid < w.j1;
+        double sg[3];
+        frac64(pre.x, pre.y, pre.z, g, sg);
+        double b6[7];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          b6[ax] = wave_min_f64(ok ? sg[ax] : __builtin_inf());
+          b6[3 + ax] = wave_max_f64(ok ? sg[ax] : -__builtin_inf());
+        }
+        b6[6] = wave_max_f64(ok ? fabs(pre.x) + fabs(pre.y) + fabs(pre.z) : 0.0);
+        if (lane < 7) {
+          double v = b6[0];
+#pragma unroll
+          for (int q = 1; q < 7; ++q) v = lane == q ? b6[q] : v;
+          reinterpret_cast<double *>(tboxes)[(buf * 4 + (tid >> 6)) * 8 + lane] = v;
+        }
+      }
+      if constexpr (SORTED && sizeof(T) == 4) {
         tile[(buf * tj + tid) * EPJ + 1] = preC;
         // the box of this wave's 64 j (tiles start on group boundaries of
         // the species, so the group is the same whatever the launch shape)
@@ -1153,17 +1375,24 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
       const int jn = jt + tj + tid;
       if (tid < tj && jn < w.j1) {
         pre = X[EPJ * jn];
-        if constexpr (SORTED) preC = X[EPJ * jn + 1];
+        if constexpr (SORTED && sizeof(T) == 4) preC = X[EPJ * jn + 1];
       }
     }
     const int jcount = min(tj, w.j1 - jt);
     int js = 0;
     if constexpr (DIAG) js = max(0, min(jcount, wbase + 1 - jt));
-    if constexpr (SORTED) {
+    if constexpr (SORTED && sizeof(T) == 4) {
       if (wave_active && js < jcount)
         sorted_tile<R, MODE, DIAG, CLAMP>(tile + buf * tj * EPJ, tboxes + buf * 32, jt, js,
                                           jcount, wbase, lane, F, g, xi, zi, cxi, cyi, czi,
                                           ibox, nab, nzz, lo, lob, hi, hib, count_t);
+      continue;
+    }
+    if constexpr (SORTED && sizeof(T) == 8) {
+      if (wave_active && js < jcount)
+        sorted_tile64<R, DIAG>(tile + buf * tj, reinterpret_cast<const double *>(tboxes) + buf * 32,
+                               jt, js, jcount, wbase, lane, g, big_bins, xi, yi, zi, ibox64, lo,
+                               hi, count_t);
       continue;
     }
     if (wave_active && js < jcount) {
@@ -1327,7 +1556,7 @@ __global__ __launch_bounds__(max_threads<BOX>()) void pairs_kernel(PairKernelArg
   // word per copy for binary32 bin -1 (t < 1/4), added to bin 0 on flush.
   // The host's allocation has one spare coordinate entry there.
   // (sorted frames: two entries per j, then the tiles' group boxes)
-  constexpr int EPJ = BOX == kBoxTricSorted ? 2 : 1;
+  constexpr int EPJ = BOX == kBoxTricSorted && sizeof(T) == 4 ? 2 : 1;
   const size_t tiles_bytes = 2 * static_cast<size_t>(a.tj) * EPJ * sizeof(V) +
                              (BOX == kBoxTricSorted ? kSortedBoxBytes : 0);
   uint32_t *hist = reinterpret_cast<uint32_t *>(smem + tiles_bytes + kGuardBytes);
@@ -1450,9 +1679,7 @@ PairFn pick_box(int box) {
     case kBoxCube:
       if constexpr (sizeof(T) == 4) return pairs_kernel<T, R, kBoxCube, SW>;
       return pairs_kernel<T, R, kBoxOrtho, SW>;
-    case kBoxTricSorted:
-      if constexpr (sizeof(T) == 4) return pairs_kernel<T, R, kBoxTricSorted, SW>;
-      return pairs_kernel<T, R, kBoxTric, SW>;
+    case kBoxTricSorted: return pairs_kernel<T, R, kBoxTricSorted, SW>;
     default: return pairs_kernel<T, R, kBoxTricSearch, SW>;
   }
 }
@@ -1484,9 +1711,9 @@ int grid_for(int64_t n, int threads) {
 
 }  // namespace
 
-hipError_t launch_stage_sorted(const double *in, void *out, int64_t n, const int64_t *offsets,
-                               int32_t n_species, const FrameParams &fp, uint64_t *keys,
-                               hipStream_t st) {
+hipError_t launch_stage_sorted(int precision, const double *in, void *out, int64_t n,
+                               const int64_t *offsets, int32_t n_species, const FrameParams &fp,
+                               uint64_t *keys, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   if (n_species < 1 || n_species > kMaxSpeciesStage || n > 0x7FFFFFFFll)
     return hipErrorInvalidValue;
@@ -1503,8 +1730,12 @@ hipError_t launch_stage_sorted(const double *in, void *out, int64_t n, const int
       bitonic_global_kernel<<<grid_for(npad / 2, threads), threads, 0, st>>>(keys, npad, j, kk);
     bitonic_local_kernel<<<blocks, 1024, 0, st>>>(keys, kk, 0);
   }
-  stage_sorted_kernel<<<grid_for(n, threads), threads, 0, st>>>(in, keys, n, fp,
-                                                                static_cast<float4 *>(out));
+  if (precision == 1)
+    stage_sorted64_kernel<<<grid_for(n, threads), threads, 0, st>>>(in, keys, n,
+                                                                    static_cast<double4 *>(out));
+  else
+    stage_sorted_kernel<<<grid_for(n, threads), threads, 0, st>>>(in, keys, n, fp,
+                                                                  static_cast<float4 *>(out));
   return hipGetLastError();
 }
 
@@ -1513,6 +1744,7 @@ hipError_t launch_stage(int precision, int box_kind, const double *in, void *out
   if (n <= 0) return hipSuccess;
   const int threads = 256;
   const int grid = grid_for(n, threads);
+  if (box_kind == kBoxTricSorted) return hipErrorInvalidValue;  // launch_stage_sorted
   if (precision == 1) {
     stage64_kernel<<<grid, threads, 0, st>>>(in, static_cast<double4 *>(out), n);
   } else {

@@ -229,7 +229,7 @@ extern "C" int dh_histo_noalloc(dh_stream stream, const double *d_coords,
   hipError_t e = hipGetLastError();
   if (e == hipSuccess)
     e = kind == kBoxTricSorted
-            ? launch_stage_sorted(d_coords, base + off_staged, n, offsets, n_species, fp,
+            ? launch_stage_sorted(precision, d_coords, base + off_staged, n, offsets, n_species, fp,
                                   reinterpret_cast<uint64_t *>(base + off_keys), st)
             : launch_stage(precision, kind, d_coords, base + off_staged, n, fp, st);
   // the counters were cleared by the planner: none passed here

@@ -226,13 +226,12 @@ namespace {
 
 // Device bytes a job holds while resident: its coordinates, the staged copy
 // (and the sort keys of a spatially sorted frame), histograms, out-of-range
-// and pair counts. Binary32 triclinic frames are counted as if sorted, an
+// and pair counts. Large triclinic frames are counted as if sorted, an
 // upper bound that needs no cell geometry.
 int64_t job_footprint(int64_t n, int32_t n_hist, int32_t n_bins, int32_t precision,
                       int32_t box_type) {
   const int64_t pts = std::max<int64_t>(1, n);
-  const bool may_sort = precision == DH_FP32 && box_type == DH_BOX_TRICLINIC &&
-                        n >= dh::kSortMinPoints;
+  const bool may_sort = box_type == DH_BOX_TRICLINIC && n >= dh::kSortMinPoints;
   return pts * 3 * static_cast<int64_t>(sizeof(double)) +
          pts * (precision == DH_FP64 || may_sort ? 32 : 16) +
          (may_sort ? dh::sort_keys_count(n) * 8 : 0) +
@@ -370,7 +369,7 @@ int start_job(dh_server *s, int slot_idx) {
     return DH_EDEVICE;
   const hipError_t staged =
       j.kind == dh::kBoxTricSorted
-          ? dh::launch_stage_sorted(sl.d_in, sl.d_staged, j.n, j.offsets.data(), k, fp,
+          ? dh::launch_stage_sorted(j.precision, sl.d_in, sl.d_staged, j.n, j.offsets.data(), k, fp,
                                     static_cast<uint64_t *>(sl.d_keys), s->setup)
           : dh::launch_stage(j.precision, j.kind, sl.d_in, sl.d_staged, j.n, fp, s->setup);
   if (staged != hipSuccess ||
