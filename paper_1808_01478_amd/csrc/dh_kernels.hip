@@ -300,6 +300,15 @@ __device__ __forceinline__ uint32_t med3_u32(uint32_t x, uint32_t lo, uint32_t h
   return r;
 }
 
+// min(a, b) for an a that is an arithmetic result (never a signalling NaN):
+// one v_min_f64, without the canonicalisation fmin adds for arbitrary input.
+// A NaN a gives b, as fmin does.
+__device__ __forceinline__ double min_arith(double a, double b) {
+  double r;
+  asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
 // Minimum and maximum over the 64 lanes of a wave, as a wave-uniform value.
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
 #pragma unroll
@@ -945,8 +954,9 @@ __device__ __forceinline__ bool group_shift64(double ilo, double ihi, double jlo
 // group's j serves all R slices with one kind of reduction (the axes that
 // need the rounding for any slice take it for all of them: for a shared
 // axis it yields the same n), so every reduced vector, q and t is
-// bit-identical to the canonical sequence. Passes whose shifts are all zero
-// skip the sums (they would change only the sign of a zero component).
+// bit-identical to the canonical sequence. Sums along an axis whose shared
+// shift is zero for every slice are skipped (they would change only the sign
+// of a zero component).
 //
 // Box slot 6 of a group holds the largest |x| + |y| + |z| of its points,
 // which bounds the magnitudes, and with them the rounding, that the margin
@@ -968,9 +978,8 @@ __device__ __forceinline__ void sorted_tile64(
 #pragma unroll
     for (int q = 0; q < 7; ++q) jb[q] = uni(gb[q]);
     // amb: bit k when axis k (a, b, c) needs the rounding for some slice;
-    // nonzero: some slice has a shared non-zero shift
-    uint32_t amb = 0;
-    bool nonzero = false;
+    // nz: bit k when some slice has a shared non-zero shift along axis k
+    uint32_t amb = 0, nz = 0;
     // exact terms, in the order of the canonical steps: x of a, b, c; y of
     // b, c; z of c (zero where the axis takes the rounding)
     double P[R][6];
@@ -996,82 +1005,125 @@ __device__ __forceinline__ void sorted_tile64(
         P[r][k] = uni(t);
       }
       amb |= amb_r;
-      nonzero = nonzero || n[0] != 0.0 || n[1] != 0.0 || n[2] != 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        if (!(amb_r & (1u << k)) && n[k] != 0.0) nz |= 1u << k;
     }
     amb = static_cast<uint32_t>(uni(static_cast<int>(amb)));
-    const bool zero = uni(static_cast<int>(nonzero)) == 0;
+    nz = static_cast<uint32_t>(uni(static_cast<int>(nz))) & ~amb;
 
-    // The pairs of all slices with one j, reduced as AMB says: short roots,
-    // one ballot, the correctly rounded root for all of them when any lane
-    // needs it (see t_fast64), then the counts.
-    auto pairs_of = [&](auto amb_c, auto zero_c, const double4 &pj, int j) {
+    // The reduced vector, q and short root t of the pairs of all slices with
+    // one j, reduced as AMB says (the lanes whose t may lie near a bin edge
+    // join the wave mask `near`, see t_fast64).
+    // AMB: the axes that take the rounding; NZ: the axes whose shared shift
+    // is non-zero for some slice (the others add nothing: their terms are 0).
+    auto reduce = [&](auto amb_c, auto nz_c, const double4 &pj, double *q, double *t,
+                      uint64_t &near) {
       constexpr uint32_t AMB = decltype(amb_c)::value;
-      constexpr bool ZERO = decltype(zero_c)::value;
-      double q[R], t[R];
-      uint64_t near = big_bins ? ~0ull : 0ull;
+      constexpr uint32_t NZ = decltype(nz_c)::value;
+      static_assert((AMB & NZ) == 0, "an axis is either rounded or shared");
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         double dx = pj.x - xi[r], dy = pj.y - yi[r], dz = pj.z - zi[r];
-        if constexpr (!ZERO) {
-          // Eq. 5's n of the axes that need it, from the unreduced d
-          double na = 0.0, nb = 0.0, nc = 0.0;
-          if constexpr (AMB & 1u) na = rint(fma(dz, g.h13, fma(dy, g.h12, dx * g.h11)));
-          if constexpr (AMB & 2u) nb = rint(fma(dz, g.h23, dy * g.h22));
-          if constexpr (AMB & 4u) nc = rint(dz * g.h33);
-          if constexpr (AMB & 4u) dz = fma(-g.cz, nc, dz); else dz = dz + P[r][5];
-          if constexpr (AMB & 2u) dy = fma(-g.by, nb, dy); else dy = dy + P[r][3];
-          if constexpr (AMB & 4u) dy = fma(-g.cy, nc, dy); else dy = dy + P[r][4];
-          if constexpr (AMB & 1u) dx = fma(-g.ax, na, dx); else dx = dx + P[r][0];
-          if constexpr (AMB & 2u) dx = fma(-g.bx, nb, dx); else dx = dx + P[r][1];
-          if constexpr (AMB & 4u) dx = fma(-g.cx, nc, dx); else dx = dx + P[r][2];
-        }
+        // Eq. 5's n of the axes that need it, from the unreduced d
+        double na = 0.0, nb = 0.0, nc = 0.0;
+        if constexpr (AMB & 1u) na = rint(fma(dz, g.h13, fma(dy, g.h12, dx * g.h11)));
+        if constexpr (AMB & 2u) nb = rint(fma(dz, g.h23, dy * g.h22));
+        if constexpr (AMB & 4u) nc = rint(dz * g.h33);
+        if constexpr (AMB & 4u) dz = fma(-g.cz, nc, dz);
+        else if constexpr (NZ & 4u) dz = dz + P[r][5];
+        if constexpr (AMB & 2u) dy = fma(-g.by, nb, dy);
+        else if constexpr (NZ & 2u) dy = dy + P[r][3];
+        if constexpr (AMB & 4u) dy = fma(-g.cy, nc, dy);
+        else if constexpr (NZ & 4u) dy = dy + P[r][4];
+        if constexpr (AMB & 1u) dx = fma(-g.ax, na, dx);
+        else if constexpr (NZ & 1u) dx = dx + P[r][0];
+        if constexpr (AMB & 2u) dx = fma(-g.bx, nb, dx);
+        else if constexpr (NZ & 2u) dx = dx + P[r][1];
+        if constexpr (AMB & 4u) dx = fma(-g.cx, nc, dx);
+        else if constexpr (NZ & 4u) dx = dx + P[r][2];
         q[r] = fma(dz, dz, fma(dy, dy, dx * dx));
         t[r] = t_fast64(q[r], g.s, near);
       }
+    };
+    // The counts of NJ consecutive j from j0: the correctly rounded root for
+    // all of them when any lane needs it, then one atomic per pair.
+    auto finish = [&](auto nj_c, const double *q, double *t, uint64_t near, int j0) {
+      constexpr int NJ = decltype(nj_c)::value;
       if (__builtin_expect(near != 0, 0))
 #pragma unroll
-        for (int r = 0; r < R; ++r) t[r] = sqrt_cr(q[r]) * g.s;
+        for (int k = 0; k < NJ * R; ++k) t[k] = sqrt_cr(q[k]) * g.s;
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
+      for (int k = 0; k < NJ * R; ++k) {
+        const int r = k % R;
         uint32_t l = lo[r];
-        if constexpr (DIAG) l = jt + j > wbase + r * 64 + lane ? l : hi;
-        count_t(t[r], l, 0u);
+        if constexpr (DIAG) l = jt + j0 + k / R > wbase + r * 64 + lane ? l : hi;
+        count_t(t[k], l, 0u);
       }
     };
-    // One pass over the group's j: the next j is read before the current
-    // j's atomics (see sorted_tile); at the end of the group the look-ahead
-    // read touches the entry after it (the next group, the other tile or the
-    // box area), never used.
-    auto run_j = [&](auto amb_c, auto zero_c) {
+    // One pass over the group's j, two j per step with one ballot. The next
+    // two j are read before the current ones' atomics (see sorted_tile); at
+    // the end of the group the look-ahead reads touch at most the two entries
+    // after it (the next group, the other tile or the box area), never used.
+    auto run_j = [&](auto amb_c, auto nz_c) {
+      using Two = std::integral_constant<int, 2>;
+      using One = std::integral_constant<int, 1>;
       int vzero;
       asm volatile("v_mov_b32 %0, 0" : "=v"(vzero));
       const double4 *cp = tb + j_begin + vzero;
-      double4 pa = cp[0];
+      double4 pa = cp[0], pb = cp[1];
       int j = j_begin;
       for (; j + 1 < j_end; j += 2, cp += 2) {
-        const double4 pb = cp[1];
-        pairs_of(amb_c, zero_c, pa, j);
+        double q[2 * R], t[2 * R];
+        uint64_t near = big_bins ? ~0ull : 0ull;
+        reduce(amb_c, nz_c, pa, q, t, near);
+        reduce(amb_c, nz_c, pb, q + R, t + R, near);
         pa = cp[2];
-        pairs_of(amb_c, zero_c, pb, j + 1);
+        pb = cp[3];
+        finish(Two{}, q, t, near, j);
       }
-      if (j < j_end) pairs_of(amb_c, zero_c, pa, j);
+      if (j < j_end) {
+        double q[R], t[R];
+        uint64_t near = big_bins ? ~0ull : 0ull;
+        reduce(amb_c, nz_c, pa, q, t, near);
+        finish(One{}, q, t, near, j);
+      }
     };
-    using No = std::integral_constant<bool, false>;
-    using Yes = std::integral_constant<bool, true>;
-    switch (amb) {
-      case 0:
-        if (zero)
-          run_j(std::integral_constant<uint32_t, 0>{}, Yes{});
-        else
-          run_j(std::integral_constant<uint32_t, 0>{}, No{});
-        break;
-      case 1: run_j(std::integral_constant<uint32_t, 1>{}, No{}); break;
-      case 2: run_j(std::integral_constant<uint32_t, 2>{}, No{}); break;
-      case 3: run_j(std::integral_constant<uint32_t, 3>{}, No{}); break;
-      case 4: run_j(std::integral_constant<uint32_t, 4>{}, No{}); break;
-      case 5: run_j(std::integral_constant<uint32_t, 5>{}, No{}); break;
-      case 6: run_j(std::integral_constant<uint32_t, 6>{}, No{}); break;
-      default: run_j(std::integral_constant<uint32_t, 7>{}, No{}); break;
+    using M0 = std::integral_constant<uint32_t, 0>;
+    using M1 = std::integral_constant<uint32_t, 1>;
+    using M2 = std::integral_constant<uint32_t, 2>;
+    using M3 = std::integral_constant<uint32_t, 3>;
+    using M4 = std::integral_constant<uint32_t, 4>;
+    using M5 = std::integral_constant<uint32_t, 5>;
+    using M6 = std::integral_constant<uint32_t, 6>;
+    using M7 = std::integral_constant<uint32_t, 7>;
+    if constexpr (DIAG) {
+      // items on the diagonal of a histogram (few pairs): Eq. 5 throughout
+      run_j(M7{}, M0{});
+    } else {
+      // the frequent kinds get their own loop (shared shifts along one axis
+      // at most, or one rounded axis with zero shifts along the others);
+      // the rest round their ambiguous axes and add the terms of all others
+      switch (amb * 8u + nz) {
+        case 0: run_j(M0{}, M0{}); break;
+        case 1: run_j(M0{}, M1{}); break;
+        case 2: run_j(M0{}, M2{}); break;
+        case 4: run_j(M0{}, M4{}); break;
+        case 8: run_j(M1{}, M0{}); break;
+        case 16: run_j(M2{}, M0{}); break;
+        case 32: run_j(M4{}, M0{}); break;
+        default:
+          switch (amb) {
+            case 0: run_j(M0{}, M7{}); break;
+            case 1: run_j(M1{}, M6{}); break;
+            case 2: run_j(M2{}, M5{}); break;
+            case 3: run_j(M3{}, M4{}); break;
+            case 4: run_j(M4{}, M3{}); break;
+            case 5: run_j(M5{}, M2{}); break;
+            case 6: run_j(M6{}, M1{}); break;
+            default: run_j(M7{}, M0{}); break;
+          }
+      }
     }
   }
 }
@@ -1124,9 +1176,8 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
   asm volatile("" : "+v"(my_lds_m));
   // bin bits of slot 0 of this window
   const uint32_t sweep_base = kMagicBits + static_cast<uint32_t>(b_lo) - s0;
-  // largest slot index of binary64 unclamped items (fmin's operands must be
-  // canonical; the compiler may still re-canonicalise it in the loop)
-  const double cap64 = __builtin_canonicalize(static_cast<double>(a.stride - 1));
+  // largest slot index of binary64 unclamped items
+  const double cap64 = static_cast<double>(a.stride - 1);
 
   // i-particles: wave w holds [wbase, wbase + 64R), lane l the R values
   // wbase + r*64 + l
@@ -1253,10 +1304,10 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
         if constexpr (!CLAMP) {
           // binary64 reads raw device coordinates: cap t so that even
           // non-finite or absurd input stays inside the LDS histogram
-          idx = static_cast<uint32_t>(fmin(t, cap64));
+          idx = static_cast<uint32_t>(min_arith(t, cap64));
         } else {
           // floor(t), saturated; t >= 0 always
-          idx = static_cast<uint32_t>(fmin(t, 4294967295.0));
+          idx = static_cast<uint32_t>(min_arith(t, 4294967295.0));
           if constexpr (SWEEP) idx -= static_cast<uint32_t>(b_lo);
           idx = max(min(idx, hi), l);
         }
