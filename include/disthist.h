@@ -139,9 +139,13 @@ int dh_histo(const double *coords, const int64_t *offsets, int32_t n_species,
              int32_t precision, uint64_t *out);
 
 /*
- * Creates a context on HIP device `device`. The context owns device scratch
- * (staged coordinates, work lists, counters) that grows on demand and is
- * reused; it never frees caller memory.
+ * Creates a context on HIP device `device` (the per-device state of the
+ * paper's GPU kernel: the device buffers it keeps between calls and reuses
+ * for every frame, Sec. 3.2). The context owns device scratch (staged
+ * coordinates, work lists, counters) that grows on demand and is reused; it
+ * never frees caller memory. *ctx receives the handle (NULL on failure);
+ * DH_EINVAL for a device index out of range, DH_ENOMEM or DH_EDEVICE if the
+ * device cannot be set up.
  */
 int dh_ctx_create(int32_t device, dh_ctx **ctx);
 
@@ -154,7 +158,10 @@ void dh_ctx_destroy(dh_ctx *ctx);
 const char *dh_ctx_last_error(const dh_ctx *ctx);
 
 /*
- * Asynchronous histogram of one frame already resident in device memory.
+ * Asynchronous histogram of one frame already resident in device memory
+ * (Algorithm 1 with Eq. 5's minimum image, Sec. 2.2; the GPU kernel of
+ * Sec. 3.2: coordinates staged once per frame, pairs counted into
+ * sub-histograms in shared memory and summed into d_out).
  *   d_coords         device [N][3] binary64; read by kernels on `stream`
  *                    after the call returns, so it must stay valid until
  *                    the stream reaches this work.

@@ -947,7 +947,7 @@ __device__ __forceinline__ bool group_shift64(double ilo, double ihi, double jlo
 // One j-tile of a spatially sorted binary64 frame for one wave. For every
 // group of 64 j-points and every slice r of the wave's i-points, each axis
 // whose Eq. 5 shift n is shared by all their pairs (group_shift64) and whose
-// terms B n are exact binary64 numbers skips that axis's fractional
+// terms B n are exact (|n| <= 1) skips that axis's fractional
 // coordinate and rounding: each fused step of Eq. 5 with that n, d - B_k n
 // rounded once, equals the plain sum d + P_k with the exact term
 // P_k = -B_k n. The other axes take Eq. 5's own steps. A pass over the
@@ -981,7 +981,8 @@ __device__ __forceinline__ void sorted_tile64(
     // nz: bit k when some slice has a shared non-zero shift along axis k
     uint32_t amb = 0, nz = 0;
     // exact terms, in the order of the canonical steps: x of a, b, c; y of
-    // b, c; z of c (zero where the axis takes the rounding)
+    // b, c; z of c (zero where the axis takes the rounding). A shared shift
+    // is used only for |n| <= 1, where the terms -B_k n are exact.
     double P[R][6];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -991,19 +992,20 @@ __device__ __forceinline__ void sorted_tile64(
       if (ibox[r][0] <= ibox[r][3]) {
         const double m = fma(hmax * (ibox[r][6] + jb[6]), 0x1p-48, 0x1p-40);
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
-          if (!group_shift64(ibox[r][k], ibox[r][3 + k], jb[k], jb[3 + k], m, n[k]))
+        for (int k = 0; k < 3; ++k) {
+          const bool shared = group_shift64(ibox[r][k], ibox[r][3 + k], jb[k], jb[3 + k], m, n[k]);
+          if (!(shared && fabs(n[k]) <= 1.0)) {
             amb_r |= 1u << k;
+            n[k] = 0.0;
+          }
+        }
       }
-      const double c[6] = {g.ax, g.bx, g.cx, g.by, g.cy, g.cz};
-      constexpr int axis[6] = {0, 1, 2, 1, 2, 2};
-#pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        const double nk = amb_r & (1u << axis[k]) ? 0.0 : n[axis[k]];
-        const double t = -c[k] * nk;
-        if (fma(-c[k], nk, -t) != 0.0) amb_r |= 1u << axis[k];  // not exact
-        P[r][k] = uni(t);
-      }
+      P[r][0] = uni(-g.ax * n[0]);
+      P[r][1] = uni(-g.bx * n[1]);
+      P[r][2] = uni(-g.cx * n[2]);
+      P[r][3] = uni(-g.by * n[1]);
+      P[r][4] = uni(-g.cy * n[2]);
+      P[r][5] = uni(-g.cz * n[2]);
       amb |= amb_r;
 #pragma unroll
       for (int k = 0; k < 3; ++k)
