@@ -13,23 +13,28 @@ enum BoxKind : int32_t {
   kBoxTric = 2,        // Eq. 5 reduction only (r_max below half the smallest width)
   kBoxTricSearch = 3,  // Eq. 5 reduction, then the 27 neighbouring images
   kBoxCube = 4,        // binary32 only: orthorhombic cell with equal edges
-  // triclinic cell without image search, points spatially sorted within each
-  // species at staging (frames of at least kSortMinPoints)
+  // Eq. 5 reduction only, points spatially sorted within each species at
+  // staging (frames of at least kSortMinPoints; see staged_kind)
   kBoxTricSorted = 5,
 };
 
 // Largest species count of a frame (the staging kernels take the offsets by
 // value).
 constexpr int kMaxSpeciesStage = 64;
-// triclinic frames (no image search) with at least this many points are
-// staged in spatial order (kBoxTricSorted)
+// frames with at least this many points may be staged in spatial order
+// (kBoxTricSorted, see staged_kind)
 constexpr int64_t kSortMinPoints = int64_t{1} << 16;
 
 // The minimum-image kind the kernels use for a frame: the geometric kind of
-// frame_constants, with large triclinic frames staged in spatial order (both
-// precisions) and the binary32 special case of equal orthorhombic edges.
+// frame_constants, with large frames staged in spatial order (triclinic
+// frames in both precisions; orthorhombic ones in binary64, where the sorted
+// kernel with a diagonal cell matrix gives the orthorhombic sequence's
+// counts bit for bit) and the binary32 special case of equal orthorhombic
+// edges.
 inline int staged_kind(int kind, int precision, const double L[3], int64_t n_points) {
-  if (kind == kBoxTric && n_points >= kSortMinPoints) return kBoxTricSorted;
+  if (n_points >= kSortMinPoints &&
+      (kind == kBoxTric || (kind == kBoxOrtho && precision != 0)))
+    return kBoxTricSorted;
   if (precision != 0) return kind;
   if (kind == kBoxOrtho && L[0] == L[1] && L[1] == L[2]) return kBoxCube;
   return kind;
@@ -58,6 +63,14 @@ constexpr int32_t kItemDiag = 1;  // i- and j-range are the same block: count j 
 constexpr int32_t kItemFull = 2;  // every lane holds a valid i-particle
 
 constexpr int kShifts = 27;
+// index of the zero shift (i = j = k = 0) in the shift tables
+constexpr int kZeroShift = 13;
+// rows of the per-octant image lists (8 octants and the full list) and
+// bytes per row (a count and kShifts indices)
+constexpr int kOctRows = 9;
+constexpr int kOctRowBytes = kShifts + 1;
+// slack e of the octant boxes in fractional coordinates (see octant_images)
+constexpr double kOctSlack = 0x1p-30;
 constexpr int kDump = 64;  // per-lane discard slots after the bin window
 // Per-wave LDS ring of reduced vectors waiting for the 27-image search:
 // one j adds at most 64 per i-particle of a lane (R) on top of fewer than 64.
@@ -110,6 +123,12 @@ struct FrameParams {
   // s = n_bins / r_max, rounded to binary32
   float cell32[6];
   float s32;
+  // image search: for each octant of a reduced vector's fractional
+  // coordinates (bit k set when component k is negative) the images that
+  // can be nearer than the vector itself; row 8 lists every image. Row
+  // layout: the count, then indices into the shift tables, padded with the
+  // zero shift (kZeroShift) to kShifts entries.
+  uint8_t oct_shift[kOctRows][kOctRowBytes];
 };
 
 // LDS of a spatially sorted frame's pair kernel besides its two j-tiles:

@@ -465,18 +465,23 @@ __device__ __forceinline__ uint32_t bits32_packed_c(uint64_t ab_j, uint64_t neg_
   }
 }
 
-// Minimum of q over the 27 images, shifts read from an LDS table (broadcast
-// reads); the same operations as search_q64 / search_q32.
+// Minimum of q over the images of the vector's octant list (row `code` of
+// the per-octant lists in LDS: a count, then shift indices padded with the
+// zero shift), three running minima; the wave runs to its longest list.
+// Images left out of a list cannot be nearer (see octant_images on the
+// host), so the minimum equals the one over all 27 images.
 template <typename T>
-__device__ __forceinline__ T search_lds(T dx, T dy, T dz, T q,
-                                        const typename V4<T>::type *__restrict__ sh) {
+__device__ __forceinline__ T search_oct(T dx, T dy, T dz, T q, int code,
+                                        const typename V4<T>::type *__restrict__ sh,
+                                        const uint8_t *__restrict__ octs) {
+  const uint8_t *row = octs + code * kOctRowBytes;
+  const uint32_t n = wave_max_u32(row[0]);
   T qa = q, qb = q, qc = q;
-#pragma unroll
-  for (int m = 0; m < kShifts; m += 3) {
+  for (uint32_t k = 0; k < n; k += 3) {
     T v[3];
 #pragma unroll
     for (int u = 0; u < 3; ++u) {
-      const typename V4<T>::type S = sh[m + u];
+      const typename V4<T>::type S = sh[row[1 + k + u]];
       const T vx = dx + S.x;
       const T vy = dy + S.y;
       const T vz = dz + S.z;
@@ -487,6 +492,31 @@ __device__ __forceinline__ T search_lds(T dx, T dy, T dz, T q,
     qc = fmin(qc, v[2]);
   }
   return fmin(qa, fmin(qb, qc));
+}
+
+// Octant row of a reduced binary64 vector: bit k when fractional component k
+// is negative; the full list when a component lies outside the octant boxes
+// of the host (|f| beyond 1/2 plus half their slack, or NaN).
+__device__ __forceinline__ int octant64(double dx, double dy, double dz, const Geo64 &g) {
+  double f[3];
+  frac64(dx, dy, dz, g, f);
+  int code = 0;
+  bool inside = true;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    code |= f[k] < 0.0 ? 1 << k : 0;
+    inside = inside && fabs(f[k]) <= 0.5 + 0.5 * kOctSlack;
+  }
+  return inside ? code : kOctRows - 1;
+}
+
+// Octant row of a reduced binary32 vector from its wrapped fixed-point
+// differences (exact, within [-1/2, 1/2) of a cell vector).
+__device__ __forceinline__ int octant32(uint64_t ab_j, uint64_t neg_ab_i, float zi, float zj) {
+  const uint64_t dab = ab_j + neg_ab_i;
+  return (static_cast<int32_t>(static_cast<uint32_t>(dab)) < 0 ? 1 : 0) |
+         (static_cast<int32_t>(static_cast<uint32_t>(dab >> 32)) < 0 ? 2 : 0) |
+         (static_cast<int32_t>(__float_as_uint(zj) - __float_as_uint(zi)) < 0 ? 4 : 0);
 }
 
 template <typename T>
@@ -1342,6 +1372,9 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
       S.w = T(0);
       sh[tid] = S;
     }
+    uint8_t *octs = reinterpret_cast<uint8_t *>(sh + kShifts);
+    for (int k = tid; k < kOctRows * kOctRowBytes; k += blockDim.x)
+      octs[k] = F->oct_shift[k / kOctRowBytes][k % kOctRowBytes];
   }
   // searches and counts the `cnt` (<= 64) oldest queued vectors
   auto drain = [&](int cnt) {
@@ -1352,7 +1385,9 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
       if (idx >= cap) idx -= cap;
       const V e = wq[idx];
       T q = fmaT(e.z, e.z, fmaT(e.y, e.y, e.x * e.x));
-      q = search_lds<T>(e.x, e.y, e.z, q, sh);
+      // entry w: the octant row of the vector (0..8, exact in T)
+      q = search_oct<T>(e.x, e.y, e.z, q, static_cast<int>(e.w), sh,
+                        reinterpret_cast<const uint8_t *>(sh + kShifts));
       if constexpr (sizeof(T) == 4)
         count_t(bin_bits32(__builtin_amdgcn_sqrtf(q)), v ? 0u : hi, v ? kMagicBits - 1u : hib);
       else
@@ -1520,8 +1555,14 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
               if (need) {
                 int pos = head + qn + below;  // < 2 cap: head < cap, qn + below < cap
                 if (pos >= cap) pos -= cap;
+                int code;
+                if constexpr (kPacked)
+                  code = octant32(pj.ab, nab[r], zi[r],
+                                  __uint_as_float(static_cast<uint32_t>(pj.cc)));
+                else
+                  code = octant64(dx, dy, dz, g);
                 V e;
-                e.x = dx; e.y = dy; e.z = dz; e.w = T(0);
+                e.x = dx; e.y = dy; e.z = dz; e.w = static_cast<T>(code);
                 wq[pos] = e;
               }
               qn += __builtin_popcountll(m);

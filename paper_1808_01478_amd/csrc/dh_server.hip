@@ -226,12 +226,14 @@ namespace {
 
 // Device bytes a job holds while resident: its coordinates, the staged copy
 // (and the sort keys of a spatially sorted frame), histograms, out-of-range
-// and pair counts. Large triclinic frames are counted as if sorted, an
-// upper bound that needs no cell geometry.
+// and pair counts. Large frames that may be staged in spatial order are
+// counted as if sorted, an upper bound that needs no cell geometry.
 int64_t job_footprint(int64_t n, int32_t n_hist, int32_t n_bins, int32_t precision,
                       int32_t box_type) {
   const int64_t pts = std::max<int64_t>(1, n);
-  const bool may_sort = box_type == DH_BOX_TRICLINIC && n >= dh::kSortMinPoints;
+  const bool may_sort = (box_type == DH_BOX_TRICLINIC ||
+                         (box_type == DH_BOX_ORTHO && precision == DH_FP64)) &&
+                        n >= dh::kSortMinPoints;
   return pts * 3 * static_cast<int64_t>(sizeof(double)) +
          pts * (precision == DH_FP64 || may_sort ? 32 : 16) +
          (may_sort ? dh::sort_keys_count(n) * 8 : 0) +

@@ -74,13 +74,21 @@ def parity_cases():
     grid = np.stack(np.meshgrid(*[np.arange(8) / 8.0] * 3, indexing="ij"), -1).reshape(-1, 3)
     out.append(_frame(grid @ cell, [300, len(grid) - 300], workloads.BOX_TRICLINIC, cell,
                       0.75 * workloads.min_width(cell), 97, "tric-search-lattice-ties"))
-    # binary32 triclinic frames of at least 65,536 points are staged in
-    # spatial order and take the group-shift path: a clustered frame, and
-    # unwrapped uniform points with a one-point species
+    # triclinic frames of at least 65,536 points are staged in spatial order
+    # and take the group-shift path: a clustered frame, and unwrapped uniform
+    # points with a one-point species
     c3s = workloads.triclinic(n=70_000)
     c3s.name = "tric-clustered-70k-sorted"
     out.append(c3s)
     xs = rng.uniform(-1.0, 2.0, size=(66_001, 3)) @ SKEW
     out.append(_frame(xs, [40_000, 1, 26_000], workloads.BOX_TRICLINIC, SKEW, 0.49 * w, 600,
                       "tric-unwrapped-66k-sorted"))
+    # binary64 orthorhombic frames of at least 65,536 points take the sorted
+    # kernel with a diagonal cell matrix: unwrapped points (shifts beyond one
+    # cell), three species with a one-point species, r_max beyond half the
+    # shortest edge
+    xo = rng.uniform(-25.0, 45.0, size=(67_001, 3))
+    out.append(_frame(xo, [30_000, 1, 37_000], workloads.BOX_ORTHO,
+                      workloads.ortho_box(20.0, 23.0, 26.0), 11.0, 800,
+                      "ortho-unwrapped-67k-sorted"))
     return out

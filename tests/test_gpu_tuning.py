@@ -38,8 +38,11 @@ FRAMES = [
                            r_max=0.45 * workloads.min_width(SKEW), n_bins=1500),
     workloads.random_frame(503, [3000], workloads.BOX_NONE, r_max=8.0, n_bins=45_000),
     workloads.triclinic(n=8000),
-    # binary32: spatially sorted staging (at least 65,536 points)
+    # spatially sorted staging (at least 65,536 points): triclinic, and
+    # orthorhombic in binary64
     workloads.triclinic(n=70_000),
+    workloads.random_frame(504, [40_000, 26_000], workloads.BOX_ORTHO,
+                           box=workloads.ortho_box(30.0, 32.0, 34.0), r_max=14.0, n_bins=3000),
 ]
 
 SHAPES = [dict(zip(("r", "copies", "tj", "noclamp", "occ_cap", "items_per_wg", "threads",
