@@ -201,45 +201,50 @@ double min_width_tri(double ax, double bx, double by, double cx, double cy, doub
 // rounding of either, so the minimum over the list is the minimum over all
 // 27, bit for bit (ties, g = 0 on a face of the box, stay in the list). The
 // kernel assigns a vector to an octant only when its computed fractional
-// coordinates lie within e/2 of the box, else to the full list.
+// coordinates lie within e/2 of the box, else to the full list, as it does
+// for octants with more than kOctCap images.
 void octant_images(FrameParams &fp) {
   const double B[3][3] = {{fp.ax, 0.0, 0.0}, {fp.bx, fp.by, 0.0}, {fp.cx, fp.cy, fp.cz}};
   const double size = std::fabs(fp.ax) + std::fabs(fp.bx) + std::fabs(fp.by) +
                       std::fabs(fp.cx) + std::fabs(fp.cy) + std::fabs(fp.cz);
   const double margin = std::ldexp(size * size, -30);
   const double e = kOctSlack;
-  for (int o = 0; o < kOctRows; ++o) {
-    uint8_t *row = fp.oct_shift[o];
+  fp.oct_full = 0;
+  int longest = 0;
+  for (int o = 0; o < 8; ++o) {
+    int list[kShifts];
     int len = 0;
     for (int m = 0; m < kShifts; ++m) {
       if (m == kZeroShift) continue;
-      bool keep = o == kOctRows - 1;
-      if (!keep) {
-        const double *S = fp.shift64[m];
-        const double s2 = S[0] * S[0] + S[1] * S[1] + S[2] * S[2];
-        double gmin = 0.0;
-        for (int v = 0; v < 8; ++v) {
-          double f[3];
-          for (int k = 0; k < 3; ++k) {
-            const bool neg = (o >> k) & 1;
-            const bool hi = (v >> k) & 1;
-            f[k] = neg ? (hi ? e : -0.5 - e) : (hi ? 0.5 + e : -e);
-          }
-          double dot = 0.0;
-          for (int c = 0; c < 3; ++c) {
-            const double bf = f[0] * B[0][c] + f[1] * B[1][c] + f[2] * B[2][c];
-            dot += bf * S[c];
-          }
-          const double gv = 2.0 * dot + s2;
-          gmin = v == 0 ? gv : std::min(gmin, gv);
+      const double *S = fp.shift64[m];
+      const double s2 = S[0] * S[0] + S[1] * S[1] + S[2] * S[2];
+      double gmin = 0.0;
+      for (int v = 0; v < 8; ++v) {
+        double f[3];
+        for (int k = 0; k < 3; ++k) {
+          const bool neg = (o >> k) & 1;
+          const bool hi = (v >> k) & 1;
+          f[k] = neg ? (hi ? e : -0.5 - e) : (hi ? 0.5 + e : -e);
         }
-        keep = !(gmin > margin);
+        double dot = 0.0;
+        for (int c = 0; c < 3; ++c) {
+          const double bf = f[0] * B[0][c] + f[1] * B[1][c] + f[2] * B[2][c];
+          dot += bf * S[c];
+        }
+        const double gv = 2.0 * dot + s2;
+        gmin = v == 0 ? gv : std::min(gmin, gv);
       }
-      if (keep) row[1 + len++] = static_cast<uint8_t>(m);
+      if (!(gmin > margin)) list[len++] = m;
     }
-    row[0] = static_cast<uint8_t>(len);
-    for (int k = len; k < kShifts; ++k) row[1 + k] = static_cast<uint8_t>(kZeroShift);
+    if (len > kOctCap) {
+      fp.oct_full |= static_cast<uint8_t>(1u << o);
+      len = 0;
+    }
+    longest = std::max(longest, len);
+    for (int k = 0; k < kOctCap; ++k)
+      fp.oct_shift[o][k] = static_cast<uint8_t>(k < len ? list[k] : kZeroShift);
   }
+  fp.oct_n = static_cast<uint8_t>((longest + 2) / 3 * 3);
 }
 
 int frame_consts(int32_t box_type, const double *box, double r_max, int32_t n_bins,
@@ -330,11 +335,11 @@ struct Launch {
 
 size_t coord_bytes(int precision) { return precision == DH_FP64 ? 32 : 16; }
 
-// LDS of the image-search rings (one per wave), the table of the 27 shift
-// vectors, the per-octant image lists and the padding before them.
+// LDS of the image-search rings (one per wave), the table of the shift
+// vectors (per-octant lists and all 27) and the padding before them.
 size_t search_queue_bytes(int precision, int threads, int r) {
-  return 32 + (static_cast<size_t>(threads / 64) * queue_cap(r) + kShifts) * coord_bytes(precision) +
-         static_cast<size_t>(kOctRows) * kOctRowBytes;
+  return 32 + (static_cast<size_t>(threads / 64) * queue_cap(r) + kSearchTable) *
+                  coord_bytes(precision);
 }
 
 // Smallest work item (pairs) when a frame is split into bounded launches.

@@ -65,10 +65,12 @@ constexpr int32_t kItemFull = 2;  // every lane holds a valid i-particle
 constexpr int kShifts = 27;
 // index of the zero shift (i = j = k = 0) in the shift tables
 constexpr int kZeroShift = 13;
-// rows of the per-octant image lists (8 octants and the full list) and
-// bytes per row (a count and kShifts indices)
-constexpr int kOctRows = 9;
-constexpr int kOctRowBytes = kShifts + 1;
+// the image search keeps at most kOctCap images per octant of a reduced
+// vector (octants that need more search all 27)
+constexpr int kOctCap = 12;
+// the search's LDS table: 8 octant rows of kOctCap shift vectors, then the
+// 27 shift vectors (the full list)
+constexpr int kSearchTable = 8 * kOctCap + kShifts;
 // slack e of the octant boxes in fractional coordinates (see octant_images)
 constexpr double kOctSlack = 0x1p-30;
 constexpr int kDump = 64;  // per-lane discard slots after the bin window
@@ -125,10 +127,13 @@ struct FrameParams {
   float s32;
   // image search: for each octant of a reduced vector's fractional
   // coordinates (bit k set when component k is negative) the images that
-  // can be nearer than the vector itself; row 8 lists every image. Row
-  // layout: the count, then indices into the shift tables, padded with the
-  // zero shift (kZeroShift) to kShifts entries.
-  uint8_t oct_shift[kOctRows][kOctRowBytes];
+  // can be nearer than the vector itself, as indices into the shift tables
+  // padded with the zero shift (kZeroShift); oct_full bit o when octant o
+  // needs more than kOctCap images (it searches all 27); oct_n the longest
+  // of the other lists, rounded up to a multiple of 3
+  uint8_t oct_shift[8][kOctCap];
+  uint8_t oct_full;
+  uint8_t oct_n;
 };
 
 // LDS of a spatially sorted frame's pair kernel besides its two j-tiles:

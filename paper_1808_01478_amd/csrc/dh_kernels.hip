@@ -465,37 +465,44 @@ __device__ __forceinline__ uint32_t bits32_packed_c(uint64_t ab_j, uint64_t neg_
   }
 }
 
-// Minimum of q over the images of the vector's octant list (row `code` of
-// the per-octant lists in LDS: a count, then shift indices padded with the
-// zero shift), three running minima; the wave runs to its longest list.
-// Images left out of a list cannot be nearer (see octant_images on the
-// host), so the minimum equals the one over all 27 images.
+// min(a, b) of two arithmetic results (never signalling NaNs), without the
+// canonicalisation fmin adds; a NaN operand gives the other, as fmin does.
+__device__ __forceinline__ float min_arith(float a, float b) {
+  float r;
+  asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
+// Minimum of q over the images in the search table from `base` (an octant
+// row, or the 27 shift vectors), n of them, three running minima. Rows are
+// padded with the zero shift, and a run past a row's end reads further
+// table entries, which are images too, so the minimum is unchanged; images
+// left out of an octant row cannot be nearer (see octant_images on the
+// host), so it equals the one over all 27 images.
 template <typename T>
-__device__ __forceinline__ T search_oct(T dx, T dy, T dz, T q, int code,
-                                        const typename V4<T>::type *__restrict__ sh,
-                                        const uint8_t *__restrict__ octs) {
-  const uint8_t *row = octs + code * kOctRowBytes;
-  const uint32_t n = wave_max_u32(row[0]);
+__device__ __forceinline__ T search_oct(T dx, T dy, T dz, T q, int base, int n,
+                                        const typename V4<T>::type *__restrict__ tab) {
   T qa = q, qb = q, qc = q;
-  for (uint32_t k = 0; k < n; k += 3) {
+  const typename V4<T>::type *row = tab + base;
+  for (int k = 0; k < n; k += 3) {
     T v[3];
 #pragma unroll
     for (int u = 0; u < 3; ++u) {
-      const typename V4<T>::type S = sh[row[1 + k + u]];
+      const typename V4<T>::type S = row[k + u];
       const T vx = dx + S.x;
       const T vy = dy + S.y;
       const T vz = dz + S.z;
       v[u] = fmaT(vz, vz, fmaT(vy, vy, vx * vx));
     }
-    qa = fmin(qa, v[0]);
-    qb = fmin(qb, v[1]);
-    qc = fmin(qc, v[2]);
+    qa = min_arith(qa, v[0]);
+    qb = min_arith(qb, v[1]);
+    qc = min_arith(qc, v[2]);
   }
-  return fmin(qa, fmin(qb, qc));
+  return min_arith(qa, min_arith(qb, qc));
 }
 
-// Octant row of a reduced binary64 vector: bit k when fractional component k
-// is negative; the full list when a component lies outside the octant boxes
+// Octant of a reduced binary64 vector: bit k when fractional component k is
+// negative; 8 (the full list) when a component lies outside the octant boxes
 // of the host (|f| beyond 1/2 plus half their slack, or NaN).
 __device__ __forceinline__ int octant64(double dx, double dy, double dz, const Geo64 &g) {
   double f[3];
@@ -507,10 +514,10 @@ __device__ __forceinline__ int octant64(double dx, double dy, double dz, const G
     code |= f[k] < 0.0 ? 1 << k : 0;
     inside = inside && fabs(f[k]) <= 0.5 + 0.5 * kOctSlack;
   }
-  return inside ? code : kOctRows - 1;
+  return inside ? code : 8;
 }
 
-// Octant row of a reduced binary32 vector from its wrapped fixed-point
+// Octant of a reduced binary32 vector from its wrapped fixed-point
 // differences (exact, within [-1/2, 1/2) of a cell vector).
 __device__ __forceinline__ int octant32(uint64_t ab_j, uint64_t neg_ab_i, float zi, float zj) {
   const uint64_t dab = ab_j + neg_ab_i;
@@ -1362,19 +1369,24 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
     qskip = uni(F->qskip64);
   if constexpr (SEARCH) {
     // this frame's shift table; read after the first tile barrier below
-    if (tid < kShifts) {
+    // the search table: the 8 octant rows, then all 27 shift vectors
+    for (int k = tid; k < kSearchTable; k += blockDim.x) {
+      const int m = k < 8 * kOctCap ? F->oct_shift[k / kOctCap][k % kOctCap] : k - 8 * kOctCap;
       V S;
       if constexpr (sizeof(T) == 4) {
-        S.x = F->shift32[tid][0]; S.y = F->shift32[tid][1]; S.z = F->shift32[tid][2];
+        S.x = F->shift32[m][0]; S.y = F->shift32[m][1]; S.z = F->shift32[m][2];
       } else {
-        S.x = F->shift64[tid][0]; S.y = F->shift64[tid][1]; S.z = F->shift64[tid][2];
+        S.x = F->shift64[m][0]; S.y = F->shift64[m][1]; S.z = F->shift64[m][2];
       }
       S.w = T(0);
-      sh[tid] = S;
+      sh[k] = S;
     }
-    uint8_t *octs = reinterpret_cast<uint8_t *>(sh + kShifts);
-    for (int k = tid; k < kOctRows * kOctRowBytes; k += blockDim.x)
-      octs[k] = F->oct_shift[k / kOctRowBytes][k % kOctRowBytes];
+  }
+  [[maybe_unused]] uint32_t oct_full = 0;
+  [[maybe_unused]] int oct_n = 0;
+  if constexpr (SEARCH) {
+    oct_full = static_cast<uint32_t>(uni(static_cast<int>(F->oct_full)));
+    oct_n = uni(static_cast<int>(F->oct_n));
   }
   // searches and counts the `cnt` (<= 64) oldest queued vectors
   auto drain = [&](int cnt) {
@@ -1385,9 +1397,12 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
       if (idx >= cap) idx -= cap;
       const V e = wq[idx];
       T q = fmaT(e.z, e.z, fmaT(e.y, e.y, e.x * e.x));
-      // entry w: the octant row of the vector (0..8, exact in T)
-      q = search_oct<T>(e.x, e.y, e.z, q, static_cast<int>(e.w), sh,
-                        reinterpret_cast<const uint8_t *>(sh + kShifts));
+      // entry w: the vector's octant, 8 for the full list (exact in T); the
+      // wave runs the full list when any of its vectors needs it
+      const int code = static_cast<int>(e.w);
+      const bool full = __builtin_amdgcn_ballot_w64(code == 8) != 0;
+      q = search_oct<T>(e.x, e.y, e.z, q, code == 8 ? 8 * kOctCap : code * kOctCap,
+                        full ? kShifts : oct_n, sh);
       if constexpr (sizeof(T) == 4)
         count_t(bin_bits32(__builtin_amdgcn_sqrtf(q)), v ? 0u : hi, v ? kMagicBits - 1u : hib);
       else
@@ -1561,6 +1576,7 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
                                   __uint_as_float(static_cast<uint32_t>(pj.cc)));
                 else
                   code = octant64(dx, dy, dz, g);
+                if ((oct_full >> code) & 1u) code = 8;
                 V e;
                 e.x = dx; e.y = dy; e.z = dz; e.w = static_cast<T>(code);
                 wq[pos] = e;
@@ -1587,8 +1603,15 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
       // a read issued after the atomics would wait for all of them
       // (bank-conflicted) before the arithmetic could start.
       if constexpr (SEARCH) {
-        // one copy of the search code: a plain j loop
-        for (int jj = js; jj < jcount; ++jj) pairs_of(load_j(jj), jt + jj);
+        // one copy of the search code: a plain j loop whose next j is read
+        // before the current one's atomics (at the end of the tile the
+        // look-ahead reads the entry just past it, never used)
+        J pn = load_j(js);
+        for (int jj = js; jj < jcount; ++jj) {
+          const J pc = pn;
+          pn = load_j(jj + 1);
+          pairs_of(pc, jt + jj);
+        }
       } else {
         // j is read through a pointer kept in a VGPR, so the two reads of an
         // iteration use immediate offsets and one add moves it on (a uniform
