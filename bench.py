@@ -33,9 +33,10 @@ import workloads  # noqa: E402
 # algorithmic FLOPs per pair of the canonical op sequence (add, sub, mul,
 # sqrt, rint, min: 1; fma: 2)
 FLOPS_PER_PAIR = {0: 10, 1: 22, 2: 34, 3: 268}
-# a searched pair adds 26 images (3 adds, mul + 2 fma: 8 FLOPs each) and 26
-# minima to the 34 FLOPs of the reduced pair
-SEARCH_FLOPS = 26 * 9
+# an image of the search costs 3 adds, mul + 2 fma (8 FLOPs) and a minimum;
+# the canonical search adds 26 images to the 34 FLOPs of the reduced pair
+IMAGE_FLOPS = 9
+SEARCH_FLOPS = 26 * IMAGE_FLOPS
 PEAK_TFLOPS = {0: 157.3, 1: 78.6}        # MI355X vector FP32 / FP64
 KERNEL_NAME = "pairs_kernel"
 
@@ -211,8 +212,10 @@ def bench_image_search(steps=3):
                        "species 120,000/80,000, r_max = 0.8 of the smallest width, 4,000 bins",
            "pairs": pairs,
            "flops": f"{FLOPS_PER_PAIR[2]} per pair (Eq. 5 reduction, root, scale) plus "
-                    f"{SEARCH_FLOPS} per searched pair (26 more images and the minimum); "
-                    "the pair kernel counts the searched pairs"}
+                    f"{IMAGE_FLOPS} per image evaluated by the search (the kernel counts the "
+                    "searched pairs and the images it evaluated for them: only the images "
+                    "of each vector's octant list); canonical_search_flops counts all 26 "
+                    "images of every searched pair instead"}
     xt = torch.from_numpy(x).cuda()
     h = torch.empty((3, 4000), dtype=torch.int64, device="cuda")
     with dh.Context(0) as c:
@@ -226,12 +229,17 @@ def bench_image_search(steps=3):
             c.profile(False)
             torch.cuda.synchronize()
             searched = c.searched_pairs()
+            images = c.searched_images()
             ms /= k
-            flops = pairs * FLOPS_PER_PAIR[2] + searched * SEARCH_FLOPS
+            flops = pairs * FLOPS_PER_PAIR[2] + images * IMAGE_FLOPS
             ach = flops / (ms * 1e-3) / 1e12
+            canon = (pairs * FLOPS_PER_PAIR[2] + searched * SEARCH_FLOPS) / (ms * 1e-3) / 1e12
             out[name] = {"kernel_ms": ms, "pairs_per_s": pairs / (ms * 1e-3),
                          "searched_pairs": searched, "searched_frac": searched / pairs,
-                         "achieved_tflops": ach, "roofline_frac": ach / PEAK_TFLOPS[prec]}
+                         "images_per_searched_pair": images / max(1, searched),
+                         "achieved_tflops": ach, "roofline_frac": ach / PEAK_TFLOPS[prec],
+                         "canonical_search_flops": {"achieved_tflops": canon,
+                                                    "roofline_frac": canon / PEAK_TFLOPS[prec]}}
     return out
 
 

@@ -536,6 +536,15 @@ int dh_ctx_profile_read(dh_ctx *ctx, double *kernel_ms, int64_t *launches);
  */
 int dh_ctx_searched_pairs(dh_ctx *ctx, uint64_t *searched);
 
+/*
+ * Images evaluated for those pairs in the same call (Sec. 2.3's neighbouring
+ * images; the kernel evaluates for each searched vector only the images of
+ * its octant list, or all 27, and a wave runs to its longest list, so this
+ * is the arithmetic actually spent on the search). 0 as for
+ * dh_ctx_searched_pairs; same waiting rule and errors.
+ */
+int dh_ctx_searched_images(dh_ctx *ctx, uint64_t *images);
+
 #ifdef __cplusplus
 }
 #endif

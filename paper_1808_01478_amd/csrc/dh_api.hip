@@ -783,10 +783,11 @@ int run_frame(dh_ctx *ctx, hipStream_t st, const FrameJob &job, const Knobs &k, 
   const bool oor_flush = job.d_oor && L.mode != kModeGlobal;
   fp.oor = oor_flush ? job.d_oor : nullptr;
   fp.oor_by_flush = oor_flush ? 1 : 0;
-  // counters: one work counter per launch, then (8-byte aligned) the count
-  // of image-searched pairs; the upload or the zero kernel clears them all
+  // counters: one work counter per launch, then (8-byte aligned) the counts
+  // of image-searched pairs and of the images evaluated for them; the upload
+  // or the zero kernel clears them all
   const size_t n_work_counters = (n_launches + 1) / 2 * 2;
-  const size_t n_counters = n_work_counters + 2;
+  const size_t n_counters = n_work_counters + 4;
   const BlobLayout lay = blob_layout(1, items.size(), pairs.size(), n_counters);
   // the counter's device address goes into the frame constants, so the blob
   // is allocated before they are uploaded (a new allocation is never taken
@@ -1716,6 +1717,17 @@ int dh_ctx_searched_pairs(dh_ctx *ctx, uint64_t *searched) {
   unsigned long long v = 0;
   DH_HIP(ctx, hipMemcpy(&v, ctx->searched_dev, sizeof v, hipMemcpyDeviceToHost));
   *searched = v;
+  return DH_OK;
+}
+
+int dh_ctx_searched_images(dh_ctx *ctx, uint64_t *images) {
+  if (!ctx || !images) return DH_EINVAL;
+  *images = 0;
+  if (!ctx->searched_dev) return DH_OK;
+  DH_HIP(ctx, hipSetDevice(ctx->device));
+  unsigned long long v = 0;
+  DH_HIP(ctx, hipMemcpy(&v, ctx->searched_dev + 1, sizeof v, hipMemcpyDeviceToHost));
+  *images = v;
   return DH_OK;
 }
 

@@ -118,8 +118,9 @@ struct FrameParams {
   int32_t noclamp;     // 1: every t of a full block fits below `stride` slots
   float qskip32;       // binary32 q (t units) below which no image is nearer
   double qskip64;      // binary64 q below which the reduced vector is nearest
-  // image search: pairs that went through the 27-image search are added here
-  // (device, 8-byte aligned) unless null
+  // image search: pairs that went through the image search are added to
+  // searched[0], the images evaluated for them to searched[1] (device,
+  // 8-byte aligned) unless null
   unsigned long long *searched;
   // spatially sorted binary32 frames: the cell rows (ax bx by cx cy cz) and
   // s = n_bins / r_max, rounded to binary32

@@ -1362,6 +1362,7 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
   V *const wq = queue + wave * cap;
   int head = 0, qn = 0;
   [[maybe_unused]] uint64_t n_searched = 0;  // pairs this wave searched in this item
+  [[maybe_unused]] uint64_t n_images = 0;    // images it evaluated for them
   [[maybe_unused]] T qskip;
   if constexpr (sizeof(T) == 4)
     qskip = uni(F->qskip32);
@@ -1400,9 +1401,9 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
       // entry w: the vector's octant, 8 for the full list (exact in T); the
       // wave runs the full list when any of its vectors needs it
       const int code = static_cast<int>(e.w);
-      const bool full = __builtin_amdgcn_ballot_w64(code == 8) != 0;
-      q = search_oct<T>(e.x, e.y, e.z, q, code == 8 ? 8 * kOctCap : code * kOctCap,
-                        full ? kShifts : oct_n, sh);
+      const int n = __builtin_amdgcn_ballot_w64(code == 8) != 0 ? kShifts : oct_n;
+      q = search_oct<T>(e.x, e.y, e.z, q, code == 8 ? 8 * kOctCap : code * kOctCap, n, sh);
+      n_images += static_cast<uint64_t>(cnt) * static_cast<uint64_t>(n);
       if constexpr (sizeof(T) == 4)
         count_t(bin_bits32(__builtin_amdgcn_sqrtf(q)), v ? 0u : hi, v ? kMagicBits - 1u : hib);
       else
@@ -1648,10 +1649,13 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
   }
   if constexpr (SEARCH) {
     if (qn > 0) drain(qn);
-    // one atomic per wave and item (one address for the whole frame)
+    // one atomic per wave and item for each count (one address each for
+    // the whole frame): searched pairs, then the images evaluated for them
     unsigned long long *const searched = F->searched;
-    if (searched != nullptr && n_searched != 0 && lane == 0)
+    if (searched != nullptr && n_searched != 0 && lane == 0) {
       atomicAdd(searched, static_cast<unsigned long long>(n_searched));
+      atomicAdd(searched + 1, static_cast<unsigned long long>(n_images));
+    }
   }
 }
 

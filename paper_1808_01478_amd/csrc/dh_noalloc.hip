@@ -188,7 +188,7 @@ extern "C" int dh_histo_noalloc(dh_stream stream, const double *d_coords,
   const size_t off_fp = 0;
   const size_t off_pairs = align256(off_fp + sizeof(FrameParams));
   const size_t off_counters = align256(off_pairs + static_cast<size_t>(n_hist) * sizeof(uint64_t));
-  const int32_t n_counters = 4;
+  const int32_t n_counters = 6;
   const size_t off_items = align256(off_counters + n_counters * sizeof(int32_t));
   const size_t off_keys = align256(off_items + static_cast<size_t>(n_items) * sizeof(WorkItem));
   const size_t off_staged = align256(off_keys + keys_bytes);

@@ -68,6 +68,7 @@ SIGNATURES = {
     "dh_ctx_profile": ([_vp, _i32], ctypes.c_int),
     "dh_ctx_profile_read": ([_vp, ctypes.POINTER(_f64), ctypes.POINTER(_i64)], ctypes.c_int),
     "dh_ctx_searched_pairs": ([_vp, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+    "dh_ctx_searched_images": ([_vp, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
 }
 
 
@@ -296,6 +297,13 @@ class Context:
         through the 27-image search (wait for its stream first)."""
         v = ctypes.c_uint64()
         _check(LIB.dh_ctx_searched_pairs(self.handle, ctypes.byref(v)), self.handle)
+        return int(v.value)
+
+    def searched_images(self) -> int:
+        """dh_ctx_searched_images: images evaluated for the searched pairs of
+        the last single-frame call (wait for its stream first)."""
+        v = ctypes.c_uint64()
+        _check(LIB.dh_ctx_searched_images(self.handle, ctypes.byref(v)), self.handle)
         return int(v.value)
 
     def pair_t_async(self, d_coords, box_type: int, box, r_max: float, n_bins: int,
