@@ -371,6 +371,27 @@ int32_t dh_sched_select(const int64_t *need_bytes, const double *waited_s, const
                         int32_t n_queued, int64_t free_bytes, int32_t free_slots,
                         double head_wait_limit_s, int32_t *admit);
 
+/*
+ * The image lists of the 27-image search for a triclinic cell (Sec. 2.3's
+ * neighbouring images beyond half the smallest width), as a pure host
+ * function (no device). For each octant o of a reduced vector's fractional
+ * coordinates (bit k of o set when component k is negative), the shift
+ * indices m = 9(i+1) + 3(j+1) + (k+1) of the images i a + j b + k c that can
+ * be nearer than the vector itself, ascending: the other images are farther
+ * at every point of the octant's box by more than a margin, so the minimum
+ * over the list equals the minimum over all 27. The pair kernels search only
+ * these lists, except that an octant whose list is longer than 12 searches
+ * all 27 images (full_mask bit o).
+ *   box        host [3][3], rows a, b, c, as for a histogram call.
+ *   lists      host int32 [8][26], overwritten; entries past an octant's
+ *              count hold 13 (the zero shift).
+ *   counts     host int32 [8], the list lengths.
+ *   full_mask  host int32, the octants searched in full.
+ * Returns DH_OK, or DH_EINVAL for a null pointer or a box a histogram call
+ * would reject.
+ */
+int dh_search_images(const double *box, int32_t *lists, int32_t *counts, int32_t *full_mask);
+
 /* ---------------------------------------------------------------------------
  * Tuned CPU kernel (the paper's cache-blocked CPU kernel, Sec. 3.1: tiles
  * sized for the L2, triangular tiles on the diagonal, coordinates as

@@ -8,7 +8,8 @@ no CPU fallback).
 """
 _EXPORTS = (
     "BOX_NONE", "BOX_ORTHO", "BOX_TRICLINIC", "FP32", "FP64", "Batch", "Context", "DisthistError",
-    "LIB_PATH", "KNOB_NAMES", "Server", "sched_select", "TUNE_CACHED", "TUNE_OFF", "TUNE_ON", "check_args",
+    "LIB_PATH", "KNOB_NAMES", "Server", "sched_select", "TUNE_CACHED", "TUNE_OFF", "TUNE_ON",
+    "check_args", "search_images",
     "exported_symbols", "histo", "n_hist", "version", "MODE_LDS", "MODE_SWEEP", "MODE_GLOBAL",
     "JOB_DONE", "JOB_QUEUED", "JOB_RUNNING", "SCHED_SHORTEST", "SCHED_ARRIVAL", "Trajectory",
     "cpu_histo", "histo_noalloc",

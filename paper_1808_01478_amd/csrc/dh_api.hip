@@ -190,7 +190,6 @@ double min_width_tri(double ax, double bx, double by, double cx, double cy, doub
   return std::min(wa, std::min(wb, wc));
 }
 
-// Canonical constants of a frame (binary64), plus their binary32 images.
 // The images of the 27-image search that can be nearer than a reduced
 // vector d, for each octant of d's fractional coordinates f = B^-1 d. An
 // image d + S (S = B n) is nearer iff g(f) = 2 (B f).S + |S|^2 < 0, linear in
@@ -203,17 +202,15 @@ double min_width_tri(double ax, double bx, double by, double cx, double cy, doub
 // kernel assigns a vector to an octant only when its computed fractional
 // coordinates lie within e/2 of the box, else to the full list, as it does
 // for octants with more than kOctCap images.
-void octant_images(FrameParams &fp) {
+// The uncapped image list of every octant (shift indices, ascending).
+void octant_lists(const FrameParams &fp, int (&list)[8][kShifts], int (&len)[8]) {
   const double B[3][3] = {{fp.ax, 0.0, 0.0}, {fp.bx, fp.by, 0.0}, {fp.cx, fp.cy, fp.cz}};
   const double size = std::fabs(fp.ax) + std::fabs(fp.bx) + std::fabs(fp.by) +
                       std::fabs(fp.cx) + std::fabs(fp.cy) + std::fabs(fp.cz);
   const double margin = std::ldexp(size * size, -30);
   const double e = kOctSlack;
-  fp.oct_full = 0;
-  int longest = 0;
   for (int o = 0; o < 8; ++o) {
-    int list[kShifts];
-    int len = 0;
+    len[o] = 0;
     for (int m = 0; m < kShifts; ++m) {
       if (m == kZeroShift) continue;
       const double *S = fp.shift64[m];
@@ -234,19 +231,30 @@ void octant_images(FrameParams &fp) {
         const double gv = 2.0 * dot + s2;
         gmin = v == 0 ? gv : std::min(gmin, gv);
       }
-      if (!(gmin > margin)) list[len++] = m;
+      if (!(gmin > margin)) list[o][len[o]++] = m;
     }
-    if (len > kOctCap) {
+  }
+}
+
+void octant_images(FrameParams &fp) {
+  int list[8][kShifts], len[8];
+  octant_lists(fp, list, len);
+  fp.oct_full = 0;
+  int longest = 0;
+  for (int o = 0; o < 8; ++o) {
+    int n = len[o];
+    if (n > kOctCap) {
       fp.oct_full |= static_cast<uint8_t>(1u << o);
-      len = 0;
+      n = 0;
     }
-    longest = std::max(longest, len);
+    longest = std::max(longest, n);
     for (int k = 0; k < kOctCap; ++k)
-      fp.oct_shift[o][k] = static_cast<uint8_t>(k < len ? list[k] : kZeroShift);
+      fp.oct_shift[o][k] = static_cast<uint8_t>(k < n ? list[o][k] : kZeroShift);
   }
   fp.oct_n = static_cast<uint8_t>((longest + 2) / 3 * 3);
 }
 
+// Canonical constants of a frame (binary64), plus their binary32 images.
 int frame_consts(int32_t box_type, const double *box, double r_max, int32_t n_bins,
                  FrameParams &fp) {
   std::memset(&fp, 0, sizeof fp);
@@ -1201,6 +1209,22 @@ int dh_check_args(const double *coords, const int64_t *offsets, int32_t n_specie
                   int32_t box_type, const double *box, double r_max, int32_t n_bins,
                   int32_t precision) {
   return check(coords, offsets, n_species, box_type, box, r_max, n_bins, precision);
+}
+
+int dh_search_images(const double *box, int32_t *lists, int32_t *counts, int32_t *full_mask) {
+  if (!box || !lists || !counts || !full_mask) return DH_EINVAL;
+  if (!box_ok(DH_BOX_TRICLINIC, box)) return DH_EINVAL;  // the rules of a histogram call
+  FrameParams fp;
+  frame_consts(DH_BOX_TRICLINIC, box, 1.0, 1, fp);
+  int list[8][kShifts], len[8];
+  octant_lists(fp, list, len);
+  for (int o = 0; o < 8; ++o) {
+    counts[o] = len[o];
+    for (int k = 0; k < kShifts - 1; ++k)
+      lists[o * (kShifts - 1) + k] = k < len[o] ? list[o][k] : kZeroShift;
+  }
+  *full_mask = fp.oct_full;
+  return DH_OK;
 }
 
 int dh_ctx_create(int32_t device, dh_ctx **out) {

@@ -69,6 +69,7 @@ SIGNATURES = {
     "dh_ctx_profile_read": ([_vp, ctypes.POINTER(_f64), ctypes.POINTER(_i64)], ctypes.c_int),
     "dh_ctx_searched_pairs": ([_vp, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
     "dh_ctx_searched_images": ([_vp, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+    "dh_search_images": ([_vp, _vp, _vp, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
 }
 
 
@@ -153,6 +154,17 @@ def check_args(coords, offsets, box_type: int, box, r_max: float, n_bins: int,
     b = _host_box(box)
     return int(LIB.dh_check_args(_np_ptr(c), _np_ptr(o), len(o) - 1, int(box_type), _np_ptr(b),
                                  float(r_max), int(n_bins), int(precision)))
+
+
+def search_images(box):
+    """dh_search_images: (lists int32 [8, 26], counts int32 [8], full_mask) of
+    the image search for a triclinic cell (host only)."""
+    b = _host_box(box)
+    lists = np.zeros((8, 26), np.int32)
+    counts = np.zeros(8, np.int32)
+    full = ctypes.c_int32()
+    _check(LIB.dh_search_images(_np_ptr(b), _np_ptr(lists), _np_ptr(counts), ctypes.byref(full)))
+    return lists, counts, int(full.value)
 
 
 def histo_noalloc(d_coords, offsets, box_type: int, box, r_max: float, n_bins: int,
