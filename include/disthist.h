@@ -189,8 +189,9 @@ int dh_histo_async(dh_ctx *ctx, dh_stream stream, const double *d_coords,
  * the library runs on until the process ends (frame constants, work list,
  * counters and the staged coordinates, 16 bytes per point in binary32 and 32
  * in binary64: about 1.4 million binary64 or 2.9 million binary32 points;
- * binary32 triclinic frames of at least 65,536 points are staged in spatial
- * order with 32 bytes per point and sort keys: about 1.0 million points).
+ * frames of at least 65,536 points staged in spatial order, triclinic ones
+ * and binary64 orthorhombic ones, take 32 bytes per point and sort keys:
+ * about 1.0 million points).
  * A frame that does not fit gets DH_EINVAL before anything is enqueued.
  * Calls share that array: calls that overlap on one device (several streams
  * or host threads) race and must be serialised by the caller. Failures

@@ -27,8 +27,8 @@ namespace {
 
 // Largest frame: staged coordinates take 16 bytes per point in binary32 and
 // 32 in binary64, so 48 MiB holds about 1.4 million binary64 points (2.9
-// million binary32) together with their work list; binary32 triclinic frames
-// staged in spatial order take 32 bytes per point plus 8 bytes of sort keys
+// million binary32) together with their work list; frames staged in spatial
+// order (see staged_kind) take 32 bytes per point plus 8 bytes of sort keys
 // per point rounded up to a power of two (about 1.0 million points).
 constexpr size_t kScratchBytes = size_t{48} << 20;
 constexpr int kMaxDevices = 64;
