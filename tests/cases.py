@@ -83,6 +83,14 @@ def parity_cases():
     xs = rng.uniform(-1.0, 2.0, size=(66_001, 3)) @ SKEW
     out.append(_frame(xs, [40_000, 1, 26_000], workloads.BOX_TRICLINIC, SKEW, 0.49 * w, 600,
                       "tric-unwrapped-66k-sorted"))
+    # no box, coordinates over 800 binary orders of magnitude: squared
+    # distances from zero and subnormals to overflow, so the short root's
+    # guard (tiny q, t near bin edges, t far out of range) runs in every wave
+    mant = rng.uniform(1.0, 2.0, size=(3000, 3)) * rng.choice([-1.0, 1.0], size=(3000, 3))
+    xw = np.ldexp(mant, rng.integers(-400, 400, size=(3000, 1)))
+    xw[rng.random(3000) < 0.02] = 0.0
+    out.append(_frame(xw, [1700, 1300], workloads.BOX_NONE, None, 1.0, 4096,
+                      "none-wide-magnitudes"))
     # binary64 orthorhombic frames of at least 65,536 points take the sorted
     # kernel with a diagonal cell matrix: unwrapped points (shifts beyond one
     # cell), three species with a one-point species, r_max beyond half the
