@@ -296,6 +296,8 @@ int frame_consts(int32_t box_type, const double *box, double r_max, int32_t n_bi
     const double B[6] = {fp.ax, fp.bx, fp.by, fp.cx, fp.cy, fp.cz};
     for (int c = 0; c < 6; ++c) fp.Bk[c] = static_cast<float>(B[c] * fp.s / kTwo32);
     for (int c = 0; c < 6; ++c) fp.cell32[c] = static_cast<float>(B[c]);
+    const double H[6] = {fp.h11, fp.h12, fp.h13, fp.h22, fp.h23, fp.h33};
+    for (int c = 0; c < 6; ++c) fp.hinv32[c] = static_cast<float>(H[c]);
     if (fp.ax > 0)
       for (int c = 0; c < 5; ++c) fp.Bn[c] = static_cast<float>(B[c + 1] / fp.ax);
     for (int q = 0; q < kShifts; ++q)

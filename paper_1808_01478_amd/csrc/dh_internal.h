@@ -122,9 +122,11 @@ struct FrameParams {
   // searched[0], the images evaluated for them to searched[1] (device,
   // 8-byte aligned) unless null
   unsigned long long *searched;
-  // spatially sorted binary32 frames: the cell rows (ax bx by cx cy cz) and
-  // s = n_bins / r_max, rounded to binary32
+  // spatially sorted binary32 frames: the cell rows (ax bx by cx cy cz), the
+  // entries of B^-1 (h11 h12 h13 h22 h23 h33) and s = n_bins / r_max,
+  // rounded to binary32
   float cell32[6];
+  float hinv32[6];
   float s32;
   // image search: for each octant of a reduced vector's fractional
   // coordinates (bit k set when component k is negative) the images that

@@ -841,10 +841,13 @@ __device__ __forceinline__ void flush_hist(uint32_t *hist, const PairKernelArgs 
 // shift n is the Eq. 5 wrap of all their pairs (group_shift on each axis).
 // If it is, the pairs take the short path: the Cartesian difference to the
 // i-point shifted by B n, with no conversion and no cell matrix per pair
-// (3 subtractions, q, root, bin). Otherwise they take the fixed-point path
-// of unsorted triclinic frames. The choice depends only on the two groups
-// (species-aligned blocks of 64 points), not on the launch shape, so every
-// launch shape, batch and server path gives the same counts.
+// (3 subtractions, q, root, bin). If exactly one axis is ambiguous, the
+// pairs take the short path with the shift of that axis's lower end and
+// wrap that axis per pair (its fractional coordinate rounded, one to three
+// fma). Otherwise they take the fixed-point path of unsorted triclinic
+// frames. The choice depends only on the two groups (species-aligned blocks
+// of 64 points), not on the launch shape, so every launch shape, batch and
+// server path gives the same counts.
 template <int R, int MODE, bool DIAG, bool CLAMP, typename CountT>
 __device__ __forceinline__ void sorted_tile(
     const float4 *__restrict__ tb, const uint32_t *__restrict__ boxes, int jt, int js,
@@ -858,6 +861,8 @@ __device__ __forceinline__ void sorted_tile(
   const float ax = uni(F->cell32[0]), bx = uni(F->cell32[1]), by = uni(F->cell32[2]);
   const float cx = uni(F->cell32[3]), cy = uni(F->cell32[4]), cz = uni(F->cell32[5]);
   const float s32 = uni(F->s32);
+  const float h11 = uni(F->hinv32[0]), h12 = uni(F->hinv32[1]), h13 = uni(F->hinv32[2]);
+  const float h22 = uni(F->hinv32[3]), h23 = uni(F->hinv32[4]), h33 = uni(F->hinv32[5]);
   constexpr uint32_t kAll = (1u << R) - 1u;
   for (int g0 = js & ~63; g0 < jcount; g0 += 64) {
     const int j_begin = max(js, g0), j_end = min(jcount, g0 + 64);
@@ -865,18 +870,31 @@ __device__ __forceinline__ void sorted_tile(
     uint32_t jb[6];
 #pragma unroll
     for (int q = 0; q < 6; ++q) jb[q] = static_cast<uint32_t>(uni(static_cast<int>(gb[q])));
-    uint32_t fast = 0;
+    // per slice: bit r of `fast` when all three shifts are shared, of `fix`
+    // when exactly one axis is ambiguous (`amb`: those axes, over the
+    // slices); both get the i-point shifted by the shifts of the group's
+    // lower ends
+    uint32_t fast = 0, fix = 0, amb = 0, ambr[R];
     float sx[R], sy[R], sz[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      int na = 0, nb = 0, nc = 0;
-      const bool f = group_shift(ibox[r][0], ibox[r][3], jb[0], jb[3], na) &&
-                     group_shift(ibox[r][1], ibox[r][4], jb[1], jb[4], nb) &&
-                     group_shift(ibox[r][2], ibox[r][5], jb[2], jb[5], nc);
-      if (f) {
-        fast |= 1u << r;
-        const float fa = static_cast<float>(na), fb = static_cast<float>(nb),
-                    fc = static_cast<float>(nc);
+      int n[3] = {0, 0, 0};
+      uint32_t a_r = 0;
+      // an empty slice (all lanes past the end) counts nothing: shift 0
+      if (ibox[r][0] <= ibox[r][3]) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          if (!group_shift(ibox[r][k], ibox[r][3 + k], jb[k], jb[3 + k], n[k])) a_r |= 1u << k;
+      }
+      ambr[r] = static_cast<uint32_t>(uni(static_cast<int>(a_r)));
+      if ((a_r & (a_r - 1u)) == 0u) {
+        if (a_r == 0u)
+          fast |= 1u << r;
+        else
+          fix |= 1u << r;
+        amb |= a_r;
+        const float fa = static_cast<float>(n[0]), fb = static_cast<float>(n[1]),
+                    fc = static_cast<float>(n[2]);
         sx[r] = cxi[r] + (fa * ax + fb * bx + fc * cx);
         sy[r] = cyi[r] + (fb * by + fc * cy);
         sz[r] = czi[r] + fc * cz;
@@ -884,6 +902,9 @@ __device__ __forceinline__ void sorted_tile(
         sx[r] = sy[r] = sz[r] = 0.f;
       }
     }
+    fast = static_cast<uint32_t>(uni(static_cast<int>(fast)));
+    fix = static_cast<uint32_t>(uni(static_cast<int>(fix)));
+    amb = static_cast<uint32_t>(uni(static_cast<int>(amb)));
     auto mask = [&](int r, int j, uint32_t &l, uint32_t &lb) {
       l = lo[r];
       lb = lob[r];
@@ -897,6 +918,30 @@ __device__ __forceinline__ void sorted_tile(
       uint32_t l, lb;
       mask(r, j, l, lb);
       const float dx = C.x - sx[r], dy = C.y - sy[r], dz = C.z - sz[r];
+      const float q = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+      count_t(__float_as_uint(fmaf(__builtin_amdgcn_sqrtf(q), s32, kMagic32)), l, lb);
+    };
+    // the short path with the ambiguous axis K wrapped per pair: its
+    // fractional coordinate (a row of B^-1) rounded to the nearest integer m,
+    // then B_K m subtracted (m = 0 for a slice whose shift K is shared)
+    auto fix_pair = [&](auto axis_c, int r, const float4 &C, int j) {
+      constexpr int K = decltype(axis_c)::value;
+      uint32_t l, lb;
+      mask(r, j, l, lb);
+      float dx = C.x - sx[r], dy = C.y - sy[r], dz = C.z - sz[r];
+      if constexpr (K == 0) {
+        const float m = rintf(fmaf(dz, h13, fmaf(dy, h12, dx * h11)));
+        dx = fmaf(-ax, m, dx);
+      } else if constexpr (K == 1) {
+        const float m = rintf(fmaf(dz, h23, dy * h22));
+        dy = fmaf(-by, m, dy);
+        dx = fmaf(-bx, m, dx);
+      } else {
+        const float m = rintf(dz * h33);
+        dz = fmaf(-cz, m, dz);
+        dy = fmaf(-cy, m, dy);
+        dx = fmaf(-cx, m, dx);
+      }
       const float q = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
       count_t(__float_as_uint(fmaf(__builtin_amdgcn_sqrtf(q), s32, kMagic32)), l, lb);
     };
@@ -935,12 +980,24 @@ __device__ __forceinline__ void sorted_tile(
       ab = (static_cast<uint64_t>(__float_as_uint(e.y)) << 32) | __float_as_uint(e.x);
       cc = (static_cast<uint64_t>(__float_as_uint(e.w)) << 32) | __float_as_uint(e.z);
     };
+    auto fix_all = [&](auto axis_c) {
+      run_j([&](const float4 &C, int j) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) fix_pair(axis_c, r, C, j);
+      }, 1);
+    };
     if (fast == kAll) {
       run_j([&](const float4 &C, int j) {
 #pragma unroll
         for (int r = 0; r < R; ++r) fast_pair(r, C, j);
       }, 1);
-    } else if (fast == 0) {
+    } else if ((fast | fix) == kAll && amb == 1u) {
+      fix_all(std::integral_constant<int, 0>{});
+    } else if ((fast | fix) == kAll && amb == 2u) {
+      fix_all(std::integral_constant<int, 1>{});
+    } else if ((fast | fix) == kAll && amb == 4u) {
+      fix_all(std::integral_constant<int, 2>{});
+    } else if ((fast | fix) == 0) {
       run_j([&](const float4 &A, int j) {
         uint64_t ab, cc;
         words(A, ab, cc);
@@ -948,10 +1005,26 @@ __device__ __forceinline__ void sorted_tile(
         for (int r = 0; r < R; ++r) slow_pair(r, ab, cc, j);
       }, 0);
     } else {
+      // slices of different kinds: one pass per slice, each slice the path
+      // its own ambiguity gives it (so the counts do not depend on which
+      // slices share a wave)
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if (fast & (1u << r)) {
           run_j([&](const float4 &C, int j) { fast_pair(r, C, j); }, 1);
+        } else if (fix & (1u << r)) {
+          if (ambr[r] == 1u)
+            run_j([&](const float4 &C, int j) {
+              fix_pair(std::integral_constant<int, 0>{}, r, C, j);
+            }, 1);
+          else if (ambr[r] == 2u)
+            run_j([&](const float4 &C, int j) {
+              fix_pair(std::integral_constant<int, 1>{}, r, C, j);
+            }, 1);
+          else
+            run_j([&](const float4 &C, int j) {
+              fix_pair(std::integral_constant<int, 2>{}, r, C, j);
+            }, 1);
         } else {
           run_j([&](const float4 &A, int j) {
             uint64_t ab, cc;
