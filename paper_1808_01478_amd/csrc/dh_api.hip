@@ -251,7 +251,7 @@ void octant_images(FrameParams &fp) {
     for (int k = 0; k < kOctCap; ++k)
       fp.oct_shift[o][k] = static_cast<uint8_t>(k < n ? list[o][k] : kZeroShift);
   }
-  fp.oct_n = static_cast<uint8_t>((longest + 2) / 3 * 3);
+  fp.oct_n = static_cast<uint8_t>(longest);
 }
 
 // Canonical constants of a frame (binary64), plus their binary32 images.

@@ -133,7 +133,7 @@ struct FrameParams {
   // can be nearer than the vector itself, as indices into the shift tables
   // padded with the zero shift (kZeroShift); oct_full bit o when octant o
   // needs more than kOctCap images (it searches all 27); oct_n the longest
-  // of the other lists, rounded up to a multiple of 3
+  // of the other lists
   uint8_t oct_shift[8][kOctCap];
   uint8_t oct_full;
   uint8_t oct_n;

@@ -474,9 +474,10 @@ __device__ __forceinline__ float min_arith(float a, float b) {
 }
 
 // Minimum of q over the images in the search table from `base` (an octant
-// row, or the 27 shift vectors), n of them, three running minima. Rows are
-// padded with the zero shift, and a run past a row's end reads further
-// table entries, which are images too, so the minimum is unchanged; images
+// row, or the 27 shift vectors), n of them (uniform), three running minima.
+// Rows are padded with the zero shift, and a run past a row's end reads
+// further table entries, which are images too, so the minimum is unchanged;
+// images
 // left out of an octant row cannot be nearer (see octant_images on the
 // host), so it equals the one over all 27 images.
 template <typename T>
@@ -484,20 +485,21 @@ __device__ __forceinline__ T search_oct(T dx, T dy, T dz, T q, int base, int n,
                                         const typename V4<T>::type *__restrict__ tab) {
   T qa = q, qb = q, qc = q;
   const typename V4<T>::type *row = tab + base;
-  for (int k = 0; k < n; k += 3) {
-    T v[3];
-#pragma unroll
-    for (int u = 0; u < 3; ++u) {
-      const typename V4<T>::type S = row[k + u];
-      const T vx = dx + S.x;
-      const T vy = dy + S.y;
-      const T vz = dz + S.z;
-      v[u] = fmaT(vz, vz, fmaT(vy, vy, vx * vx));
-    }
-    qa = min_arith(qa, v[0]);
-    qb = min_arith(qb, v[1]);
-    qc = min_arith(qc, v[2]);
+  auto image = [&](int k) {
+    const typename V4<T>::type S = row[k];
+    const T vx = dx + S.x;
+    const T vy = dy + S.y;
+    const T vz = dz + S.z;
+    return fmaT(vz, vz, fmaT(vy, vy, vx * vx));
+  };
+  int k = 0;
+  for (; k + 2 < n; k += 3) {
+    const T v0 = image(k), v1 = image(k + 1), v2 = image(k + 2);
+    qa = min_arith(qa, v0);
+    qb = min_arith(qb, v1);
+    qc = min_arith(qc, v2);
   }
+  for (; k < n; ++k) qa = min_arith(qa, image(k));
   return min_arith(qa, min_arith(qb, qc));
 }
 
