@@ -138,14 +138,20 @@ __device__ __forceinline__ double sqrt_cr(double q) {
 // lies within 2^13 ulps of the canonical t (correctly rounded root times s).
 // It decides the bin whenever it is farther than 2^16 ulps from every
 // integer. The lanes where that is not certain are added to the wave mask
-// `near`: t within 2^16 ulps of an integer, and q below 2^-767, zero or NaN.
-// For t < 2^20 the integers are multiples of 2^32 ulps of t, so t is that
-// far from every integer when the low 32 bits of its encoding are at least
-// 2^16 away from a multiple of 2^32 (a conservative test: two integer
-// operations). Every t at or above 2^20 is out of range, as is the canonical
-// t, when n_bins < 2^20 - 2; with more bins the callers take the correctly
-// rounded root for every pair. A NaN t (q = +inf) counts out of range like
-// the canonical +inf.
+// `near`: t within 2^16 ulps of an integer. For t < 2^20 the integers are
+// multiples of 2^32 ulps of t, so t is that far from every integer when the
+// low 32 bits of its encoding are at least 2^16 away from a multiple of 2^32
+// (a conservative test: two integer operations). Every t at or above 2^20 is
+// out of range, as is the canonical t, when n_bins < 2^20 - 2; with more
+// bins the callers take the correctly rounded root for every pair. The
+// bound holds for every normal q (all intermediates stay normal). q = 0
+// gives t = 0 * inf = NaN, whose encoding ends in 32 zero bits, so the test
+// flags it; so it does for a subnormal q if v_rsq_f64 flushed it (q * inf,
+// then inf - inf). Otherwise, for subnormal q the canonical t is below
+// 2^-511 s, under 2^-11 when s < 2^500 (the callers take the correctly
+// rounded root for every pair beyond that), and the short root, within a
+// few ulps of it, falls in bin 0 as well. A NaN t (q = +inf or NaN) counts
+// out of range like the canonical one.
 __device__ __forceinline__ double t_fast64(double q, double s, uint64_t &near) {
   const double y = __builtin_amdgcn_rsq(q);
   double g = q * y;
@@ -154,14 +160,13 @@ __device__ __forceinline__ double t_fast64(double q, double s, uint64_t &near) {
   g = fma(g, e, g);
   const double t = g * s;
   const uint32_t lo = static_cast<uint32_t>(__double_as_longlong(t)) + 0x10000u;
-  near |= __builtin_amdgcn_ballot_w64(!(q >= 0x1p-767));
   near |= __builtin_amdgcn_ballot_w64(lo < 0x20000u);
   return t;
 }
 
 // t with the canonical arithmetic for one pair: the short root, or, when any
 // lane of the wave needs it, the correctly rounded one (a uniform branch).
-// big_bins: n_bins >= 2^20 - 2 (always the correctly rounded root).
+// big_bins: always the correctly rounded root (see run_item).
 __device__ __forceinline__ double t_guarded64(double q, double s, bool big_bins) {
   uint64_t near = big_bins ? ~0ull : 0ull;
   const double t = t_fast64(q, s, near);
@@ -1366,9 +1371,11 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
       nzz[k] = 0ull;
   }
   const int n_bins = uni(F->n_bins);
-  // binary64: t at or above 2^20 can lie near a bin edge only with this many
-  // bins (see t_fast64)
-  [[maybe_unused]] const bool big_bins = n_bins >= (1 << 20) - 2;
+  // binary64: the correctly rounded root for every pair when t at or above
+  // 2^20 can lie near a bin edge (this many bins) or the scale s is so large
+  // that a subnormal q could reach bin 1 (see t_fast64)
+  [[maybe_unused]] const bool big_bins =
+      n_bins >= (1 << 20) - 2 || !(uni(F->s) < 0x1p500);
   // the output is global memory: say so, so the atomics are global_atomic_*
   // (a generic pointer would give flat atomics, which also count as LDS
   // operations in lgkmcnt)
