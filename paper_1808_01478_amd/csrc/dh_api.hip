@@ -298,6 +298,15 @@ int frame_consts(int32_t box_type, const double *box, double r_max, int32_t n_bi
     for (int c = 0; c < 6; ++c) fp.cell32[c] = static_cast<float>(B[c]);
     const double H[6] = {fp.h11, fp.h12, fp.h13, fp.h22, fp.h23, fp.h33};
     for (int c = 0; c < 6; ++c) fp.hinv32[c] = static_cast<float>(H[c]);
+    for (int q = 0; q < 64; ++q) {
+      float f[3];
+      for (int k = 0; k < 3; ++k) f[k] = static_cast<float>((q >> k & 1) - (q >> (3 + k) & 1));
+      const float *b = fp.cell32;
+      fp.gshift32[q][0] = (f[0] * b[0] + f[1] * b[1]) + f[2] * b[3];
+      fp.gshift32[q][1] = f[1] * b[2] + f[2] * b[4];
+      fp.gshift32[q][2] = f[2] * b[5];
+      fp.gshift32[q][3] = 0.f;
+    }
     if (fp.ax > 0)
       for (int c = 0; c < 5; ++c) fp.Bn[c] = static_cast<float>(B[c + 1] / fp.ax);
     for (int q = 0; q < kShifts; ++q)

@@ -128,6 +128,10 @@ struct FrameParams {
   float cell32[6];
   float hinv32[6];
   float s32;
+  // spatially sorted binary32 frames: the lattice shift B n for the wraps
+  // n_k = +1 (bit k of q), -1 (bit 3 + k) or 0, in binary32 as
+  // (n_a a_x + n_b b_x) + n_c c_x, n_b b_y + n_c c_y, n_c c_z (w unused)
+  alignas(16) float gshift32[64][4];
   // image search: for each octant of a reduced vector's fractional
   // coordinates (bit k set when component k is negative) the images that
   // can be nearer than the vector itself, as indices into the shift tables

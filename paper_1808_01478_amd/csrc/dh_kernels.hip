@@ -337,22 +337,6 @@ __device__ __forceinline__ double wave_max_f64(double v) {
   return uni(v);
 }
 
-// Lattice shift n (in cell vectors, one axis) shared by every pair of a
-// group of i-points with fixed-point fractions in [ilo, ihi] and a group of
-// j-points in [jlo, jhi]: the Eq. 5 wrap of u_j - u_i is the n with
-// u_j - u_i - n 2^32 in [-2^31, 2^31), i.e. floor((u_j - u_i + 2^31) / 2^32),
-// the same for the whole interval [jlo - ihi, jhi - ilo] iff both ends give
-// the same n. Returns false when they differ (or a group is empty).
-__device__ __forceinline__ bool group_shift(uint32_t ilo, uint32_t ihi, uint32_t jlo,
-                                            uint32_t jhi, int &n) {
-  if (ilo > ihi || jlo > jhi) return false;
-  const int64_t dlo = static_cast<int64_t>(jlo) - static_cast<int64_t>(ihi) + (int64_t{1} << 31);
-  const int64_t dhi = static_cast<int64_t>(jhi) - static_cast<int64_t>(ilo) + (int64_t{1} << 31);
-  const int64_t nlo = dlo >> 32, nhi = dhi >> 32;  // arithmetic shifts: floor
-  n = static_cast<int>(nlo);
-  return nlo == nhi;
-}
-
 // Triclinic reduced vector (t units) from packed fractional words.
 __device__ __forceinline__ void tric_vec32(uint64_t ab_j, uint64_t neg_ab_i, float zi, float zj,
                                            const Geo32 &g, float &dx, float &dy, float &dz) {
@@ -844,121 +828,168 @@ __device__ __forceinline__ void flush_hist(uint32_t *hist, const PairKernelArgs 
 
 // One j-tile of a spatially sorted frame for one wave. For every group of 64
 // j-points of the tile and every slice r of the wave's i-points, the two
-// groups' bounding boxes (fixed-point fractions) decide whether one lattice
-// shift n is the Eq. 5 wrap of all their pairs (group_shift on each axis).
-// If it is, the pairs take the short path: the Cartesian difference to the
-// i-point shifted by B n, with no conversion and no cell matrix per pair
-// (3 subtractions, q, root, bin). If exactly one axis is ambiguous, the
-// pairs take the short path with the shift of that axis's lower end and
-// wrap that axis per pair (its fractional coordinate rounded, one to three
-// fma). Otherwise they take the fixed-point path of unsorted triclinic
-// frames. The choice depends only on the two groups (species-aligned blocks
-// of 64 points), not on the launch shape, so every launch shape, batch and
-// server path gives the same counts.
+// groups' bounding boxes (fixed-point fractions) decide, axis by axis,
+// whether one lattice shift n is the Eq. 5 wrap of all their pairs: the wrap
+// of u_j - u_i is the n with u_j - u_i - n 2^32 in [-2^31, 2^31), i.e.
+// floor((u_j - u_i + 2^31) / 2^32), in {-1, 0, 1}, and it is shared iff both
+// ends of [jlo - ihi, jhi - ilo] give the same n. Lane 3r + k of the wave
+// tests axis k of slice r, so one pass of a few instructions and four ballots
+// classify all R slices. If every axis is shared, the pairs take the short
+// path: the Cartesian difference to the i-point shifted by B n (a table
+// entry), with no conversion and no cell matrix per pair (3 subtractions, q,
+// root, bin). If exactly one axis K is ambiguous and its two ends differ by
+// one, the pairs take the short path with the shift of K's lower end, or
+// with one more cell vector B_K when the pair's fractional coordinate along
+// K (row K of B^-1 applied to the difference) exceeds 1/2: a compare of the
+// j-point's projection with a threshold of the slice and a select of the
+// shifted i-point. Otherwise they take the fixed-point path of unsorted
+// triclinic frames. The path and the arithmetic of a pair depend only on its
+// two groups (species-aligned blocks of 64 points), not on the launch shape
+// or on the other slices of the wave, so every launch shape, batch and server
+// path gives the same counts.
 template <int R, int MODE, bool DIAG, bool CLAMP, typename CountT>
 __device__ __forceinline__ void sorted_tile(
     const float4 *__restrict__ tb, const uint32_t *__restrict__ boxes, int jt, int js,
-    int jcount, int wbase, int lane, const FrameParams *F, const Geo32 &g, const float (&xi)[R],
-    const float (&zi)[R], const float (&cxi)[R], const float (&cyi)[R], const float (&czi)[R],
-    const uint32_t (&ibox)[R][6], const uint64_t (&nab)[R], const uint64_t (&nzz)[R / 2],
-    const uint32_t (&lo)[R], const uint32_t (&lob)[R], uint32_t hi, uint32_t hib,
-    CountT &count_t) {
-  (void)xi;
-  (void)zi;
+    int jcount, int wbase, int lane, const FrameParams *F, const Geo32 &g,
+    const float4 *__restrict__ X, int i0, int i1, const float (&cxi)[R], const float (&cyi)[R],
+    const float (&czi)[R], uint32_t ib_lo, uint32_t ib_hi, uint32_t ib_empty, uint32_t hi,
+    uint32_t hib, CountT &count_t) {
   const float ax = uni(F->cell32[0]), bx = uni(F->cell32[1]), by = uni(F->cell32[2]);
   const float cx = uni(F->cell32[3]), cy = uni(F->cell32[4]), cz = uni(F->cell32[5]);
   const float s32 = uni(F->s32);
   const float h11 = uni(F->hinv32[0]), h12 = uni(F->hinv32[1]), h13 = uni(F->hinv32[2]);
   const float h22 = uni(F->hinv32[3]), h23 = uni(F->hinv32[4]), h33 = uni(F->hinv32[5]);
+  // the lattice shifts B n, read through the scalar cache with a uniform index
+  using ConstF = const __attribute__((address_space(4))) float;
+  const ConstF *gshift = (const ConstF *)(&F->gshift32[0][0]);
   constexpr uint32_t kAll = (1u << R) - 1u;
+  // this lane's axis of the group boxes (lanes 3R and up repeat axis 0)
+  const int bk = lane < 3 * R ? lane % 3 : 0;
+  const uint32_t keep = ~ib_empty;
   for (int g0 = js & ~63; g0 < jcount; g0 += 64) {
     const int j_begin = max(js, g0), j_end = min(jcount, g0 + 64);
     const uint32_t *gb = boxes + (g0 >> 6) * 8;
-    uint32_t jb[6];
-#pragma unroll
-    for (int q = 0; q < 6; ++q) jb[q] = static_cast<uint32_t>(uni(static_cast<int>(gb[q])));
+    const uint32_t jl = gb[bk], jh = gb[3 + bk];
+    // wrap of the lower and upper end of this lane's interval
+    const int nl = static_cast<int>(jl - ib_hi >= 0x80000000u) - static_cast<int>(jl < ib_hi);
+    const int nh = static_cast<int>(jh - ib_lo >= 0x80000000u) - static_cast<int>(jh < ib_lo);
+    // bit 3r + k: axis k of slice r is ambiguous, spans more than two wraps,
+    // has lower-end wrap +1, -1 (an empty slice counts nothing: shift 0)
+    const uint32_t m_amb = static_cast<uint32_t>(__builtin_amdgcn_ballot_w64(nl != nh)) & keep;
+    const uint32_t m_wide = static_cast<uint32_t>(__builtin_amdgcn_ballot_w64(nh - nl > 1)) & keep;
+    const uint32_t m_pos = static_cast<uint32_t>(__builtin_amdgcn_ballot_w64(nl > 0)) & keep;
+    const uint32_t m_neg = static_cast<uint32_t>(__builtin_amdgcn_ballot_w64(nl < 0)) & keep;
     // per slice: bit r of `fast` when all three shifts are shared, of `fix`
-    // when exactly one axis is ambiguous (`amb`: those axes, over the
-    // slices); both get the i-point shifted by the shifts of the group's
-    // lower ends
+    // when exactly one axis is ambiguous by one wrap (`amb`: those axes, over
+    // the slices); both get the i-point shifted by the wraps of the lower ends
     uint32_t fast = 0, fix = 0, amb = 0, ambr[R];
     float sx[R], sy[R], sz[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      int n[3] = {0, 0, 0};
-      uint32_t a_r = 0;
-      // an empty slice (all lanes past the end) counts nothing: shift 0
-      if (ibox[r][0] <= ibox[r][3]) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-          if (!group_shift(ibox[r][k], ibox[r][3 + k], jb[k], jb[3 + k], n[k])) a_r |= 1u << k;
-      }
-      ambr[r] = static_cast<uint32_t>(uni(static_cast<int>(a_r)));
-      if ((a_r & (a_r - 1u)) == 0u) {
+      const uint32_t a_r = (m_amb >> (3 * r)) & 7u;
+      ambr[r] = a_r;
+      if ((a_r & (a_r - 1u)) == 0u && ((m_wide >> (3 * r)) & 7u) == 0u) {
         if (a_r == 0u)
           fast |= 1u << r;
         else
           fix |= 1u << r;
         amb |= a_r;
-        const float fa = static_cast<float>(n[0]), fb = static_cast<float>(n[1]),
-                    fc = static_cast<float>(n[2]);
-        sx[r] = cxi[r] + (fa * ax + fb * bx + fc * cx);
-        sy[r] = cyi[r] + (fb * by + fc * cy);
-        sz[r] = czi[r] + fc * cz;
+        const uint32_t q = ((m_pos >> (3 * r)) & 7u) | (((m_neg >> (3 * r)) & 7u) << 3);
+        const ConstF *S = gshift + 4 * q;
+        sx[r] = cxi[r] + S[0];
+        sy[r] = cyi[r] + S[1];
+        sz[r] = czi[r] + S[2];
       } else {
         sx[r] = sy[r] = sz[r] = 0.f;
       }
     }
-    fast = static_cast<uint32_t>(uni(static_cast<int>(fast)));
-    fix = static_cast<uint32_t>(uni(static_cast<int>(fix)));
-    amb = static_cast<uint32_t>(uni(static_cast<int>(amb)));
-    auto mask = [&](int r, int j, uint32_t &l, uint32_t &lb) {
-      l = lo[r];
-      lb = lob[r];
+    // Clamp bounds of a pair (see count_t): l = 0 and lb = the guard word
+    // below bin 0 for a pair that counts, the lane's discard slot for the
+    // lower triangle of a diagonal item. The short paths need nothing else:
+    // a lane past the end of the item holds an i-point at infinity, whose q
+    // is +inf, which the upper clamp discards. The fixed-point path passes
+    // the lane's own bounds (l0, lb0).
+    auto mask = [&](int r, int j, uint32_t &l, uint32_t &lb, uint32_t l0 = 0u,
+                    uint32_t lb0 = kMagicBits - 1u) {
+      l = l0;
+      lb = lb0;
       if constexpr (DIAG) {
         const bool up = jt + j > wbase + r * 64 + lane;
         l = up ? l : hi;
         lb = up ? lb : hib;
       }
     };
+    auto bin = [&](int r, int j, float dx, float dy, float dz) {
+      uint32_t l, lb;
+      mask(r, j, l, lb);
+      const float q = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+      count_t(__float_as_uint(fmaf(__builtin_amdgcn_sqrtf(q), s32, kMagic32)), l, lb);
+    };
     auto fast_pair = [&](int r, const float4 &C, int j) {
-      uint32_t l, lb;
-      mask(r, j, l, lb);
-      const float dx = C.x - sx[r], dy = C.y - sy[r], dz = C.z - sz[r];
-      const float q = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-      count_t(__float_as_uint(fmaf(__builtin_amdgcn_sqrtf(q), s32, kMagic32)), l, lb);
+      bin(r, j, C.x - sx[r], C.y - sy[r], C.z - sz[r]);
     };
-    // the short path with the ambiguous axis K wrapped per pair: its
-    // fractional coordinate (a row of B^-1) rounded to the nearest integer m,
-    // then B_K m subtracted (m = 0 for a slice whose shift K is shared)
-    auto fix_pair = [&](auto axis_c, int r, const float4 &C, int j) {
+    // row K of B^-1 applied to a point: its fractional coordinate along K
+    // (up to the constant of the cell centre)
+    auto proj = [&](auto axis_c, float x, float y, float z) {
       constexpr int K = decltype(axis_c)::value;
-      uint32_t l, lb;
-      mask(r, j, l, lb);
-      float dx = C.x - sx[r], dy = C.y - sy[r], dz = C.z - sz[r];
-      if constexpr (K == 0) {
-        const float m = rintf(fmaf(dz, h13, fmaf(dy, h12, dx * h11)));
-        dx = fmaf(-ax, m, dx);
-      } else if constexpr (K == 1) {
-        const float m = rintf(fmaf(dz, h23, dy * h22));
-        dy = fmaf(-by, m, dy);
-        dx = fmaf(-bx, m, dx);
-      } else {
-        const float m = rintf(dz * h33);
-        dz = fmaf(-cz, m, dz);
-        dy = fmaf(-cy, m, dy);
-        dx = fmaf(-cx, m, dx);
-      }
-      const float q = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-      count_t(__float_as_uint(fmaf(__builtin_amdgcn_sqrtf(q), s32, kMagic32)), l, lb);
+      if constexpr (K == 0)
+        return fmaf(z, h13, fmaf(y, h12, x * h11));
+      else if constexpr (K == 1)
+        return fmaf(z, h23, y * h22);
+      else
+        return z * h33;
     };
-    auto slow_pair = [&](int r, uint64_t ab, uint64_t cc, int j) {
+    // One-axis wrap of slice r along K: the threshold the j-point's
+    // projection must exceed (1/2 above the shifted i-point's; +inf for a
+    // slice whose shift K is shared, which then takes exactly the short
+    // path) and the i-point shifted by one more cell vector B_K.
+    struct Wrap {
+      float th, x, y, z;
+    };
+    auto wrap_of = [&](auto axis_c, int r) {
+      constexpr int K = decltype(axis_c)::value;
+      Wrap w;
+      w.th = (fix >> r) & 1u ? proj(axis_c, sx[r], sy[r], sz[r]) + 0.5f : __builtin_inff();
+      w.x = sx[r] + (K == 0 ? ax : K == 1 ? bx : cx);
+      w.y = K == 0 ? sy[r] : sy[r] + (K == 1 ? by : cy);
+      w.z = K == 2 ? sz[r] + cz : sz[r];
+      return w;
+    };
+    auto fix_pair = [&](auto axis_c, int r, const Wrap &w, const float4 &C, float p, int j) {
+      constexpr int K = decltype(axis_c)::value;
+      const bool up = p > w.th;
+      const float ux = up ? w.x : sx[r];
+      const float uy = K >= 1 && up ? w.y : sy[r];
+      const float uz = K == 2 && up ? w.z : sz[r];
+      bin(r, j, C.x - ux, C.y - uy, C.z - uz);
+    };
+    // The fixed-point path (rare) reloads its i-words: -(b:a) of the
+    // i-point of slice r, -(c':c) of slices 2k and 2k+1 (one 64-bit addition
+    // to j's (c:c) gives both c differences, the second lowered by one unit
+    // when the first borrows), and the lane's clamp bounds.
+    struct SlowI {
+      uint64_t nab, nzz;
+      uint32_t l0, lb0;
+    };
+    auto slow_i = [&](int r) {
+      const int i = wbase + r * 64 + lane, ip = wbase + (r ^ 1) * 64 + lane;
+      const float4 P = X[2 * (i < i1 ? i : i0)];
+      const float4 Q = X[2 * (ip < i1 ? ip : i0)];
+      const float z0 = r % 2 == 0 ? P.z : Q.z, z1 = r % 2 == 0 ? Q.z : P.z;
+      SlowI v;
+      v.nab = 0ull - ((static_cast<uint64_t>(__float_as_uint(P.y)) << 32) | __float_as_uint(P.x));
+      v.nzz = 0ull - ((static_cast<uint64_t>(__float_as_uint(z1)) << 32) | __float_as_uint(z0));
+      v.l0 = i < i1 ? 0u : hi;
+      v.lb0 = i < i1 ? kMagicBits - 1u : hib;
+      return v;
+    };
+    auto slow_pair = [&](int r, const SlowI &v, uint64_t ab, uint64_t cc, int j) {
       uint32_t l, lb;
-      mask(r, j, l, lb);
-      const uint64_t dcc = cc + nzz[r / 2];
+      mask(r, j, l, lb, v.l0, v.lb0);
+      const uint64_t dcc = cc + v.nzz;
       const float fcd = static_cast<float>(
           static_cast<int32_t>(static_cast<uint32_t>(r % 2 == 0 ? dcc : dcc >> 32)));
-      count_t(bits32_packed_c<kBoxTric>(ab, nab[r], fcd, g), l, lb);
+      count_t(bits32_packed_c<kBoxTric>(ab, v.nab, fcd, g), l, lb);
     };
     // Every loop reads the next j before the current j's atomics: LDS
     // operations complete in order, so a read issued after the atomics would
@@ -988,9 +1019,19 @@ __device__ __forceinline__ void sorted_tile(
       cc = (static_cast<uint64_t>(__float_as_uint(e.w)) << 32) | __float_as_uint(e.z);
     };
     auto fix_all = [&](auto axis_c) {
-      run_j([&](const float4 &C, int j) {
+      Wrap w[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) fix_pair(axis_c, r, C, j);
+      for (int r = 0; r < R; ++r) w[r] = wrap_of(axis_c, r);
+      run_j([&](const float4 &C, int j) {
+        const float p = proj(axis_c, C.x, C.y, C.z);
+#pragma unroll
+        for (int r = 0; r < R; ++r) fix_pair(axis_c, r, w[r], C, p, j);
+      }, 1);
+    };
+    auto fix_one = [&](auto axis_c, int r) {
+      const Wrap w = wrap_of(axis_c, r);
+      run_j([&](const float4 &C, int j) {
+        fix_pair(axis_c, r, w, C, proj(axis_c, C.x, C.y, C.z), j);
       }, 1);
     };
     if (fast == kAll) {
@@ -1005,11 +1046,14 @@ __device__ __forceinline__ void sorted_tile(
     } else if ((fast | fix) == kAll && amb == 4u) {
       fix_all(std::integral_constant<int, 2>{});
     } else if ((fast | fix) == 0) {
+      SlowI v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = slow_i(r);
       run_j([&](const float4 &A, int j) {
         uint64_t ab, cc;
         words(A, ab, cc);
 #pragma unroll
-        for (int r = 0; r < R; ++r) slow_pair(r, ab, cc, j);
+        for (int r = 0; r < R; ++r) slow_pair(r, v[r], ab, cc, j);
       }, 0);
     } else {
       // slices of different kinds: one pass per slice, each slice the path
@@ -1021,22 +1065,17 @@ __device__ __forceinline__ void sorted_tile(
           run_j([&](const float4 &C, int j) { fast_pair(r, C, j); }, 1);
         } else if (fix & (1u << r)) {
           if (ambr[r] == 1u)
-            run_j([&](const float4 &C, int j) {
-              fix_pair(std::integral_constant<int, 0>{}, r, C, j);
-            }, 1);
+            fix_one(std::integral_constant<int, 0>{}, r);
           else if (ambr[r] == 2u)
-            run_j([&](const float4 &C, int j) {
-              fix_pair(std::integral_constant<int, 1>{}, r, C, j);
-            }, 1);
+            fix_one(std::integral_constant<int, 1>{}, r);
           else
-            run_j([&](const float4 &C, int j) {
-              fix_pair(std::integral_constant<int, 2>{}, r, C, j);
-            }, 1);
+            fix_one(std::integral_constant<int, 2>{}, r);
         } else {
+          const SlowI v = slow_i(r);
           run_j([&](const float4 &A, int j) {
             uint64_t ab, cc;
             words(A, ab, cc);
-            slow_pair(r, ab, cc, j);
+            slow_pair(r, v, ab, cc, j);
           }, 0);
         }
       }
@@ -1306,10 +1345,12 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
   const uint32_t hi = static_cast<uint32_t>(win + lane);  // discard slot of this lane
   uint32_t lo[R];
   // sorted frames: Cartesian i-positions, and the fixed-point bounding box of
-  // each 64-particle slice r of the wave (its valid lanes): lo a, b, c, hi a,
-  // b, c; an empty slice has lo > hi
+  // each 64-particle slice r of the wave (its valid lanes), one axis per
+  // lane: lane 3r + k holds the lower (ib_lo) and upper (ib_hi) bound along
+  // axis k; ib_empty has bits 3r, 3r + 1, 3r + 2 set for a slice without
+  // valid lanes
   [[maybe_unused]] float cxi[R], cyi[R], czi[R];
-  [[maybe_unused]] uint32_t ibox[R][6];
+  [[maybe_unused]] uint32_t ib_lo = 0, ib_hi = 0, ib_empty = 0;
   // binary64 sorted frames: boxes of the fractional coordinates B^-1 x
   // (slot 6: the largest |x| + |y| + |z| of the slice)
   [[maybe_unused]] double ibox64[R][7];
@@ -1331,13 +1372,22 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
       ibox64[r][6] = wave_max_f64(ok ? fabs(p.x) + fabs(p.y) + fabs(p.z) : 0.0);
     }
     if constexpr (SORTED && sizeof(T) == 4) {
+      // a lane past the end of the item: an i-point at infinity (every q of
+      // its short-path pairs is +inf and lands in its discard slot)
       const V c = X[EPJ * (ok ? i : w.i0) + 1];
-      cxi[r] = c.x; cyi[r] = c.y; czi[r] = c.z;
+      cxi[r] = ok ? c.x : __builtin_inff();
+      cyi[r] = ok ? c.y : __builtin_inff();
+      czi[r] = ok ? c.z : __builtin_inff();
       const uint32_t u[3] = {__float_as_uint(p.x), __float_as_uint(p.y), __float_as_uint(p.z)};
 #pragma unroll
       for (int ax = 0; ax < 3; ++ax) {
-        ibox[r][ax] = wave_min_u32(ok ? u[ax] : 0xFFFFFFFFu);
-        ibox[r][3 + ax] = wave_max_u32(ok ? u[ax] : 0u);
+        const uint32_t bl = wave_min_u32(ok ? u[ax] : 0xFFFFFFFFu);
+        const uint32_t bh = wave_max_u32(ok ? u[ax] : 0u);
+        if (lane == 3 * r + ax) {
+          ib_lo = bl;
+          ib_hi = bh;
+        }
+        if (ax == 0 && bl > bh) ib_empty |= 7u << (3 * r);
       }
     }
   }
@@ -1570,8 +1620,8 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
     if constexpr (SORTED && sizeof(T) == 4) {
       if (wave_active && js < jcount)
         sorted_tile<R, MODE, DIAG, CLAMP>(tile + buf * tj * EPJ, tboxes + buf * 32, jt, js,
-                                          jcount, wbase, lane, F, g, xi, zi, cxi, cyi, czi,
-                                          ibox, nab, nzz, lo, lob, hi, hib, count_t);
+                                          jcount, wbase, lane, F, g, X, w.i0, w.i1, cxi, cyi,
+                                          czi, ib_lo, ib_hi, ib_empty, hi, hib, count_t);
       continue;
     }
     if constexpr (SORTED && sizeof(T) == 8) {
