@@ -35,6 +35,11 @@ def mixed_frames():
         workloads.trajectory_frame(3).subset([3000] * 4),
         workloads.tiny(n=2048),
     ]
+    # a triclinic frame of at least 65,536 points: staged in spatial order,
+    # group-shift kernel
+    sorted_frame = workloads.triclinic(n=66_000)
+    sorted_frame.name = "tric-clustered-66k-sorted"
+    fr.append(sorted_frame)
     return fr
 
 

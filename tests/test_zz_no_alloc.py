@@ -14,6 +14,11 @@ pytestmark = pytest.mark.gpu
 SKEW = np.array([[10.0, 0, 0], [3.0, 9.5, 0], [-2.0, 3.5, 9.0]])
 
 
+def _named(frame, name):
+    frame.name = name
+    return frame
+
+
 def frames():
     w = workloads.min_width(SKEW)
     return [
@@ -27,6 +32,7 @@ def frames():
         workloads.random_frame(506, [1600, 900], workloads.BOX_ORTHO, n_bins=3_000_000),
         workloads.random_frame(507, [1], workloads.BOX_NONE, n_bins=16),
         workloads.tiny(n=3000),
+        _named(workloads.triclinic(n=66_000), "tric-clustered-66k-sorted"),
     ]
 
 
