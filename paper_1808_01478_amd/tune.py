@@ -26,7 +26,8 @@ def main(argv=None) -> int:
 
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_CACHE)
-    ap.add_argument("--workloads", default="ortho100k,tiny,triclinic1M,image_search")
+    ap.add_argument("--workloads",
+                    default="ortho100k,tiny,triclinic1M,image_search,trajectory")
     args = ap.parse_args(argv)
     makers = {"ortho100k": workloads.ortho, "tiny": workloads.tiny,
               "triclinic1M": workloads.triclinic, "image_search": workloads.image_search}
@@ -39,6 +40,18 @@ def main(argv=None) -> int:
     ctx.set_tuning(dh.TUNE_ON, fresh)
     dev = torch.device("cuda")
     for name in args.workloads.split(","):
+        if name == "trajectory":
+            # binary32 buckets of the 512-frame trajectory (log2 N 14-18,
+            # one to four species): the first frame of each bucket is tuned,
+            # the others find its entry
+            for fr in workloads.trajectory(512):
+                x = torch.from_numpy(fr.coords).to(dev)
+                out = torch.empty((fr.n_hist, fr.n_bins), dtype=torch.int64, device=dev)
+                ctx.histo_async(x, fr.offsets, fr.box_type, fr.box, fr.r_max, fr.n_bins,
+                                dh.FP32, out)
+            torch.cuda.synchronize()
+            print(f"trajectory precision={dh.FP32}: 512 frames", flush=True)
+            continue
         fr = makers[name]()
         x = torch.from_numpy(fr.coords).to(dev)
         out = torch.empty((fr.n_hist, fr.n_bins), dtype=torch.int64, device=dev)
