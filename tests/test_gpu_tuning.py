@@ -69,6 +69,31 @@ def test_all_shapes_identical(ctx, precision, fi):
     ctx.set_config(None)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_sorted_frame_every_mode(ctx, precision):
+    """The spatially sorted triclinic frame (ragged i-blocks, diagonal items,
+    lanes past the end of an item) in every accumulation mode: four LDS
+    copies leave room for a third of its 20,000 bins, so it runs as bin
+    windows; `wide` = 1 forces uint64 global atomics. Counts and out-of-range
+    counts equal the default single LDS histogram's."""
+    fr = FRAMES[4]
+    print(f"\n[case] sorted frame, all modes, prec={precision}", flush=True)
+    ctx.set_config(None)
+    ref, ref_oor = run_gpu(ctx, fr, precision)
+    assert ctx.last_config()["mode"] == 0
+    for knobs, mode in (([4, 4, 256, 1, 0, 8, 1024, 0], 1), ([8, 4, 128, 0, 0, 4, 512, 0], 1),
+                        ([8, 1, 256, 1, 0, 8, 256, 1], 2), ([4, 2, 128, 1, 1, 16, 256, 1], 2)):
+        ctx.set_config(knobs)
+        h, oor = run_gpu(ctx, fr, precision)
+        cfg = ctx.last_config()
+        assert cfg["mode"] == mode, (knobs, cfg)
+        if mode == 1:
+            assert cfg["sweeps"] >= 2, cfg
+        assert np.array_equal(h, ref), f"shape {knobs} changed the counts"
+        assert np.array_equal(oor, ref_oor)
+    ctx.set_config(None)
+
+
 def test_invalid_shape_rejected(ctx):
     import paper_1808_01478_amd as dh
     for bad in ([3, 1, 256, 1, 0, 8, 256, 3], [8, 3, 256, 1, 0, 8, 256, 3],
