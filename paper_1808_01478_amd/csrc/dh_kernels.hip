@@ -134,8 +134,10 @@ __device__ __forceinline__ double sqrt_cr(double q) {
 
 // The scaled distance t = sqrt(q) * s from a short root: v_rsq_f64 (relative
 // error at most 2^-23, the precision the ISA states for it) and one
-// Goldschmidt step give sqrt(q) within about 1.5 * 2^-46 relative, so this t
-// lies within 2^13 ulps of the canonical t (correctly rounded root times s).
+// Goldschmidt step, with s folded into the step's last fma (g s (1 + e)
+// instead of (g (1 + e)) s: one multiplication less), give t within about
+// 1.5 * 2^-46 relative plus three roundings, so it lies within 2^13 ulps of
+// the canonical t (correctly rounded root times s).
 // It decides the bin whenever it is farther than 2^16 ulps from every
 // integer. The lanes where that is not certain are added to the wave mask
 // `near`: t within 2^16 ulps of an integer. For t < 2^20 the integers are
@@ -154,11 +156,11 @@ __device__ __forceinline__ double sqrt_cr(double q) {
 // out of range like the canonical one.
 __device__ __forceinline__ double t_fast64(double q, double s, uint64_t &near) {
   const double y = __builtin_amdgcn_rsq(q);
-  double g = q * y;
+  const double g = q * y;
   const double h = 0.5 * y;
   const double e = fma(-h, g, 0.5);
-  g = fma(g, e, g);
-  const double t = g * s;
+  const double gs = g * s;
+  const double t = fma(gs, e, gs);
   const uint32_t lo = static_cast<uint32_t>(__double_as_longlong(t)) + 0x10000u;
   near |= __builtin_amdgcn_ballot_w64(lo < 0x20000u);
   return t;
@@ -1530,9 +1532,15 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
       if (idx >= cap) idx -= cap;
       const V e = wq[idx];
       T q = fmaT(e.z, e.z, fmaT(e.y, e.y, e.x * e.x));
-      // entry w: the vector's octant, 8 for the full list (exact in T); the
-      // wave runs the full list when any of its vectors needs it
-      const int code = static_cast<int>(e.w);
+      // the vector's octant (8: outside the octant boxes), 8 as well when its
+      // list is the full one; the wave runs the full list when any of its
+      // vectors needs it
+      int code;
+      if constexpr (sizeof(T) == 4)
+        code = __float_as_int(e.w);
+      else
+        code = octant64(e.x, e.y, e.z, g);
+      if ((oct_full >> code) & 1u) code = 8;
       const int n = __builtin_amdgcn_ballot_w64(code == 8) != 0 ? kShifts : oct_n;
       q = search_oct<T>(e.x, e.y, e.z, q, code == 8 ? 8 * kOctCap : code * kOctCap, n, sh);
       n_images += static_cast<uint64_t>(cnt) * static_cast<uint64_t>(n);
@@ -1703,15 +1711,16 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
               if (need) {
                 int pos = head + qn + below;  // < 2 cap: head < cap, qn + below < cap
                 if (pos >= cap) pos -= cap;
-                int code;
-                if constexpr (kPacked)
-                  code = octant32(pj.ab, nab[r], zi[r],
-                                  __uint_as_float(static_cast<uint32_t>(pj.cc)));
-                else
-                  code = octant64(dx, dy, dz, g);
-                if ((oct_full >> code) & 1u) code = 8;
+                // binary32: the octant from the exact signs of the
+                // fixed-point differences, as the bits of w; binary64 takes
+                // it in the drain from the vector itself
                 V e;
-                e.x = dx; e.y = dy; e.z = dz; e.w = static_cast<T>(code);
+                e.x = dx; e.y = dy; e.z = dz;
+                if constexpr (kPacked)
+                  e.w = __int_as_float(octant32(pj.ab, nab[r], zi[r],
+                                                __uint_as_float(static_cast<uint32_t>(pj.cc))));
+                else
+                  e.w = T(0);
                 wq[pos] = e;
               }
               qn += __builtin_popcountll(m);

@@ -9,10 +9,10 @@ the ISA states for it (2^-23) in both directions.
   iteration alone returns the wrong neighbour for half of them), on those
   nearest to squared midpoints, at powers of two, at the edge of the scaled
   range (2^-767) and on subnormals.
-* t_fast64 (seed + one Goldschmidt step) must stay within 2^13 ulps of the
-  canonical t, and whenever its guard (low 32 bits of t at least 2^16 from a
-  multiple of 2^32, t < 2^20) lets it through, its floor must equal the
-  canonical floor.
+* t_fast64 (seed + one Goldschmidt step, the scale folded into its last
+  fma) must stay within 2^13 ulps of the canonical t, and whenever its guard
+  (low 32 bits of t at least 2^16 from a multiple of 2^32, t < 2^20) lets it
+  through, its floor must equal the canonical floor.
 
 This checks the method the kernel implements; the GPU tests check the kernel
 itself against the oracle on the same arguments (tests/test_gpu_sqrt.py)."""
@@ -84,10 +84,10 @@ def t_fast(q, s, rel):
     g = mul(q, y)
     h = mul(0.5, y)
     e = fma(-h, g, 0.5)
-    g = fma(g, e, g)
-    t = mul(g, s)
+    gs = mul(g, s)
+    t = fma(gs, e, gs)
     lo = (bits(t) + 0x10000) & 0xFFFFFFFF
-    near = (not q >= 2.0 ** -767) or lo < 0x20000
+    near = lo < 0x20000
     return t, near
 
 
