@@ -1125,52 +1125,46 @@ template <int R, bool DIAG, typename CountT>
 __device__ __forceinline__ void sorted_tile64(
     const double4 *__restrict__ tb, const double *__restrict__ boxes, int jt, int js,
     int jcount, int wbase, int lane, const Geo64 &g, bool big_bins, const double (&xi)[R],
-    const double (&yi)[R], const double (&zi)[R], const double (&ibox)[R][7],
-    const uint32_t (&lo)[R], uint32_t hi, CountT &count_t) {
+    const double (&yi)[R], const double (&zi)[R], double ib_lo, double ib_hi, double ib_mag,
+    uint32_t ib_empty, const uint32_t (&lo)[R], uint32_t hi, CountT &count_t) {
   const double hmax = fmax(fmax(fabs(g.h11), fabs(g.h12)),
                            fmax(fmax(fabs(g.h13), fabs(g.h22)), fmax(fabs(g.h23), fabs(g.h33))));
+  // lane 3r + k tests axis k of slice r (lanes 3R and up repeat axis 0)
+  const int bk = lane < 3 * R ? lane % 3 : 0;
+  const uint32_t keep = ~ib_empty;
   for (int g0 = js & ~63; g0 < jcount; g0 += 64) {
     const int j_begin = max(js, g0), j_end = min(jcount, g0 + 64);
     const double *gb = boxes + (g0 >> 6) * 8;
-    double jb[7];
-#pragma unroll
-    for (int q = 0; q < 7; ++q) jb[q] = uni(gb[q]);
+    // this lane's axis: is the shift shared by all pairs of the two groups,
+    // and is its term -B_k n exact (|n| <= 1)? Four ballots give, per slice
+    // and axis, the rounded axes and the shared shifts +1 and -1 (an empty
+    // slice counts nothing: shift 0).
+    const double m = fma(hmax * (ib_mag + gb[6]), 0x1p-48, 0x1p-40);
+    double n;
+    const bool shared = group_shift64(ib_lo, ib_hi, gb[bk], gb[3 + bk], m, n);
+    const bool use = shared && fabs(n) <= 1.0;
+    const uint32_t m_amb = static_cast<uint32_t>(__builtin_amdgcn_ballot_w64(!use)) & keep;
+    const uint32_t m_pos =
+        static_cast<uint32_t>(__builtin_amdgcn_ballot_w64(use && n == 1.0)) & keep;
+    const uint32_t m_neg =
+        static_cast<uint32_t>(__builtin_amdgcn_ballot_w64(use && n == -1.0)) & keep;
     // amb: bit k when axis k (a, b, c) needs the rounding for some slice;
     // nz: bit k when some slice has a shared non-zero shift along axis k
     uint32_t amb = 0, nz = 0;
-    // exact terms, in the order of the canonical steps: x of a, b, c; y of
-    // b, c; z of c (zero where the axis takes the rounding). A shared shift
-    // is used only for |n| <= 1, where the terms -B_k n are exact.
-    double P[R][6];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      double n[3] = {0.0, 0.0, 0.0};
-      uint32_t amb_r = 0;
-      // an empty slice (all lanes past the end: lo > hi) counts nothing
-      if (ibox[r][0] <= ibox[r][3]) {
-        const double m = fma(hmax * (ibox[r][6] + jb[6]), 0x1p-48, 0x1p-40);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const bool shared = group_shift64(ibox[r][k], ibox[r][3 + k], jb[k], jb[3 + k], m, n[k]);
-          if (!(shared && fabs(n[k]) <= 1.0)) {
-            amb_r |= 1u << k;
-            n[k] = 0.0;
-          }
-        }
-      }
-      P[r][0] = uni(-g.ax * n[0]);
-      P[r][1] = uni(-g.bx * n[1]);
-      P[r][2] = uni(-g.cx * n[2]);
-      P[r][3] = uni(-g.by * n[1]);
-      P[r][4] = uni(-g.cy * n[2]);
-      P[r][5] = uni(-g.cz * n[2]);
-      amb |= amb_r;
-#pragma unroll
-      for (int k = 0; k < 3; ++k)
-        if (!(amb_r & (1u << k)) && n[k] != 0.0) nz |= 1u << k;
+      amb |= (m_amb >> (3 * r)) & 7u;
+      nz |= ((m_pos | m_neg) >> (3 * r)) & 7u;
     }
-    amb = static_cast<uint32_t>(uni(static_cast<int>(amb)));
-    nz = static_cast<uint32_t>(uni(static_cast<int>(nz))) & ~amb;
+    nz &= ~amb;
+    // exact term -B n of slice r along axis k for cell entry b, in the order
+    // of the canonical steps (zero where the slice's shift is 0 or the axis
+    // takes the rounding); selected from the ballots, so each loop below
+    // keeps only the terms it adds
+    auto P = [&](int r, int k, double b) {
+      const uint32_t bit = 1u << (3 * r + k);
+      return (m_pos & bit) ? -b : ((m_neg & bit) ? b : 0.0);
+    };
 
     // The reduced vector, q and short root t of the pairs of all slices with
     // one j, reduced as AMB says (the lanes whose t may lie near a bin edge
@@ -1191,17 +1185,17 @@ __device__ __forceinline__ void sorted_tile64(
         if constexpr (AMB & 2u) nb = rint(fma(dz, g.h23, dy * g.h22));
         if constexpr (AMB & 4u) nc = rint(dz * g.h33);
         if constexpr (AMB & 4u) dz = fma(-g.cz, nc, dz);
-        else if constexpr (NZ & 4u) dz = dz + P[r][5];
+        else if constexpr (NZ & 4u) dz = dz + P(r, 2, g.cz);
         if constexpr (AMB & 2u) dy = fma(-g.by, nb, dy);
-        else if constexpr (NZ & 2u) dy = dy + P[r][3];
+        else if constexpr (NZ & 2u) dy = dy + P(r, 1, g.by);
         if constexpr (AMB & 4u) dy = fma(-g.cy, nc, dy);
-        else if constexpr (NZ & 4u) dy = dy + P[r][4];
+        else if constexpr (NZ & 4u) dy = dy + P(r, 2, g.cy);
         if constexpr (AMB & 1u) dx = fma(-g.ax, na, dx);
-        else if constexpr (NZ & 1u) dx = dx + P[r][0];
+        else if constexpr (NZ & 1u) dx = dx + P(r, 0, g.ax);
         if constexpr (AMB & 2u) dx = fma(-g.bx, nb, dx);
-        else if constexpr (NZ & 2u) dx = dx + P[r][1];
+        else if constexpr (NZ & 2u) dx = dx + P(r, 1, g.bx);
         if constexpr (AMB & 4u) dx = fma(-g.cx, nc, dx);
-        else if constexpr (NZ & 4u) dx = dx + P[r][2];
+        else if constexpr (NZ & 4u) dx = dx + P(r, 2, g.cx);
         q[r] = fma(dz, dz, fma(dy, dy, dx * dx));
         t[r] = t_fast64(q[r], g.s, near);
       }
@@ -1353,9 +1347,12 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
   // valid lanes
   [[maybe_unused]] float cxi[R], cyi[R], czi[R];
   [[maybe_unused]] uint32_t ib_lo = 0, ib_hi = 0, ib_empty = 0;
-  // binary64 sorted frames: boxes of the fractional coordinates B^-1 x
-  // (slot 6: the largest |x| + |y| + |z| of the slice)
-  [[maybe_unused]] double ibox64[R][7];
+  // binary64 sorted frames: boxes of the fractional coordinates B^-1 x, one
+  // axis per lane (lane 3r + k: axis k of slice r), the largest
+  // |x| + |y| + |z| of slice r in lanes 3r to 3r + 2, and ib64_empty with
+  // bits 3r to 3r + 2 set for a slice without valid lanes
+  [[maybe_unused]] double ib64_lo = 0.0, ib64_hi = 0.0, ib64_mag = 0.0;
+  [[maybe_unused]] uint32_t ib64_empty = 0;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int i = wbase + r * 64 + lane;
@@ -1368,10 +1365,16 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
       frac64(p.x, p.y, p.z, g, sg);
 #pragma unroll
       for (int ax = 0; ax < 3; ++ax) {
-        ibox64[r][ax] = wave_min_f64(ok ? sg[ax] : __builtin_inf());
-        ibox64[r][3 + ax] = wave_max_f64(ok ? sg[ax] : -__builtin_inf());
+        const double bl = wave_min_f64(ok ? sg[ax] : __builtin_inf());
+        const double bh = wave_max_f64(ok ? sg[ax] : -__builtin_inf());
+        if (lane == 3 * r + ax) {
+          ib64_lo = bl;
+          ib64_hi = bh;
+        }
+        if (ax == 0 && !(bl <= bh)) ib64_empty |= 7u << (3 * r);
       }
-      ibox64[r][6] = wave_max_f64(ok ? fabs(p.x) + fabs(p.y) + fabs(p.z) : 0.0);
+      const double mag = wave_max_f64(ok ? fabs(p.x) + fabs(p.y) + fabs(p.z) : 0.0);
+      if (lane >= 3 * r && lane < 3 * r + 3) ib64_mag = mag;
     }
     if constexpr (SORTED && sizeof(T) == 4) {
       // a lane past the end of the item: an i-point at infinity (every q of
@@ -1635,7 +1638,8 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
     if constexpr (SORTED && sizeof(T) == 8) {
       if (wave_active && js < jcount)
         sorted_tile64<R, DIAG>(tile + buf * tj, reinterpret_cast<const double *>(tboxes) + buf * 32,
-                               jt, js, jcount, wbase, lane, g, big_bins, xi, yi, zi, ibox64, lo,
+                               jt, js, jcount, wbase, lane, g, big_bins, xi, yi, zi, ib64_lo,
+                               ib64_hi, ib64_mag, ib64_empty, lo,
                                hi, count_t);
       continue;
     }
