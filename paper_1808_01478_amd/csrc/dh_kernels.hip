@@ -135,15 +135,17 @@ __device__ __forceinline__ double sqrt_cr(double q) {
 // The scaled distance t = sqrt(q) * s from a short root: v_rsq_f64 (relative
 // error at most 2^-23, the precision the ISA states for it) and one
 // Goldschmidt step, with s folded into the step's last fma (g s (1 + e)
-// instead of (g (1 + e)) s: one multiplication less), give t within about
+// instead of (g (1 + e)) s: one dependent step less), give t within about
 // 1.5 * 2^-46 relative plus three roundings, so it lies within 2^13 ulps of
 // the canonical t (correctly rounded root times s).
 // It decides the bin whenever it is farther than 2^16 ulps from every
-// integer. The lanes where that is not certain are added to the wave mask
-// `near`: t within 2^16 ulps of an integer. For t < 2^20 the integers are
-// multiples of 2^32 ulps of t, so t is that far from every integer when the
-// low 32 bits of its encoding are at least 2^16 away from a multiple of 2^32
-// (a conservative test: two integer operations). Every t at or above 2^20 is
+// integer. For t < 2^20 the integers are multiples of 2^32 ulps of t, so t
+// is that far from every integer when the low 32 bits of its encoding are
+// at least 2^16 away from a multiple of 2^32, i.e. when lo + 2^16 (mod 2^32)
+// is at least 2^17, lo being those bits (a conservative test). The caller
+// keeps the smallest lo + 2^16 of its pairs per lane in `gap` (a minimum the
+// compiler forms three at a time) and takes the correctly rounded root for
+// all of them when any lane's gap is below 2^17 (one ballot). Every t at or above 2^20 is
 // out of range, as is the canonical t, when n_bins < 2^20 - 2; with more
 // bins the callers take the correctly rounded root for every pair. The
 // bound holds for every normal q (all intermediates stay normal). q = 0
@@ -154,25 +156,34 @@ __device__ __forceinline__ double sqrt_cr(double q) {
 // rounded root for every pair beyond that), and the short root, within a
 // few ulps of it, falls in bin 0 as well. A NaN t (q = +inf or NaN) counts
 // out of range like the canonical one.
-__device__ __forceinline__ double t_fast64(double q, double s, uint64_t &near) {
+__device__ __forceinline__ double t_fast64(double q, double s, uint32_t &gap) {
   const double y = __builtin_amdgcn_rsq(q);
   const double g = q * y;
   const double h = 0.5 * y;
   const double e = fma(-h, g, 0.5);
   const double gs = g * s;
   const double t = fma(gs, e, gs);
-  const uint32_t lo = static_cast<uint32_t>(__double_as_longlong(t)) + 0x10000u;
-  near |= __builtin_amdgcn_ballot_w64(lo < 0x20000u);
+  gap = min(gap, static_cast<uint32_t>(__double_as_longlong(t)) + 0x10000u);
   return t;
+}
+
+// Initial gap of a group of pairs: 0 (the correctly rounded root for every
+// pair) when the histogram has 2^20 - 2 bins or more or s is huge (big_bins,
+// see run_item), else no pair yet.
+__device__ __forceinline__ uint32_t gap_init(bool big_bins) { return big_bins ? 0u : ~0u; }
+
+// Whether any lane of the wave has a pair whose short t may lie near an
+// integer (a uniform answer).
+__device__ __forceinline__ bool any_near(uint32_t gap) {
+  return __builtin_amdgcn_ballot_w64(gap < 0x20000u) != 0;
 }
 
 // t with the canonical arithmetic for one pair: the short root, or, when any
 // lane of the wave needs it, the correctly rounded one (a uniform branch).
-// big_bins: always the correctly rounded root (see run_item).
 __device__ __forceinline__ double t_guarded64(double q, double s, bool big_bins) {
-  uint64_t near = big_bins ? ~0ull : 0ull;
-  const double t = t_fast64(q, s, near);
-  if (__builtin_expect(near != 0, 0)) return sqrt_cr(q) * s;
+  uint32_t gap = gap_init(big_bins);
+  const double t = t_fast64(q, s, gap);
+  if (__builtin_expect(any_near(gap), 0)) return sqrt_cr(q) * s;
   return t;
 }
 
@@ -1167,12 +1178,12 @@ __device__ __forceinline__ void sorted_tile64(
     };
 
     // The reduced vector, q and short root t of the pairs of all slices with
-    // one j, reduced as AMB says (the lanes whose t may lie near a bin edge
-    // join the wave mask `near`, see t_fast64).
+    // one j, reduced as AMB says (each lane keeps in `gap` how close its t
+    // come to an integer, see t_fast64).
     // AMB: the axes that take the rounding; NZ: the axes whose shared shift
     // is non-zero for some slice (the others add nothing: their terms are 0).
     auto reduce = [&](auto amb_c, auto nz_c, const double4 &pj, double *q, double *t,
-                      uint64_t &near) {
+                      uint32_t &gap) {
       constexpr uint32_t AMB = decltype(amb_c)::value;
       constexpr uint32_t NZ = decltype(nz_c)::value;
       static_assert((AMB & NZ) == 0, "an axis is either rounded or shared");
@@ -1197,14 +1208,14 @@ __device__ __forceinline__ void sorted_tile64(
         if constexpr (AMB & 4u) dx = fma(-g.cx, nc, dx);
         else if constexpr (NZ & 4u) dx = dx + P(r, 2, g.cx);
         q[r] = fma(dz, dz, fma(dy, dy, dx * dx));
-        t[r] = t_fast64(q[r], g.s, near);
+        t[r] = t_fast64(q[r], g.s, gap);
       }
     };
     // The counts of NJ consecutive j from j0: the correctly rounded root for
     // all of them when any lane needs it, then one atomic per pair.
-    auto finish = [&](auto nj_c, const double *q, double *t, uint64_t near, int j0) {
+    auto finish = [&](auto nj_c, const double *q, double *t, uint32_t gap, int j0) {
       constexpr int NJ = decltype(nj_c)::value;
-      if (__builtin_expect(near != 0, 0))
+      if (__builtin_expect(any_near(gap), 0))
 #pragma unroll
         for (int k = 0; k < NJ * R; ++k) t[k] = sqrt_cr(q[k]) * g.s;
 #pragma unroll
@@ -1229,18 +1240,18 @@ __device__ __forceinline__ void sorted_tile64(
       int j = j_begin;
       for (; j + 1 < j_end; j += 2, cp += 2) {
         double q[2 * R], t[2 * R];
-        uint64_t near = big_bins ? ~0ull : 0ull;
-        reduce(amb_c, nz_c, pa, q, t, near);
-        reduce(amb_c, nz_c, pb, q + R, t + R, near);
+        uint32_t gap = gap_init(big_bins);
+        reduce(amb_c, nz_c, pa, q, t, gap);
+        reduce(amb_c, nz_c, pb, q + R, t + R, gap);
         pa = cp[2];
         pb = cp[3];
-        finish(Two{}, q, t, near, j);
+        finish(Two{}, q, t, gap, j);
       }
       if (j < j_end) {
         double q[R], t[R];
-        uint64_t near = big_bins ? ~0ull : 0ull;
-        reduce(amb_c, nz_c, pa, q, t, near);
-        finish(One{}, q, t, near, j);
+        uint32_t gap = gap_init(big_bins);
+        reduce(amb_c, nz_c, pa, q, t, gap);
+        finish(One{}, q, t, gap, j);
       }
     };
     using M0 = std::integral_constant<uint32_t, 0>;
@@ -1485,7 +1496,8 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
           // floor(t), saturated; t >= 0 always
           idx = static_cast<uint32_t>(min_arith(t, 4294967295.0));
           if constexpr (SWEEP) idx -= static_cast<uint32_t>(b_lo);
-          idx = max(min(idx, hi), l);
+          // the slot clamped to [l, hi] (l is 0 or hi): one v_med3_u32
+          idx = med3_u32(idx, l, hi);
         }
         // byte offset with one shift (copies interleaved bin-major), so the
         // address is a single v_lshl_add_u32
@@ -1667,13 +1679,13 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
           // correctly rounded root for all of them when any lane of the wave
           // has a t near an integer (see t_fast64)
           double q[R], t[R];
-          uint64_t near = big_bins ? ~0ull : 0ull;
+          uint32_t gap = gap_init(big_bins);
 #pragma unroll
           for (int r = 0; r < R; ++r) {
             q[r] = q64<BOX>(xi[r], yi[r], zi[r], pj.x, pj.y, pj.z, g);
-            t[r] = t_fast64(q[r], g.s, near);
+            t[r] = t_fast64(q[r], g.s, gap);
           }
-          if (__builtin_expect(near != 0, 0))
+          if (__builtin_expect(any_near(gap), 0))
 #pragma unroll
             for (int r = 0; r < R; ++r) t[r] = sqrt_cr(q[r]) * g.s;
 #pragma unroll
