@@ -74,9 +74,11 @@ constexpr int kSearchTable = 8 * kOctCap + kShifts;
 // slack e of the octant boxes in fractional coordinates (see octant_images)
 constexpr double kOctSlack = 0x1p-30;
 constexpr int kDump = 64;  // per-lane discard slots after the bin window
-// Per-wave LDS ring of reduced vectors waiting for the 27-image search:
-// one j adds at most 64 per i-particle of a lane (R) on top of fewer than 64.
-constexpr int queue_cap(int r) { return 64 * (r + 1); }
+// Per-wave LDS ring of reduced vectors waiting for the 27-image search: the
+// wave searches 64 of them as soon as 64 are queued, after each slice of
+// pairs, so a slice adds at most 64 on top of fewer than 64 (the same for
+// every number of slices r).
+constexpr int queue_cap(int /* slices per lane */) { return 128; }
 
 // Constants of one frame, computed once on the host.
 //

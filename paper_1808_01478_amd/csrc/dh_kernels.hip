@@ -1740,6 +1740,7 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
                 wq[pos] = e;
               }
               qn += __builtin_popcountll(m);
+              if (qn >= 64) drain(64);
             }
           } else if constexpr (kPacked) {
             // c differences of i-particles r and r+1 from one 64-bit add
@@ -1753,8 +1754,6 @@ __device__ __forceinline__ void run_item(const PairKernelArgs &a, const WorkItem
             count_t(pair_t<T, BOX>(xi[r], yi[r], zi[r], pj.x, pj.y, pj.z, g), l, lb);
           }
         }
-        if constexpr (SEARCH)
-          while (qn >= 64) drain(64);
       };
       // Ping-pong over two j registers: the read of the next j is issued
       // before the current j's atomics. LDS operations complete in order, so
