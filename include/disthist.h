@@ -142,12 +142,20 @@ int dh_histo(const double *coords, const int64_t *offsets, int32_t n_species,
  * Creates a context on HIP device `device` (the per-device state of the
  * paper's GPU kernel: the device buffers it keeps between calls and reuses
  * for every frame, Sec. 3.2). The context owns device scratch (staged
- * coordinates, work lists, counters) that grows on demand and is reused; it
- * never frees caller memory. *ctx receives the handle (NULL on failure);
- * DH_EINVAL for a device index out of range, DH_ENOMEM or DH_EDEVICE if the
+ * coordinates, sort keys, work lists, counters) that grows on demand and is
+ * reused; it never frees caller memory.
+ *   hbm_budget_bytes  the most device memory the context may hold: its
+ *                     scratch plus the buffers of its live batches; 0 for no
+ *                     limit. A call or dh_batch_create that would need more
+ *                     fails with DH_EBUDGET and the context stays usable;
+ *                     no output has been written, unless the call was
+ *                     tuning its launch shape (DH_TUNE_ON), whose trial
+ *                     runs write the output. Caller buffers do not count.
+ * *ctx receives the handle (NULL on failure); DH_EINVAL for a negative
+ * budget or a device index out of range, DH_ENOMEM or DH_EDEVICE if the
  * device cannot be set up.
  */
-int dh_ctx_create(int32_t device, dh_ctx **ctx);
+int dh_ctx_create(int32_t device, int64_t hbm_budget_bytes, dh_ctx **ctx);
 
 /* Releases a context and its scratch (synchronises its device first). */
 void dh_ctx_destroy(dh_ctx *ctx);

@@ -41,6 +41,10 @@ struct dh_ctx {
   size_t in_cap = 0;
   uint64_t *d_out = nullptr;
   size_t out_cap = 0;
+  // device memory budget of the context's scratch and its live batches
+  // (0: none), and the device bytes those batches hold
+  size_t budget = 0;
+  size_t batch_bytes = 0;
   std::string last_error;
   std::mutex mu;
   std::string arch;
@@ -98,6 +102,7 @@ struct dh_batch {
   bool any_oor = false;
   void *d_staged = nullptr;
   void *d_blob = nullptr;
+  size_t budget_bytes = 0;  // device bytes counted against the context's budget
   size_t off_frames = 0, off_items = 0, off_counters = 0;
   std::vector<Group> groups;
   // spatially sorted frames (staged by their own sort, not the batched
@@ -605,6 +610,16 @@ void refine_tail(std::vector<WorkItem> &items, int grid, int tj) {
 int ensure_device(dh_ctx *ctx, void **ptr, size_t *cap, size_t need) {
   if (need <= *cap) return DH_OK;
   size_t want = std::max(need, *cap + *cap / 2);
+  if (ctx->budget) {
+    // checked before the old buffer goes, so a refused call leaves the
+    // context as it was; the growth slack is cut to what the budget leaves
+    const size_t others = ctx_device_bytes(ctx) - *cap + ctx->batch_bytes;
+    if (others > ctx->budget || need > ctx->budget - others)
+      return fail(ctx, DH_EBUDGET,
+                  "%zu bytes of device scratch needed beside the %zu held; budget %zu bytes",
+                  need, others, ctx->budget);
+    want = std::min(want, ctx->budget - others);
+  }
   if (*ptr) {
     DH_HIP(ctx, hipDeviceSynchronize());
     DH_HIP(ctx, hipFree(*ptr));
@@ -1238,11 +1253,13 @@ int dh_search_images(const double *box, int32_t *lists, int32_t *counts, int32_t
   return DH_OK;
 }
 
-int dh_ctx_create(int32_t device, dh_ctx **out) {
+int dh_ctx_create(int32_t device, int64_t hbm_budget_bytes, dh_ctx **out) {
   if (!out) return DH_EINVAL;
   *out = nullptr;
+  if (hbm_budget_bytes < 0) return DH_EINVAL;
   dh_ctx *ctx = new (std::nothrow) dh_ctx;
   if (!ctx) return DH_ENOMEM;
+  ctx->budget = static_cast<size_t>(hbm_budget_bytes);
   int rc = ctx_init(ctx, device);
   if (rc) {
     dh_ctx_destroy(ctx);
@@ -1406,7 +1423,7 @@ int dh_histo(const double *coords, const int64_t *offsets, int32_t n_species, in
     std::lock_guard<std::mutex> g(g_default_mu);
     auto it = g_default.find(dev);
     if (it == g_default.end()) {
-      rc = dh_ctx_create(dev, &ctx);
+      rc = dh_ctx_create(dev, 0, &ctx);
       if (rc) return rc;
       g_default[dev] = ctx;
     } else {
@@ -1603,17 +1620,32 @@ int dh_batch_create(dh_ctx *ctx, const dh_frame_desc *frames, int32_t n_frames, 
     b->max_hist = std::max(b->max_hist, info[f].fp.n_hist);
     b->any_oor = b->any_oor || frames[f].d_out_of_range != nullptr;
   }
-  if (hipMalloc(&b->d_staged, staged_bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    b->d_staged = nullptr;
-    return bail(fail(ctx, DH_ENOMEM, "hipMalloc of %zu bytes failed", staged_bytes));
-  }
   // blob: frames | items | pairs | counters
   b->off_frames = 0;
   b->off_items = align_up(n_frames * sizeof(FrameParams), 256);
   const size_t off_pairs = align_up(b->off_items + items.size() * sizeof(WorkItem), 256);
   b->off_counters = align_up(off_pairs + pairs.size() * sizeof(uint64_t), 256);
   const size_t blob_bytes = b->off_counters + align_up(b->groups.size() * sizeof(int32_t), 256);
+  int64_t max_sorted = 0;
+  for (int32_t f = 0; f < n_frames; ++f)
+    if (info[f].fp.box == kBoxTricSorted) max_sorted = std::max(max_sorted, info[f].fp.n_points);
+  const size_t keys_bytes =
+      max_sorted > 0 ? static_cast<size_t>(sort_keys_count(max_sorted)) * 8 : 0;
+  // the batch's buffers count against the context's budget while it lives
+  const size_t own = staged_bytes + blob_bytes + keys_bytes;
+  if (ctx->budget) {
+    const size_t held = ctx_device_bytes(ctx) + ctx->batch_bytes;
+    if (held > ctx->budget || own > ctx->budget - held)
+      return bail(fail(ctx, DH_EBUDGET,
+                       "the batch needs %zu bytes of device memory beside the %zu held; "
+                       "budget %zu bytes",
+                       own, held, ctx->budget));
+  }
+  if (hipMalloc(&b->d_staged, staged_bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    b->d_staged = nullptr;
+    return bail(fail(ctx, DH_ENOMEM, "hipMalloc of %zu bytes failed", staged_bytes));
+  }
   if (hipMalloc(&b->d_blob, blob_bytes) != hipSuccess) {
     (void)hipGetLastError();
     b->d_blob = nullptr;
@@ -1621,25 +1653,22 @@ int dh_batch_create(dh_ctx *ctx, const dh_frame_desc *frames, int32_t n_frames, 
   }
   char *db = static_cast<char *>(b->d_blob);
   std::vector<char> host(blob_bytes, 0);
-  int64_t max_sorted = 0;
   for (int32_t f = 0; f < n_frames; ++f) {
     FrameParams fp = info[f].fp;
     fp.coords = static_cast<char *>(b->d_staged) + staged_off[f];
     fp.pairs = reinterpret_cast<const uint64_t *>(db + off_pairs) + pairs_base[f];
     std::memcpy(host.data() + b->off_frames + f * sizeof(FrameParams), &fp, sizeof fp);
-    if (fp.box == kBoxTricSorted) {
+    if (fp.box == kBoxTricSorted)
       b->sorted.push_back({f, frames[f].d_coords, const_cast<void *>(fp.coords),
                            info[f].offsets, fp});
-      max_sorted = std::max(max_sorted, fp.n_points);
-    }
   }
-  if (max_sorted > 0 &&
-      hipMalloc(&b->d_keys, static_cast<size_t>(sort_keys_count(max_sorted)) * 8) !=
-          hipSuccess) {
+  if (keys_bytes > 0 && hipMalloc(&b->d_keys, keys_bytes) != hipSuccess) {
     (void)hipGetLastError();
     b->d_keys = nullptr;
     return bail(fail(ctx, DH_ENOMEM, "hipMalloc of the sort keys failed"));
   }
+  b->budget_bytes = own;
+  ctx->batch_bytes += own;
   if (!items.empty())
     std::memcpy(host.data() + b->off_items, items.data(), items.size() * sizeof(WorkItem));
   if (!pairs.empty())
@@ -1702,6 +1731,7 @@ void dh_batch_destroy(dh_batch *b) {
     if (b->d_blob) (void)hipFree(b->d_blob);
     if (b->d_keys) (void)hipFree(b->d_keys);
   }
+  if (b->ctx) b->ctx->batch_bytes -= b->budget_bytes;
   (void)hipGetLastError();
   delete b;
 }

@@ -26,7 +26,7 @@ SIGNATURES = {
     "dh_strerror": ([ctypes.c_int], ctypes.c_char_p),
     "dh_check_args": ([_vp, _vp, _i32, _i32, _vp, _f64, _i32, _i32], ctypes.c_int),
     "dh_histo": ([_vp, _vp, _i32, _i32, _vp, _f64, _i32, _i32, _vp], ctypes.c_int),
-    "dh_ctx_create": ([_i32, ctypes.POINTER(_vp)], ctypes.c_int),
+    "dh_ctx_create": ([_i32, _i64, ctypes.POINTER(_vp)], ctypes.c_int),
     "dh_ctx_destroy": ([_vp], None),
     "dh_ctx_last_error": ([_vp], ctypes.c_char_p),
     "dh_histo_async": ([_vp, _vp, _vp, _vp, _i32, _i32, _vp, _f64, _i32, _i32, _vp, _vp],
@@ -219,11 +219,13 @@ def _stream_handle(stream) -> Optional[int]:
 
 
 class Context:
-    """A dh_ctx on one device (owns reusable device scratch)."""
+    """A dh_ctx on one device (owns reusable device scratch). hbm_budget_bytes
+    bounds the device memory of its scratch and live batches (0: no limit);
+    a call that needs more raises DisthistError with code DH_EBUDGET."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
         h = ctypes.c_void_p()
-        _check(LIB.dh_ctx_create(int(device), ctypes.byref(h)))
+        _check(LIB.dh_ctx_create(int(device), int(hbm_budget_bytes), ctypes.byref(h)))
         self.handle = h
         self.device = device
 

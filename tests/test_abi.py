@@ -94,6 +94,15 @@ def test_histo_rejects_before_touching_the_device(dh):
     assert rc == -1 and (out_untouched == 7).all()
 
 
+def test_ctx_create_rejects_negative_budget(dh):
+    # the budget is checked before the device is touched, so this runs on a
+    # machine without a GPU
+    from paper_1808_01478_amd import disthist
+    h = ctypes.c_void_p(1)
+    assert disthist.LIB.dh_ctx_create(0, -1, ctypes.byref(h)) == disthist.DH_EINVAL
+    assert not h.value
+
+
 def test_no_cpu_fallback_in_product_package():
     # the product package never imports the oracle
     pkg = os.path.join(ROOT, "paper_1808_01478_amd")
