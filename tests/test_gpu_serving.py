@@ -1,8 +1,9 @@
 """The serving loop on the GPU: every job's result in a concurrent mix is
 bit-identical to the same job run alone (same kernels, integer sums), also
 when the jobs' work items share pair-kernel launches (continuous batching),
-binary64 jobs equal the oracle, jobs of the serving workload's full sizes
-are exact, the budget bounds the admitted footprints, and bad jobs fail
+binary64 jobs equal the oracle, jobs drawn as the serving workload draws
+them equal the oracle (binary64) or lie within the binary32 edge bound, jobs
+of the serving workload's full sizes are exact, the budget bounds the admitted footprints, and bad jobs fail
 alone."""
 import math
 import time
@@ -59,6 +60,39 @@ def test_mix_equals_alone_and_oracle():
     for (f, p), (h, _, _) in list(zip(jobs, results))[:6]:
         if p == 1:
             assert np.array_equal(h, oracle.frame_histogram(f).hist), f.name
+
+
+def test_serving_workload_jobs_against_oracle():
+    """Jobs drawn exactly as the measured serving workload draws them (seed 5:
+    50 warm-up jobs, then the measured ones; N log-uniform in [1e3, 2e6], no
+    box, orthorhombic or triclinic, 1-3 species, 1k/10k/50k bins): the
+    measured jobs of at most 30,000 points among the first 120, each served in
+    binary32 (the workload's precision) and binary64, all at once. binary64
+    equals the oracle bit for bit; binary32 lies within the edge-pair bound of
+    the oracle, histograms and out-of-range counts."""
+    import paper_1808_01478_amd as dh
+    from gpu_util import fp32_bound_violations, oor_bound_violations
+    rng = np.random.Generator(np.random.PCG64(5))
+    drawn = [workloads.serving_job(rng, j, 0.0).frame for j in range(50 + 120)]
+    jobs = [f for f in drawn[50:] if f.n <= 30_000]
+    assert len(jobs) >= 40
+    print(f"\n[case] serving workload: {len(jobs)} measured jobs of at most 30,000 points, "
+          f"both precisions", flush=True)
+    with dh.Server(0, hbm_budget_bytes=8 << 30, max_inflight=8) as srv:
+        ids = [(srv.submit(f.coords, f.offsets, f.box_type, f.box, f.r_max, f.n_bins, 0),
+                srv.submit(f.coords, f.offsets, f.box_type, f.box, f.r_max, f.n_bins, 1))
+               for f in jobs]
+        res = [(srv.wait(a), srv.wait(b)) for a, b in ids]
+        st = srv.stats()
+    assert st["completed"] == 2 * len(jobs) and st["failed"] == 0
+    for f, ((h32, o32, _), (h64, o64, _)) in zip(jobs, res):
+        w = oracle.edge_window(f.coords, f.box, f.r_max)
+        ref = oracle.frame_histogram(f, edge_window=w)
+        assert np.array_equal(h64, ref.hist), f"{f.name}: binary64 differs from the oracle"
+        assert np.array_equal(o64, ref.out_of_range), f"{f.name}: binary64 out-of-range"
+        bad = fp32_bound_violations(h32, ref.hist, ref.edges)
+        bad += oor_bound_violations(o32, ref.out_of_range, ref.edges)
+        assert not bad, f"{f.name}: " + "; ".join(bad[:5])
 
 
 def test_budget_back_pressure():
