@@ -682,7 +682,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="triclinic1M",
                     choices=("triclinic1M", "ortho100k", "tiny"))
-    ap.add_argument("--fp64-steps", type=int, default=None)
+    ap.add_argument("--fp64-steps", type=int, default=None,
+                    help="timed binary64 steps (default: as many as --steps)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-jobs", type=int, default=1000,
                     help="measured jobs of the serving comparison (0 = skip)")
@@ -725,7 +726,7 @@ def main():
         if os.path.exists(DEFAULT_CACHE):
             os.environ.setdefault("DH_TUNE", str(dh.TUNE_CACHED))
             os.environ.setdefault("DH_TUNE_CACHE", DEFAULT_CACHE)
-    fp64_steps = args.fp64_steps if args.fp64_steps is not None else max(1, args.steps // 2)
+    fp64_steps = args.fp64_steps if args.fp64_steps is not None else max(1, args.steps)
     _, head, res = bench_frame(ctx, args.workload, args.steps, fp64_steps, max(1, args.warmup),
                                frame)
     r32, r64 = res["fp32"], res.get("fp64")
