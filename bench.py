@@ -783,6 +783,7 @@ def main():
     # PCIe-inclusive rate of the synchronous host-buffer entry point
     progress("host buffers")
     line["host_buffers"] = time_host_buffers(frame, dh.FP32, max(1, args.steps // 4))
+    line["host_buffers"]["fp64"] = time_host_buffers(frame, dh.FP64, max(1, args.steps // 4))
     if args.serving_jobs > 0:
         progress(f"serving, {args.serving_jobs} jobs")
         line["serving"] = bench_serving(args.serving_jobs)
